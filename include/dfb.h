@@ -1,0 +1,192 @@
+/*
+ * dfb.h -- C ABI of an MI355X (gfx950) per-tile sort-last compositor: the
+ * data-parallel tile operation of the Distributed FrameBuffer (Usher, Wald,
+ * Amstutz, Guenther, Brownlee, Pascucci: "Scalable Ray Tracing Using the
+ * Distributed FrameBuffer", EuroVis 2019).
+ *
+ * One handle owns one GPU's share of a framebuffer: every tile it composites
+ * is "owned" by it in the paper's sense (Sec. 3, Listing 1 TileDescriptor).
+ * Per frame the caller hands over every contributor's generation-1 tiles
+ * (Sec. 3.1.1; Listing 3: one tile per (tile, contributing brick)), and the
+ * library runs, on the GPU, the sort-and-blend tile operation (Sec. 4.2,
+ * Listing 4), the progressive-refinement accumulation with its variance
+ * (Listing 1: accumulationID, accumulation and variance tiles), the
+ * tone-mapping pixel operation (Sec. 3.1.2) and the display-format
+ * conversion (Sec. 3.1: RGBA8, RGBAF32 or NONE).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a dfb_status; no C++ exception crosses the ABI.
+ *  - Device pointers are HIP device addresses on the device that was current
+ *    when the handle was created.  Host pointers are plain process memory.
+ *  - Work is enqueued on the HIP stream given to dfb_create (which may be 0,
+ *    the null stream).  Results are visible to the host only after
+ *    dfb_synchronize or a synchronisation of that stream.
+ *  - A HIP error is sticky: once one is seen, every later call on the handle
+ *    returns DFB_ERR_HIP.
+ *  - One host thread at a time per handle.  dfb_last_error returns a string
+ *    owned by the handle, valid until its next call.
+ */
+#ifndef DFB_H
+#define DFB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dfb_ctx* dfb_handle;
+
+typedef enum {
+  DFB_OK = 0,
+  DFB_ERR_INVALID_ARG = -1,  /* null pointer, bad size, id out of range */
+  DFB_ERR_STATE = -2,        /* call out of order (e.g. composite before set_fragments) */
+  DFB_ERR_INCOMPLETE = -3,   /* a tile's layer count differs from its declared children */
+  DFB_ERR_DUPLICATE = -4,    /* two layers with the same (tile_id, source_id) */
+  DFB_ERR_BAD_VALUE = -5,    /* DFB_VALIDATE found a NaN depth */
+  DFB_ERR_OOM = -6,          /* a device or host allocation failed */
+  DFB_ERR_HIP = -7,          /* a HIP call failed (sticky) */
+  DFB_ERR_UNSUPPORTED = -8   /* e.g. more layers in one tile than the kernels handle */
+} dfb_status;
+
+typedef enum { DFB_F32 = 0, DFB_F16 = 1 } dfb_dtype;   /* storage of all five planes */
+
+/* Display formats of the final pixels (Sec. 3.1): NONE stores nothing. */
+typedef enum { DFB_FMT_RGBA8 = 0, DFB_FMT_RGBAF32 = 1, DFB_FMT_NONE = 2 } dfb_format;
+
+typedef enum {
+  DFB_BUF_FINAL = 0,          /* display pixels: RGBA8 as uint8[n][P][4], RGBAF32 as float[n][P][4] */
+  DFB_BUF_FINISHED_F32 = 1,   /* finished (composited) tile, float[n][P][4]; needs DFB_KEEP_FINISHED */
+  DFB_BUF_ACCUM_F32 = 2,      /* running mean, float[n][P][4] */
+  DFB_BUF_M2_F32 = 3,         /* Welford M2 of R,G,B, float[n][3][P] (planar per tile) */
+  DFB_BUF_TILE_VARIANCE = 4,  /* per-tile variance of the mean, float[n]; +inf while n < 2 */
+  DFB_BUF_SORT_ORDER = 5      /* debug, needs DFB_KEEP_SORT_ORDER: see below */
+} dfb_buffer;
+
+/* dfb_config.flags */
+#define DFB_VALIDATE 0x1u        /* scan depths on the device; NaN -> DFB_ERR_BAD_VALUE */
+#define DFB_KEEP_SORT_ORDER 0x2u /* debug: store each pixel's sorted layer order */
+#define DFB_KEEP_FINISHED 0x4u   /* store the finished FP32 tile every frame */
+
+/* dfb_composite_frame frame_flags */
+#define DFB_ACCUMULATE 0x1u      /* fold this frame into the running mean (fused) */
+
+typedef struct {
+  int32_t width, height;   /* framebuffer, pixels */
+  int32_t tile_w, tile_h;  /* DFB tile: the unit contributors hand over (Listing 1 TILE_SIZE).
+                              Tile grid is ceil(W/tw) x ceil(H/th), row-major ids; edge tiles
+                              are stored whole, pixels past the image edge are composited but
+                              excluded from the variance. */
+  int32_t work_w, work_h;  /* GPU scheduling unit inside a tile; must divide tile_w / tile_h.
+                              0,0 = autotune over {32,64,128}^2 (those that divide the tile). */
+  int32_t waves_per_tile;  /* 64-lane waves per work unit: 1, 2 or 4; 0 = autotune */
+  int32_t frag_dtype;      /* dfb_dtype */
+  int32_t format;          /* dfb_format */
+  float background[4];     /* premultiplied RGBA of the generation-0 background tile (Sec. 4.2) */
+  float tonemap_gamma;     /* 1 = clamp only; else colour channels raised to 1/gamma */
+  uint32_t flags;          /* DFB_VALIDATE | DFB_KEEP_SORT_ORDER | DFB_KEEP_FINISHED */
+} dfb_config;
+
+/* One generation-1 tile from one contributor (Listing 1 Tile; Listing 3).
+ * Its pixels are block `block` of the fragment buffer: plane c in
+ * {0:R, 1:G, 2:B, 3:A, 4:depth} of pixel p (row-major inside the tile) is
+ * element frag[(block*5 + c)*P + p], P = tile_w*tile_h, colour premultiplied.
+ * source_id names the contributor (a rank, or a rank's brick: Sec. 4.2 allows
+ * several bricks per rank); it breaks depth ties, nearer-first by smaller id. */
+typedef struct {
+  int32_t tile_id;
+  uint32_t source_id;
+  int64_t block;
+} dfb_layer;
+
+typedef struct {
+  int32_t n_tiles, tiles_x, tiles_y;
+  int32_t n_layers, max_layers_per_tile;
+  int32_t work_w, work_h, waves_per_tile;  /* the launch shape in use (after autotune) */
+  int32_t accumulation_id;                 /* frames folded in since the last reset */
+  int32_t grid_size;                       /* persistent workgroups per frame */
+  int64_t n_fragments;                     /* sum over tiles of layers * P */
+} dfb_info;
+
+/* Create a compositor.  Validates cfg, allocates the device buffers for the
+ * finished / accumulation / variance / display tiles on the current device.
+ * hip_stream: a hipStream_t (may be 0).  On success *out is a new handle. */
+dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out);
+
+/* Free every device buffer and the handle; waits for pending work. */
+dfb_status dfb_destroy(dfb_handle h);
+
+/* Hand over one frame's generation-1 tiles (Sec. 3.1 setTile; Sec. 3.1.1).
+ *   frag_dev   device buffer of n_blocks blocks in cfg.frag_dtype (layout above).
+ *              Borrowed, not copied: it must stay unchanged until the frame's
+ *              composite has completed on the stream.
+ *   layers     host array, any order (arrival order is not fixed, Sec. 3.1.1);
+ *              copied during the call.
+ *   expected   host int32[n_tiles] or NULL: the children count each tile's
+ *              background tile declares (Sec. 4.2).  When given, every tile must
+ *              have exactly that many layers, else DFB_ERR_INCOMPLETE.
+ * Errors: bad tile id or block -> DFB_ERR_INVALID_ARG, repeated
+ * (tile_id, source_id) -> DFB_ERR_DUPLICATE, more than 4096 layers in one
+ * tile -> DFB_ERR_UNSUPPORTED.  A tile with no layers is the background. */
+dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_blocks,
+                             const dfb_layer* layers, int32_t n_layers, const int32_t* expected);
+
+/* Composite every tile of the frame in one persistent launch (a one-node HIP
+ * graph, replayed each frame) that takes tiles from a device work queue in
+ * longest-first order: per pixel, sort the layers by (depth with NaN last and
+ * -0 == +0, source_id), blend front to back with premultiplied "over", put
+ * the background colour behind (Sec. 4.2, Listing 4).  With DFB_ACCUMULATE
+ * the same launch folds the frame into the running mean (Welford), reduces
+ * the per-tile variance of the mean and writes the display pixels of the
+ * mean; without it the display pixels are those of this frame.
+ * Tonemap: y = clamp(x,0,1) (NaN -> 0), colour ^ (1/gamma), code
+ * floor(255 y + 0.5).  If work_w/waves_per_tile are 0, the first frame of a
+ * new layer layout first autotunes them (synchronously). */
+dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags);
+
+/* Unfused accumulation of the last finished frame (needs DFB_KEEP_FINISHED):
+ * the same Welford update, variance and display conversion as
+ * DFB_ACCUMULATE, as a separate pass. */
+dfb_status dfb_accumulate(dfb_handle h);
+
+/* Start progressive refinement over: the next accumulated frame is n = 1. */
+dfb_status dfb_reset_accumulation(dfb_handle h);
+
+/* Copy tiles [first_tile, first_tile + n_tiles) of one buffer to dst (host, or
+ * device if dst_is_device), stream-ordered.  DFB_BUF_SORT_ORDER holds, for
+ * each tile in id order, uint16[K_t][P]: entry (i, p) is the index, among the
+ * tile's layers ordered by ascending source_id, of the i-th nearest fragment
+ * of pixel p; it is only kept for the last composited frame. */
+dfb_status dfb_read_tiles(dfb_handle h, dfb_buffer which, int32_t first_tile, int32_t n_tiles,
+                          void* dst, int dst_is_device);
+
+/* Bytes dfb_read_tiles would copy for that range (0 if not available). */
+int64_t dfb_buffer_bytes(dfb_handle h, dfb_buffer which, int32_t first_tile, int32_t n_tiles);
+
+/* Wait for everything enqueued on the handle's stream. */
+dfb_status dfb_synchronize(dfb_handle h);
+
+/* Shape of the current frame and launch. */
+dfb_status dfb_get_info(dfb_handle h, dfb_info* out);
+
+/* Average device time (ms) of the last n composite launches, measured with
+ * HIP events on the handle's stream; -1 if none were timed.  Timing is on
+ * while enable != 0 (dfb_set_timing). */
+dfb_status dfb_set_timing(dfb_handle h, int enable);
+double dfb_kernel_ms(dfb_handle h);
+
+/* Host-only check of one frame's layer list against a config, without a GPU:
+ * the same validation dfb_set_fragments does.  counts: nullable int32[n_tiles]
+ * that receives each tile's layer count. */
+dfb_status dfb_validate_layers(const dfb_config* cfg, int64_t n_blocks, const dfb_layer* layers,
+                               int32_t n_layers, const int32_t* expected, int32_t* counts);
+
+/* Human-readable last error of the handle (or of the last failed create when
+ * h is NULL). */
+const char* dfb_last_error(dfb_handle h);
+const char* dfb_status_string(dfb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFB_H */

@@ -1,0 +1,269 @@
+"""Python binding of the MI355X per-tile sort-last compositor (``include/dfb.h``).
+
+Argument marshalling only: every step of the compositing path runs in the
+HIP library ``libdfb.so`` built from ``csrc/``.  There is no fallback: if the
+library is missing, :func:`load` raises.  PyTorch, when used, only provides
+device memory and streams (load this module after ``import torch`` so both
+share one HIP runtime).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from ._build import LIB_PATH, build  # noqa: F401
+
+# ---------------------------------------------------------------- constants
+DFB_OK = 0
+DFB_ERR_INVALID_ARG = -1
+DFB_ERR_STATE = -2
+DFB_ERR_INCOMPLETE = -3
+DFB_ERR_DUPLICATE = -4
+DFB_ERR_BAD_VALUE = -5
+DFB_ERR_OOM = -6
+DFB_ERR_HIP = -7
+DFB_ERR_UNSUPPORTED = -8
+
+DFB_F32, DFB_F16 = 0, 1
+DFB_FMT_RGBA8, DFB_FMT_RGBAF32, DFB_FMT_NONE = 0, 1, 2
+(DFB_BUF_FINAL, DFB_BUF_FINISHED_F32, DFB_BUF_ACCUM_F32, DFB_BUF_M2_F32,
+ DFB_BUF_TILE_VARIANCE, DFB_BUF_SORT_ORDER) = range(6)
+DFB_VALIDATE, DFB_KEEP_SORT_ORDER, DFB_KEEP_FINISHED = 0x1, 0x2, 0x4
+DFB_ACCUMULATE = 0x1
+
+# every symbol include/dfb.h declares
+EXPORTED = (
+    "dfb_create", "dfb_destroy", "dfb_set_fragments", "dfb_composite_frame", "dfb_accumulate",
+    "dfb_reset_accumulation", "dfb_read_tiles", "dfb_buffer_bytes", "dfb_synchronize",
+    "dfb_get_info", "dfb_set_timing", "dfb_kernel_ms", "dfb_validate_layers", "dfb_last_error",
+    "dfb_status_string",
+)
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("work_w", ctypes.c_int32), ("work_h", ctypes.c_int32),
+                ("waves_per_tile", ctypes.c_int32), ("frag_dtype", ctypes.c_int32),
+                ("format", ctypes.c_int32), ("background", ctypes.c_float * 4),
+                ("tonemap_gamma", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class Layer(ctypes.Structure):
+    _fields_ = [("tile_id", ctypes.c_int32), ("source_id", ctypes.c_uint32), ("block", ctypes.c_int64)]
+
+
+LAYER_DTYPE = np.dtype([("tile_id", "<i4"), ("source_id", "<u4"), ("block", "<i8")])
+assert LAYER_DTYPE.itemsize == ctypes.sizeof(Layer)
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("tiles_x", ctypes.c_int32), ("tiles_y", ctypes.c_int32),
+                ("n_layers", ctypes.c_int32), ("max_layers_per_tile", ctypes.c_int32),
+                ("work_w", ctypes.c_int32), ("work_h", ctypes.c_int32),
+                ("waves_per_tile", ctypes.c_int32), ("accumulation_id", ctypes.c_int32),
+                ("grid_size", ctypes.c_int32), ("n_fragments", ctypes.c_int64)]
+
+
+class DfbError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("dfb status %d: %s" % (status, message))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load ``libdfb.so`` (built by ``build()``).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdfb.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "dfb_create": ([ctypes.POINTER(Config), P, ctypes.POINTER(P)], I32),
+        "dfb_destroy": ([P], I32),
+        "dfb_set_fragments": ([P, P, I64, P, I32, P], I32),
+        "dfb_composite_frame": ([P, U32], I32),
+        "dfb_accumulate": ([P], I32),
+        "dfb_reset_accumulation": ([P], I32),
+        "dfb_read_tiles": ([P, I32, I32, I32, P, ctypes.c_int], I32),
+        "dfb_buffer_bytes": ([P, I32, I32, I32], I64),
+        "dfb_synchronize": ([P], I32),
+        "dfb_get_info": ([P, ctypes.POINTER(Info)], I32),
+        "dfb_set_timing": ([P, ctypes.c_int], I32),
+        "dfb_kernel_ms": ([P], ctypes.c_double),
+        "dfb_validate_layers": ([ctypes.POINTER(Config), I64, P, I32, P, P], I32),
+        "dfb_last_error": ([P], ctypes.c_char_p),
+        "dfb_status_string": ([I32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status, handle=None):
+    if status != DFB_OK:
+        lib = load()
+        msg = lib.dfb_last_error(handle).decode(errors="replace")
+        raise DfbError(status, msg or lib.dfb_status_string(status).decode())
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(ctypes.c_void_p)
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return ctypes.c_void_p(int(a))
+
+
+def make_config(width, height, tile_w=64, tile_h=None, *, work=0, waves=0, dtype=DFB_F32,
+                fmt=DFB_FMT_RGBA8, background=(0.0, 0.0, 0.0, 0.0), gamma=1.0, flags=0):
+    tile_h = tile_w if tile_h is None else tile_h
+    ww, wh = (work, work) if isinstance(work, int) else work
+    return Config(width, height, tile_w, tile_h, ww, wh, waves, dtype, fmt,
+                  (ctypes.c_float * 4)(*background), gamma, flags)
+
+
+def as_layers(layers):
+    """numpy record array with fields tile_id, source_id, block -> C layout."""
+    out = np.empty(len(layers), dtype=LAYER_DTYPE)
+    for f in LAYER_DTYPE.names:
+        out[f] = np.asarray(layers[f])
+    return out
+
+
+# ---------------------------------------------------------- the C calls
+def dfb_create(cfg: Config, stream=0):
+    lib = load()
+    h = ctypes.c_void_p()
+    _check(lib.dfb_create(ctypes.byref(cfg), ctypes.c_void_p(int(stream)), ctypes.byref(h)))
+    return h
+
+
+def dfb_destroy(h):
+    _check(load().dfb_destroy(h))
+
+
+def dfb_set_fragments(h, frag_dev, n_blocks, layers, expected=None):
+    lay = as_layers(layers)
+    exp = None if expected is None else np.ascontiguousarray(expected, dtype=np.int32)
+    _check(load().dfb_set_fragments(h, _ptr(frag_dev), int(n_blocks), _ptr(lay), len(lay), _ptr(exp)), h)
+
+
+def dfb_composite_frame(h, frame_flags=0):
+    _check(load().dfb_composite_frame(h, frame_flags), h)
+
+
+def dfb_accumulate(h):
+    _check(load().dfb_accumulate(h), h)
+
+
+def dfb_reset_accumulation(h):
+    _check(load().dfb_reset_accumulation(h), h)
+
+
+def dfb_buffer_bytes(h, which, first_tile, n_tiles):
+    return int(load().dfb_buffer_bytes(h, which, first_tile, n_tiles))
+
+
+def dfb_read_tiles(h, which, first_tile, n_tiles, dst, dst_is_device=False):
+    _check(load().dfb_read_tiles(h, which, first_tile, n_tiles, _ptr(dst), int(bool(dst_is_device))), h)
+
+
+def dfb_synchronize(h):
+    _check(load().dfb_synchronize(h), h)
+
+
+def dfb_get_info(h) -> Info:
+    info = Info()
+    _check(load().dfb_get_info(h, ctypes.byref(info)), h)
+    return info
+
+
+def dfb_set_timing(h, enable=True):
+    _check(load().dfb_set_timing(h, int(bool(enable))), h)
+
+
+def dfb_kernel_ms(h) -> float:
+    return float(load().dfb_kernel_ms(h))
+
+
+def dfb_validate_layers(cfg: Config, n_blocks, layers, expected=None):
+    """Host-only validation; returns per-tile counts or raises DfbError."""
+    lib = load()
+    lay = as_layers(layers)
+    n_tiles = (-(-cfg.width // cfg.tile_w)) * (-(-cfg.height // cfg.tile_h))
+    counts = np.zeros(n_tiles, dtype=np.int32)
+    exp = None if expected is None else np.ascontiguousarray(expected, dtype=np.int32)
+    _check(lib.dfb_validate_layers(ctypes.byref(cfg), int(n_blocks), _ptr(lay), len(lay), _ptr(exp), _ptr(counts)))
+    return counts
+
+
+# ---------------------------------------------------------- convenience
+class Compositor:
+    """Owns a handle; reads results back into numpy arrays."""
+
+    def __init__(self, cfg: Config, stream=0):
+        self.cfg = cfg
+        self.h = dfb_create(cfg, stream)
+        self.P = cfg.tile_w * cfg.tile_h
+        self.n_tiles = (-(-cfg.width // cfg.tile_w)) * (-(-cfg.height // cfg.tile_h))
+
+    def close(self):
+        if self.h:
+            dfb_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_fragments(self, frag_dev, n_blocks, layers, expected=None):
+        dfb_set_fragments(self.h, frag_dev, n_blocks, layers, expected)
+
+    def composite(self, accumulate=False):
+        dfb_composite_frame(self.h, DFB_ACCUMULATE if accumulate else 0)
+
+    def accumulate(self):
+        dfb_accumulate(self.h)
+
+    def reset(self):
+        dfb_reset_accumulation(self.h)
+
+    def info(self):
+        return dfb_get_info(self.h)
+
+    def read(self, which, first_tile=0, n_tiles=None):
+        n_tiles = self.n_tiles - first_tile if n_tiles is None else n_tiles
+        nbytes = dfb_buffer_bytes(self.h, which, first_tile, n_tiles)
+        buf = np.empty(nbytes, dtype=np.uint8)
+        if nbytes:
+            dfb_read_tiles(self.h, which, first_tile, n_tiles, buf)
+        dfb_synchronize(self.h)
+        P = self.P
+        if which == DFB_BUF_FINAL:
+            if self.cfg.format == DFB_FMT_RGBA8:
+                return buf.reshape(n_tiles, P, 4)
+            return buf.view(np.float32).reshape(n_tiles, P, 4)
+        if which in (DFB_BUF_FINISHED_F32, DFB_BUF_ACCUM_F32):
+            return buf.view(np.float32).reshape(n_tiles, P, 4)
+        if which == DFB_BUF_M2_F32:
+            return buf.view(np.float32).reshape(n_tiles, 3, P)
+        if which == DFB_BUF_TILE_VARIANCE:
+            return buf.view(np.float32)
+        if which == DFB_BUF_SORT_ORDER:
+            return buf.view(np.uint16)
+        raise ValueError(which)

@@ -1,0 +1,85 @@
+// Internal interface between the host runtime (dfb_runtime.hip) and the
+// gfx950 kernels (dfb_kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfb {
+
+// Layers per tile handled by the register sort; above it, the workgroup-wide
+// LDS sort takes over.
+constexpr int kRegMax = 32;
+// Largest layer count per tile the LDS sort supports (keys + weights of one
+// pixel must fit the LDS budget below).
+constexpr int kMaxLayers = 4096;
+// LDS bytes the large-K path uses for keys (u64) and weights (f32).
+constexpr int kBigLdsBytes = 64 * 1024;
+
+enum ModeBits : uint32_t {
+  kModeAccumulate = 1u,     // fold into the running mean + per-tile variance
+  kModeKeepFinished = 2u,   // store the finished f32 tile
+  kModeKeepOrder = 4u,      // store the per-pixel sorted order (debug)
+  kModeFmtRGBA8 = 8u,       // display: RGBA8
+  kModeFmtF32 = 16u,        // display: RGBA f32
+  kModeGamma = 32u,         // colour ^ (1/gamma) before quantising
+};
+
+// Everything one frame launch needs; passed by value (a graph node's
+// parameters are updated per frame).
+struct FrameArgs {
+  const void* frag;            // fragment blocks (caller's buffer)
+  const int32_t* tile_off;     // [n_tiles + 1] CSR offsets into layer_block
+  const int64_t* layer_block;  // [n_layers] block of each layer; per tile ordered by source id
+  const int32_t* work_list;    // [n_work] work-unit ids, longest tile first
+  unsigned long long* queue;   // work-queue counter (monotonic across frames)
+  uint32_t* tile_done;         // [n_tiles] finished work units (monotonic across frames)
+  unsigned long long q_base;   // queue value at this frame's start
+  uint32_t done_base;          // tile_done value at this frame's start
+  int32_t n_work;
+  int32_t width, height, tiles_x, n_tiles;
+  int32_t tile_w, tile_h, P;
+  int32_t work_w, work_h, subs_x, subs_per_tile, work_px;
+  float bg[4];
+  float inv_gamma;
+  uint32_t mode;
+  int32_t n_acc;               // accumulation id after this frame (>= 1)
+  float inv_n;                 // 1 / n_acc
+  float* finished;             // [n_tiles][P][4]
+  float* accum;                // [n_tiles][P][4]
+  float* m2;                   // [n_tiles][3][P]
+  float* tile_var;             // [n_tiles]
+  float* var_partial;          // [n_work]
+  void* final_out;             // RGBA8 uint32[n_tiles][P] or float4[n_tiles][P]
+  uint16_t* order;             // [n_layers][P]
+};
+
+struct AccumArgs {
+  const float* finished;
+  float* accum;
+  float* m2;
+  float* tile_var;
+  void* final_out;
+  int32_t width, height, tiles_x, n_tiles, tile_w, tile_h, P;
+  float inv_gamma;
+  uint32_t mode;
+  int32_t n_acc;
+  float inv_n;
+};
+
+struct ValidateArgs {
+  const void* frag;
+  const int64_t* layer_block;
+  int32_t n_layers, P;
+  uint32_t* bad;   // set to 1 if a NaN depth is seen
+};
+
+// Kernel entry points for a given fragment type and register-sort cap.
+// dtype: 0 f32, 1 f16.  kcap: 8, 16 or 32 (layers handled in registers).
+const void* frame_kernel(int dtype, int kcap);
+const void* accumulate_kernel();
+const void* validate_kernel(int dtype);
+
+// Dynamic LDS bytes a frame launch needs.
+size_t frame_lds_bytes(int kcap, int threads, int max_layers);
+
+}  // namespace dfb

@@ -1,0 +1,483 @@
+// gfx950 kernels of the per-tile sort-last compositor.
+//
+// One persistent launch per frame.  Each workgroup (64 * waves_per_tile lanes)
+// repeatedly takes a work unit -- a work_w x work_h rectangle of one DFB tile
+// -- from a device queue ordered longest tile first, and for every pixel of it
+//   1. builds the key (ordered depth bits << 32 | layer index) of each of the
+//      tile's K layers from coalesced SoA depth loads, staging alpha in LDS,
+//   2. sorts the keys (registers for K <= 32, an LDS bitonic sort shared by
+//      the workgroup for larger K),
+//   3. walks the sorted keys front to back computing the transmittance T in
+//      front of each layer ("over", Sec. 4.2 of the paper) and writes it back
+//      into the layer's LDS slot,
+//   4. sums T_l * colour_l in layer order with coalesced colour loads and puts
+//      the background behind (the generation-0 tile),
+//   5. optionally stores the finished f32 pixel, folds it into the running
+//      mean and M2 (Welford) and tonemaps the displayed value to RGBA8.
+// Per-tile variance: a wave/LDS reduction of M2 over the unit; units of one
+// tile combine their partial sums in a fixed order (deterministic).
+// Every fragment byte is read from HBM exactly once.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dfb_internal.h"
+#include "sortnet.h"
+
+namespace dfb {
+namespace {
+
+template <typename FT>
+__device__ __forceinline__ float ldf(const void* base, size_t i);
+template <>
+__device__ __forceinline__ float ldf<float>(const void* base, size_t i) {
+  return static_cast<const float*>(base)[i];
+}
+template <>
+__device__ __forceinline__ float ldf<_Float16>(const void* base, size_t i) {
+  return static_cast<float>(static_cast<const _Float16*>(base)[i]);
+}
+
+// Order-preserving map of a depth to 32 bits: NaN above everything, -0 == +0.
+__device__ __forceinline__ uint32_t depth_bits(float d) {
+  uint32_t b = __float_as_uint(d);
+  if (d != d) return 0xFFFFFFFFu;
+  if (b == 0x80000000u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t quantise(float x, bool gamma, float inv_gamma) {
+  float y = x > 0.f ? x : 0.f;  // NaN compares false -> 0
+  y = y < 1.f ? y : 1.f;
+  if (gamma) y = powf(y, inv_gamma);
+  return static_cast<uint32_t>(floorf(fmaf(255.f, y, 0.5f)));
+}
+
+__device__ __forceinline__ uint32_t pack_rgba8(float4 v, uint32_t mode, float inv_gamma) {
+  const bool g = (mode & kModeGamma) != 0;
+  return quantise(v.x, g, inv_gamma) | (quantise(v.y, g, inv_gamma) << 8) |
+         (quantise(v.z, g, inv_gamma) << 16) | (quantise(v.w, false, 1.f) << 24);
+}
+
+// Pixel -> finished / accumulated / displayed outputs.  Returns the pixel's
+// M2 sum over RGB (0 when not accumulating or outside the image).
+__device__ __forceinline__ float store_pixel(float4 x, size_t px, size_t m2_base, int P,
+                                             bool inside, uint32_t mode, int n_acc, float inv_n,
+                                             float inv_gamma, float* finished, float* accum,
+                                             float* m2, void* final_out) {
+  if (mode & kModeKeepFinished) reinterpret_cast<float4*>(finished)[px] = x;
+  float4 disp = x;
+  float vs = 0.f;
+  if (mode & kModeAccumulate) {
+    float* q = m2 + m2_base;
+    float4 mu;
+    float q0, q1, q2;
+    if (n_acc == 1) {
+      mu = x;
+      q0 = q1 = q2 = 0.f;
+    } else {
+      mu = reinterpret_cast<const float4*>(accum)[px];
+      q0 = q[0];
+      q1 = q[P];
+      q2 = q[2 * P];
+      const float d0 = x.x - mu.x, d1 = x.y - mu.y, d2 = x.z - mu.z, d3 = x.w - mu.w;
+      mu.x = fmaf(d0, inv_n, mu.x);
+      mu.y = fmaf(d1, inv_n, mu.y);
+      mu.z = fmaf(d2, inv_n, mu.z);
+      mu.w = fmaf(d3, inv_n, mu.w);
+      q0 = fmaf(d0, x.x - mu.x, q0);
+      q1 = fmaf(d1, x.y - mu.y, q1);
+      q2 = fmaf(d2, x.z - mu.z, q2);
+    }
+    reinterpret_cast<float4*>(accum)[px] = mu;
+    q[0] = q0;
+    q[P] = q1;
+    q[2 * P] = q2;
+    if (inside) vs = q0 + q1 + q2;
+    disp = mu;
+  }
+  if (mode & kModeFmtRGBA8) {
+    static_cast<uint32_t*>(final_out)[px] = pack_rgba8(disp, mode, inv_gamma);
+  } else if (mode & kModeFmtF32) {
+    static_cast<float4*>(final_out)[px] = disp;
+  }
+  return vs;
+}
+
+struct Unit {
+  int t, sx0, sy0, x0, y0;  // tile, unit origin inside the tile, tile origin in the image
+};
+
+__device__ __forceinline__ int unit_pixel(const FrameArgs& a, const Unit& u, int q, bool& inside) {
+  const int qy = q / a.work_w;
+  const int qx = q - qy * a.work_w;
+  const int ty = u.sy0 + qy, tx = u.sx0 + qx;
+  inside = (u.x0 + tx < a.width) && (u.y0 + ty < a.height);
+  return ty * a.tile_w + tx;
+}
+
+__device__ __forceinline__ float finish_px(const FrameArgs& a, const Unit& u, int p, bool inside,
+                                           float4 x) {
+  const size_t px = static_cast<size_t>(u.t) * a.P + p;
+  const size_t mb = static_cast<size_t>(u.t) * 3 * a.P + p;
+  return store_pixel(x, px, mb, a.P, inside, a.mode, a.n_acc, a.inv_n, a.inv_gamma, a.finished,
+                     a.accum, a.m2, a.final_out);
+}
+
+// ---------------------------------------------------------------- K <= 32
+// One lane per pixel.  wl points at this lane's column of a [KMAX][NT] LDS
+// array: the lane writes alpha of layer l to wl[l*NT], later overwrites it
+// with the transmittance in front of layer l.  No lane reads another lane's
+// column, so no barrier is needed.
+template <typename FT, int KMAX>
+__device__ __forceinline__ float4 composite_px(const FrameArgs& a, const int64_t* __restrict__ blk,
+                                               int K, int off, int p, float* __restrict__ wl,
+                                               int NT) {
+  const size_t P = static_cast<size_t>(a.P);
+  uint64_t key[KMAX];
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l < K) {
+      const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p;
+      const float d = ldf<FT>(a.frag, base + 4 * P);
+      const float al = ldf<FT>(a.frag, base + 3 * P);
+      key[l] = (static_cast<uint64_t>(depth_bits(d)) << 32) | static_cast<uint32_t>(l);
+      wl[l * NT] = al;
+    } else {
+      key[l] = ~0ull;
+    }
+  }
+  sort_network<KMAX>(key);
+  float T = 1.f, A = 0.f;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    if (i < K) {
+      const int l = static_cast<int>(static_cast<uint32_t>(key[i]));
+      const float al = wl[l * NT];
+      wl[l * NT] = T;
+      A = fmaf(T, al, A);
+      T = T * (1.f - al);
+      if (a.mode & kModeKeepOrder)
+        a.order[static_cast<size_t>(off + i) * P + p] = static_cast<uint16_t>(l);
+    }
+  }
+  float R = 0.f, G = 0.f, B = 0.f;
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l < K) {
+      const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p;
+      const float w = wl[l * NT];
+      R = fmaf(w, ldf<FT>(a.frag, base), R);
+      G = fmaf(w, ldf<FT>(a.frag, base + P), G);
+      B = fmaf(w, ldf<FT>(a.frag, base + 2 * P), B);
+    }
+  }
+  return make_float4(fmaf(T, a.bg[0], R), fmaf(T, a.bg[1], G), fmaf(T, a.bg[2], B),
+                     fmaf(T, a.bg[3], A));
+}
+
+template <typename FT, int KMAX>
+__device__ float unit_reg(const FrameArgs& a, const Unit& u, const int64_t* blk, int K, int off,
+                          float* lds) {
+  const int NT = blockDim.x, tid = threadIdx.x;
+  float vs = 0.f;
+  for (int q = tid; q < a.work_px; q += NT) {
+    bool inside;
+    const int p = unit_pixel(a, u, q, inside);
+    const float4 x = composite_px<FT, KMAX>(a, blk, K, off, p, lds + tid, NT);
+    vs += finish_px(a, u, p, inside, x);
+  }
+  return vs;
+}
+
+__device__ float unit_background(const FrameArgs& a, const Unit& u) {
+  const int NT = blockDim.x;
+  float vs = 0.f;
+  for (int q = threadIdx.x; q < a.work_px; q += NT) {
+    bool inside;
+    const int p = unit_pixel(a, u, q, inside);
+    vs += finish_px(a, u, p, inside, make_float4(a.bg[0], a.bg[1], a.bg[2], a.bg[3]));
+  }
+  return vs;
+}
+
+// ---------------------------------------------------------------- K > 32
+// The workgroup handles G pixels at a time.  LDS rows (one per pixel) hold Kp
+// keys (u64) and Kp floats (alpha, later T); columns are XOR-swizzled by the
+// row so that both the coalesced fill (threads across pixels) and the sort
+// (threads along a row) are free of bank conflicts.  S = NT / G lanes share a
+// pixel for the front-to-back walk (a product scan over S chunks) and for the
+// colour sums (a fixed-order reduction).
+template <typename FT>
+__device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ blk,
+                           int K, int off, char* lds) {
+  const int NT = blockDim.x, tid = threadIdx.x;
+  const size_t P = static_cast<size_t>(a.P);
+  int Kp = 64;
+  while (Kp < K) Kp <<= 1;
+  int G = kBigLdsBytes / (Kp * 12);
+  G = G > NT ? NT : G;
+  G = G > 64 ? 64 : G;
+  while (G & (G - 1)) G &= G - 1;  // power of two
+  const int S = NT / G;            // lanes per pixel
+  const int C = Kp / S > 0 ? Kp / S : 1;  // sorted positions per lane
+  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+  float* wv = reinterpret_cast<float*>(keys + static_cast<size_t>(G) * Kp);
+  float4* red = reinterpret_cast<float4*>(lds + kBigLdsBytes);  // [NT]
+  float* tend = reinterpret_cast<float*>(red + NT);               // [G]
+  const int gm = tid % G, sm = tid / G;
+  float vs = 0.f;
+  for (int q0 = 0; q0 < a.work_px; q0 += G) {
+    // 1. keys and alpha (coalesced over the G pixels)
+    for (int e = tid; e < G * Kp; e += NT) {
+      const int g = e % G, l = e / G, q = q0 + g;
+      uint64_t key = ~0ull;
+      float al = 0.f;
+      if (l < K && q < a.work_px) {
+        bool in;
+        const int p = unit_pixel(a, u, q, in);
+        const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p;
+        key = (static_cast<uint64_t>(depth_bits(ldf<FT>(a.frag, base + 4 * P))) << 32) |
+              static_cast<uint32_t>(l);
+        al = ldf<FT>(a.frag, base + 3 * P);
+      }
+      const int col = l ^ (g & 15);
+      keys[g * Kp + col] = key;
+      wv[g * Kp + col] = al;
+    }
+    __syncthreads();
+    // 2. sort every row
+    for (int size = 2; size <= Kp; size <<= 1) {
+      for (int str = size >> 1; str > 0; str >>= 1) {
+        for (int e = tid; e < G * (Kp / 2); e += NT) {
+          const int g = e / (Kp / 2), c = e - g * (Kp / 2);
+          const int lo = (c / str) * (2 * str) + (c % str);
+          const int hi = (str == (size >> 1)) ? (lo ^ (size - 1)) : (lo + str);
+          uint64_t* r = keys + g * Kp;
+          const int sw = g & 15;
+          const uint64_t x = r[lo ^ sw], y = r[hi ^ sw];
+          if (y < x) {
+            r[lo ^ sw] = y;
+            r[hi ^ sw] = x;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // 3. front-to-back walk: chunk products, exclusive scan over the S chunks.
+    //    Rows past the unit's last pixel hold only padding keys: skipped.
+    const int sw = gm & 15;
+    const uint64_t* row = keys + gm * Kp;
+    float* wrow = wv + gm * Kp;
+    const int qme = q0 + gm;
+    const bool live = qme < a.work_px;
+    const int i0 = sm * C, i1 = live ? ((i0 + C < K) ? i0 + C : K) : 0;
+    float prod = 1.f;
+    for (int i = i0; i < i1; ++i) {
+      const int l = static_cast<int>(static_cast<uint32_t>(row[i ^ sw]));
+      prod = prod * (1.f - wrow[l ^ sw]);
+    }
+    red[tid].x = prod;
+    __syncthreads();
+    float T = 1.f;
+    for (int s2 = 0; s2 < sm; ++s2) T = T * red[s2 * G + gm].x;
+    __syncthreads();
+    float Ap = 0.f;
+    bool in_me = false;
+    const int p_me = live ? unit_pixel(a, u, qme, in_me) : 0;
+    for (int i = i0; i < i1; ++i) {
+      const int l = static_cast<int>(static_cast<uint32_t>(row[i ^ sw]));
+      const float al = wrow[l ^ sw];
+      wrow[l ^ sw] = T;
+      Ap = fmaf(T, al, Ap);
+      T = T * (1.f - al);
+      if (a.mode & kModeKeepOrder)
+        a.order[static_cast<size_t>(off + i) * P + p_me] = static_cast<uint16_t>(l);
+    }
+    __syncthreads();
+    // 4. colour in layer order (coalesced over the G pixels)
+    float R = 0.f, Gc = 0.f, B = 0.f;
+    if (live) {
+      for (int l = sm; l < K; l += S) {
+        const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p_me;
+        const float w = wrow[l ^ sw];
+        R = fmaf(w, ldf<FT>(a.frag, base), R);
+        Gc = fmaf(w, ldf<FT>(a.frag, base + P), Gc);
+        B = fmaf(w, ldf<FT>(a.frag, base + 2 * P), B);
+      }
+    }
+    // lanes whose chunk is the last non-empty one hold the final T
+    const int last = (K - 1) / C;
+    red[tid] = make_float4(R, Gc, B, Ap);
+    if (sm == last) tend[gm] = T;
+    __syncthreads();
+    if (sm == 0 && live) {
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int s2 = 0; s2 < S; ++s2) {
+        const float4 v = red[s2 * G + gm];
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
+      }
+      const float Te = tend[gm];
+      const float4 x = make_float4(fmaf(Te, a.bg[0], acc.x), fmaf(Te, a.bg[1], acc.y),
+                                   fmaf(Te, a.bg[2], acc.z), fmaf(Te, a.bg[3], acc.w));
+      vs += finish_px(a, u, p_me, in_me, x);
+    }
+    __syncthreads();
+  }
+  return vs;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float variance_of_mean(float sum, int inside_px, int n) {
+  if (n < 2) return __int_as_float(0x7f800000);
+  return sum / (3.f * static_cast<float>(inside_px) * static_cast<float>(n) *
+                static_cast<float>(n - 1));
+}
+
+template <typename FT, int KCAP>
+__global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  __shared__ int s_item;
+  __shared__ float s_red[4];
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      const unsigned long long v = atomicAdd(a.queue, 1ull) - a.q_base;
+      s_item = v < static_cast<unsigned long long>(a.n_work) ? static_cast<int>(v) : a.n_work;
+    }
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= a.n_work) break;
+    const int w = a.work_list[it];
+    Unit u;
+    u.t = w / a.subs_per_tile;
+    const int s = w - u.t * a.subs_per_tile;
+    u.sy0 = (s / a.subs_x) * a.work_h;
+    u.sx0 = (s - (s / a.subs_x) * a.subs_x) * a.work_w;
+    u.y0 = (u.t / a.tiles_x) * a.tile_h;
+    u.x0 = (u.t - (u.t / a.tiles_x) * a.tiles_x) * a.tile_w;
+    const int off = a.tile_off[u.t];
+    const int K = a.tile_off[u.t + 1] - off;
+    const int64_t* blk = a.layer_block + off;
+    float* wl = reinterpret_cast<float*>(lds);
+    float vs;
+    if (K == 0) vs = unit_background(a, u);
+    else if (K <= 1) vs = unit_reg<FT, 1>(a, u, blk, K, off, wl);
+    else if (K <= 2) vs = unit_reg<FT, 2>(a, u, blk, K, off, wl);
+    else if (K <= 3) vs = unit_reg<FT, 3>(a, u, blk, K, off, wl);
+    else if (K <= 4) vs = unit_reg<FT, 4>(a, u, blk, K, off, wl);
+    else if (K <= 6) vs = unit_reg<FT, 6>(a, u, blk, K, off, wl);
+    else if (K <= 8) vs = unit_reg<FT, 8>(a, u, blk, K, off, wl);
+    else if (KCAP >= 16 && K <= 12) vs = unit_reg<FT, (KCAP >= 16 ? 12 : 1)>(a, u, blk, K, off, wl);
+    else if (KCAP >= 16 && K <= 16) vs = unit_reg<FT, (KCAP >= 16 ? 16 : 1)>(a, u, blk, K, off, wl);
+    else if (KCAP >= 32 && K <= 24) vs = unit_reg<FT, (KCAP >= 32 ? 24 : 1)>(a, u, blk, K, off, wl);
+    else if (KCAP >= 32 && K <= 32) vs = unit_reg<FT, (KCAP >= 32 ? 32 : 1)>(a, u, blk, K, off, wl);
+    else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
+    if (a.mode & kModeAccumulate) {
+      // per-tile variance of the mean: fixed-order reductions only
+      vs = wave_sum(vs);
+      if ((tid & 63) == 0) s_red[tid >> 6] = vs;
+      __syncthreads();
+      if (tid == 0) {
+        float sum = 0.f;
+        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) sum += s_red[i];
+        const int wx = a.width - u.x0, wy = a.height - u.y0;
+        const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
+        if (a.subs_per_tile == 1) {
+          a.tile_var[u.t] = variance_of_mean(sum, inside, a.n_acc);
+        } else {
+          __hip_atomic_store(a.var_partial + w, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __threadfence();
+          const uint32_t old = atomicAdd(a.tile_done + u.t, 1u);
+          if (old == a.done_base + static_cast<uint32_t>(a.subs_per_tile) - 1u) {
+            __threadfence();
+            float tot = 0.f;
+            for (int i = 0; i < a.subs_per_tile; ++i)
+              tot += __hip_atomic_load(a.var_partial + u.t * a.subs_per_tile + i,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.tile_var[u.t] = variance_of_mean(tot, inside, a.n_acc);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Unfused accumulation of the stored finished tiles: one workgroup per tile.
+__global__ void __launch_bounds__(256) accumulate_kernel_t(AccumArgs a) {
+  __shared__ float s_red[4];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  const int x0 = (t % a.tiles_x) * a.tile_w, y0 = (t / a.tiles_x) * a.tile_h;
+  float vs = 0.f;
+  for (int p = tid; p < a.P; p += blockDim.x) {
+    const int py = p / a.tile_w, pxl = p - py * a.tile_w;
+    const bool inside = (x0 + pxl < a.width) && (y0 + py < a.height);
+    const size_t px = static_cast<size_t>(t) * a.P + p;
+    const float4 x = reinterpret_cast<const float4*>(a.finished)[px];
+    vs += store_pixel(x, px, static_cast<size_t>(t) * 3 * a.P + p, a.P, inside,
+                      (a.mode & ~kModeKeepFinished) | kModeAccumulate, a.n_acc, a.inv_n,
+                      a.inv_gamma, nullptr, a.accum, a.m2, a.final_out);
+  }
+  vs = wave_sum(vs);
+  if ((tid & 63) == 0) s_red[tid >> 6] = vs;
+  __syncthreads();
+  if (tid == 0) {
+    float sum = 0.f;
+    for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) sum += s_red[i];
+    const int wx = a.width - x0, wy = a.height - y0;
+    const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
+    a.tile_var[t] = variance_of_mean(sum, inside, a.n_acc);
+  }
+}
+
+// NaN scan of every layer's depth plane: one workgroup per layer.
+template <typename FT>
+__global__ void __launch_bounds__(256) validate_kernel_t(ValidateArgs a) {
+  const int l = blockIdx.x;
+  if (l >= a.n_layers) return;
+  const size_t base = static_cast<size_t>(a.layer_block[l]) * 5 * a.P + 4 * static_cast<size_t>(a.P);
+  bool bad = false;
+  for (int p = threadIdx.x; p < a.P; p += blockDim.x) {
+    const float d = ldf<FT>(a.frag, base + p);
+    bad |= (d != d);
+  }
+  if (bad) atomicOr(a.bad, 1u);
+}
+
+}  // namespace
+
+const void* frame_kernel(int dtype, int kcap) {
+  if (dtype == 0) {
+    if (kcap <= 8) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8>);
+    if (kcap <= 16) return reinterpret_cast<const void*>(&frame_kernel_t<float, 16>);
+    return reinterpret_cast<const void*>(&frame_kernel_t<float, 32>);
+  }
+  if (kcap <= 8) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 8>);
+  if (kcap <= 16) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 16>);
+  return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 32>);
+}
+
+const void* accumulate_kernel() { return reinterpret_cast<const void*>(&accumulate_kernel_t); }
+
+const void* validate_kernel(int dtype) {
+  return dtype == 0 ? reinterpret_cast<const void*>(&validate_kernel_t<float>)
+                    : reinterpret_cast<const void*>(&validate_kernel_t<_Float16>);
+}
+
+size_t frame_lds_bytes(int kcap, int threads, int max_layers) {
+  size_t small = static_cast<size_t>(kcap) * threads * sizeof(float);
+  size_t big = 0;
+  if (max_layers > kcap) big = kBigLdsBytes + static_cast<size_t>(threads) * 16 + 64 * 4;
+  return small > big ? small : big;
+}
+
+}  // namespace dfb

@@ -1,0 +1,847 @@
+// Host runtime of the C ABI in include/dfb.h: handle, validation, the
+// per-tile layer table (CSR), the longest-first work queue, the one-node HIP
+// graph replayed per frame, and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dfb.h"
+#include "dfb_internal.h"
+
+namespace {
+
+using dfb::FrameArgs;
+
+std::string g_create_error;
+
+enum class State { kEmpty, kReady, kComposited };
+
+struct AutotuneKey {
+  int device, width, height, tile_w, tile_h, dtype, max_k;
+  uint64_t digest;
+  bool operator<(const AutotuneKey& o) const {
+    return std::tie(device, width, height, tile_w, tile_h, dtype, max_k, digest) <
+           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.max_k, o.digest);
+  }
+};
+struct Shape {
+  int work_w, work_h, waves;
+};
+std::map<AutotuneKey, Shape> g_autotune_cache;
+
+}  // namespace
+
+struct dfb_ctx {
+  dfb_config cfg{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_cu = 0;
+  int tiles_x = 0, tiles_y = 0, n_tiles = 0, P = 0;
+  State state = State::kEmpty;
+  bool sticky_hip = false;
+  std::string err;
+
+  // device outputs
+  float* finished = nullptr;
+  float* accum = nullptr;
+  float* m2 = nullptr;
+  float* tile_var = nullptr;
+  void* final_out = nullptr;
+  uint16_t* order = nullptr;
+  size_t order_cap = 0;
+  int acc_n = 0;          // frames folded in
+  bool have_finished = false;
+
+  // per-frame layer table
+  const void* frag = nullptr;
+  int64_t n_blocks = 0;
+  int n_layers = 0, max_k = 0;
+  std::vector<int32_t> h_off;
+  std::vector<int64_t> h_block;
+  std::vector<dfb_layer> last_layers;
+  std::vector<int32_t> last_expected;
+  bool last_had_expected = false;
+  uint64_t digest = 0;
+  int32_t* d_off = nullptr;
+  int64_t* d_block = nullptr;
+  size_t block_cap = 0;
+  int32_t* d_work = nullptr;
+  size_t work_cap = 0;
+  float* d_var_partial = nullptr;
+  size_t partial_cap = 0;
+  unsigned long long* d_queue = nullptr;
+  uint32_t* d_tile_done = nullptr;
+  uint32_t* d_flag = nullptr;
+  unsigned long long q_base = 0;
+  uint32_t done_base = 0;
+
+  // launch shape
+  Shape shape{0, 0, 0};
+  bool shape_valid = false;
+  int kcap = 8;
+  int grid = 0;
+  int n_work = 0;
+  int subs_x = 1, subs_per_tile = 1;
+  bool work_valid = false;  // d_work matches shape + layer table
+
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
+  const void* graph_func = nullptr;
+  int graph_threads = 0, graph_grid = 0;
+  size_t graph_lds = 0;
+  FrameArgs graph_args{};
+
+  // timing: a ring of event pairs, harvested when a slot is reused
+  static constexpr int kRing = 64;
+  bool timing = false;
+  hipEvent_t ev0[kRing] = {}, ev1[kRing] = {};
+  bool pending[kRing] = {};
+  int ring_pos = 0;
+  double time_sum_ms = 0.0;
+  int time_n = 0;
+};
+
+namespace {
+
+dfb_status fail(dfb_ctx* h, dfb_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+dfb_status hip_fail(dfb_ctx* h, hipError_t e, const char* what) {
+  if (h) h->sticky_hip = true;
+  return fail(h, DFB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define DFB_HIP(h, call)                                    \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #call);  \
+  } while (0)
+
+dfb_status check_config(const dfb_config* c, std::string& msg) {
+  if (!c) { msg = "config is null"; return DFB_ERR_INVALID_ARG; }
+  if (c->width <= 0 || c->height <= 0 || c->tile_w <= 0 || c->tile_h <= 0) {
+    msg = "width, height, tile_w, tile_h must be positive";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (static_cast<int64_t>(c->tile_w) * c->tile_h > 65536) {
+    msg = "tile_w * tile_h must be <= 65536";
+    return DFB_ERR_INVALID_ARG;
+  }
+  const int64_t tx = (c->width + c->tile_w - 1) / c->tile_w, ty = (c->height + c->tile_h - 1) / c->tile_h;
+  if (tx * ty > (1 << 24) || tx * ty * c->tile_w * c->tile_h > (int64_t(1) << 31)) {
+    msg = "framebuffer too large";
+    return DFB_ERR_OOM;
+  }
+  if ((c->work_w == 0) != (c->work_h == 0)) {
+    msg = "work_w and work_h must both be 0 (autotune) or both set";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (c->work_w < 0 || c->work_h < 0 || (c->work_w && (c->tile_w % c->work_w || c->tile_h % c->work_h))) {
+    msg = "work_w / work_h must divide tile_w / tile_h";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (!(c->waves_per_tile == 0 || c->waves_per_tile == 1 || c->waves_per_tile == 2 || c->waves_per_tile == 4)) {
+    msg = "waves_per_tile must be 0, 1, 2 or 4";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (c->frag_dtype != DFB_F32 && c->frag_dtype != DFB_F16) { msg = "bad frag_dtype"; return DFB_ERR_INVALID_ARG; }
+  if (c->format != DFB_FMT_RGBA8 && c->format != DFB_FMT_RGBAF32 && c->format != DFB_FMT_NONE) {
+    msg = "bad format";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (!(c->tonemap_gamma > 0.f) || !std::isfinite(c->tonemap_gamma)) { msg = "tonemap_gamma must be > 0"; return DFB_ERR_INVALID_ARG; }
+  if (c->flags & ~(DFB_VALIDATE | DFB_KEEP_SORT_ORDER | DFB_KEEP_FINISHED)) { msg = "unknown flag"; return DFB_ERR_INVALID_ARG; }
+  return DFB_OK;
+}
+
+// Validation + per-tile counts (host, O(n_layers + n_tiles)).
+dfb_status validate_layers(const dfb_config* c, int64_t n_blocks, const dfb_layer* layers, int32_t n_layers,
+                           const int32_t* expected, std::vector<int32_t>& counts, std::string& msg) {
+  dfb_status s = check_config(c, msg);
+  if (s != DFB_OK) return s;
+  const int tiles_x = (c->width + c->tile_w - 1) / c->tile_w;
+  const int n_tiles = tiles_x * ((c->height + c->tile_h - 1) / c->tile_h);
+  if (n_layers < 0 || n_blocks < 0 || (n_layers > 0 && !layers)) { msg = "bad layer list"; return DFB_ERR_INVALID_ARG; }
+  counts.assign(n_tiles, 0);
+  for (int32_t i = 0; i < n_layers; ++i) {
+    const dfb_layer& L = layers[i];
+    if (L.tile_id < 0 || L.tile_id >= n_tiles) {
+      msg = "layer " + std::to_string(i) + ": tile_id " + std::to_string(L.tile_id) + " out of range";
+      return DFB_ERR_INVALID_ARG;
+    }
+    if (L.block < 0 || L.block >= n_blocks) {
+      msg = "layer " + std::to_string(i) + ": block " + std::to_string(L.block) + " out of range";
+      return DFB_ERR_INVALID_ARG;
+    }
+    counts[L.tile_id]++;
+  }
+  for (int t = 0; t < n_tiles; ++t) {
+    if (counts[t] > dfb::kMaxLayers) {
+      msg = "tile " + std::to_string(t) + " has " + std::to_string(counts[t]) + " layers; at most " +
+            std::to_string(dfb::kMaxLayers) + " are supported";
+      return DFB_ERR_UNSUPPORTED;
+    }
+    if (expected && expected[t] != counts[t]) {
+      msg = "tile " + std::to_string(t) + ": " + std::to_string(counts[t]) + " layers arrived, background declared " +
+            std::to_string(expected[t]);
+      return DFB_ERR_INCOMPLETE;
+    }
+  }
+  return DFB_OK;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+template <typename T>
+dfb_status ensure(dfb_ctx* h, T*& ptr, size_t& cap, size_t count) {
+  if (count <= cap && ptr) return DFB_OK;
+  if (ptr) {
+    DFB_HIP(h, hipStreamSynchronize(h->stream));
+    DFB_HIP(h, hipFree(ptr));
+    ptr = nullptr;
+    cap = 0;
+  }
+  size_t n = std::max<size_t>(count, 1);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+    return fail(h, DFB_ERR_OOM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  cap = n;
+  return DFB_OK;
+}
+
+dfb_status alloc_plain(dfb_ctx* h, void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, std::max<size_t>(bytes, 16));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(h, DFB_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return DFB_OK;
+}
+
+dfb_status check_usable(dfb_ctx* h) {
+  if (!h) return DFB_ERR_INVALID_ARG;
+  if (h->sticky_hip) return fail(h, DFB_ERR_HIP, "an earlier HIP error left the handle unusable: " + h->err);
+  return DFB_OK;
+}
+
+int kcap_for(int max_k) { return max_k <= 8 ? 8 : (max_k <= 16 ? 16 : 32); }
+
+// Candidate launch shapes: square work units of 32/64/128 that divide the
+// tile (else the whole tile), times 1/2/4 waves.
+std::vector<Shape> candidates(const dfb_config& c) {
+  std::vector<std::pair<int, int>> sizes;
+  if (c.work_w) {
+    sizes.push_back({c.work_w, c.work_h});
+  } else {
+    for (int s : {32, 64, 128})
+      if (c.tile_w % s == 0 && c.tile_h % s == 0) sizes.push_back({s, s});
+    if (sizes.empty()) sizes.push_back({c.tile_w, c.tile_h});
+  }
+  std::vector<int> waves;
+  if (c.waves_per_tile) waves.push_back(c.waves_per_tile);
+  else waves = {1, 2, 4};
+  std::vector<Shape> out;
+  for (auto& s : sizes)
+    for (int w : waves) out.push_back({s.first, s.second, w});
+  return out;
+}
+
+// Work list for a shape: every (tile, unit) pair, tiles with more layers
+// first (longest-processing-time order), ties by tile id.
+dfb_status build_work(dfb_ctx* h, const Shape& s) {
+  const int sx = h->cfg.tile_w / s.work_w, sy = h->cfg.tile_h / s.work_h;
+  h->subs_x = sx;
+  h->subs_per_tile = sx * sy;
+  h->n_work = h->n_tiles * h->subs_per_tile;
+  std::vector<int32_t> tiles(h->n_tiles);
+  for (int t = 0; t < h->n_tiles; ++t) tiles[t] = t;
+  std::stable_sort(tiles.begin(), tiles.end(), [&](int a, int b) {
+    return (h->h_off[a + 1] - h->h_off[a]) > (h->h_off[b + 1] - h->h_off[b]);
+  });
+  std::vector<int32_t> work(h->n_work);
+  size_t k = 0;
+  for (int t : tiles)
+    for (int u = 0; u < h->subs_per_tile; ++u) work[k++] = t * h->subs_per_tile + u;
+  dfb_status st = ensure(h, h->d_work, h->work_cap, work.size());
+  if (st != DFB_OK) return st;
+  st = ensure(h, h->d_var_partial, h->partial_cap, work.size());
+  if (st != DFB_OK) return st;
+  DFB_HIP(h, hipMemcpyAsync(h->d_work, work.data(), work.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  DFB_HIP(h, hipStreamSynchronize(h->stream));  // host vector goes out of scope
+  h->work_valid = true;
+  return DFB_OK;
+}
+
+dfb_status ensure_accum(dfb_ctx* h) {
+  if (h->accum) return DFB_OK;
+  const size_t px = static_cast<size_t>(h->n_tiles) * h->P;
+  dfb_status s = alloc_plain(h, reinterpret_cast<void**>(&h->accum), px * 16);
+  if (s != DFB_OK) return s;
+  s = alloc_plain(h, reinterpret_cast<void**>(&h->m2), px * 12);
+  if (s != DFB_OK) return s;
+  return DFB_OK;
+}
+
+FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
+  FrameArgs a{};
+  a.frag = h->frag;
+  a.tile_off = h->d_off;
+  a.layer_block = h->d_block;
+  a.work_list = h->d_work;
+  a.queue = h->d_queue;
+  a.tile_done = h->d_tile_done;
+  a.q_base = h->q_base;
+  a.done_base = h->done_base;
+  a.n_work = h->n_work;
+  a.width = h->cfg.width;
+  a.height = h->cfg.height;
+  a.tiles_x = h->tiles_x;
+  a.n_tiles = h->n_tiles;
+  a.tile_w = h->cfg.tile_w;
+  a.tile_h = h->cfg.tile_h;
+  a.P = h->P;
+  a.work_w = h->shape.work_w;
+  a.work_h = h->shape.work_h;
+  a.subs_x = h->subs_x;
+  a.subs_per_tile = h->subs_per_tile;
+  a.work_px = h->shape.work_w * h->shape.work_h;
+  for (int c = 0; c < 4; ++c) a.bg[c] = h->cfg.background[c];
+  a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
+  a.mode = mode;
+  a.n_acc = h->acc_n;
+  a.inv_n = h->acc_n > 0 ? 1.f / static_cast<float>(h->acc_n) : 1.f;
+  a.finished = h->finished;
+  a.accum = h->accum;
+  a.m2 = h->m2;
+  a.tile_var = h->tile_var;
+  a.var_partial = h->d_var_partial;
+  a.final_out = h->final_out;
+  a.order = h->order;
+  return a;
+}
+
+uint32_t display_mode(const dfb_config& c) {
+  uint32_t m = 0;
+  if (c.format == DFB_FMT_RGBA8) m |= dfb::kModeFmtRGBA8;
+  if (c.format == DFB_FMT_RGBAF32) m |= dfb::kModeFmtF32;
+  if (c.tonemap_gamma != 1.f) m |= dfb::kModeGamma;
+  return m;
+}
+
+dfb_status grid_for(dfb_ctx* h, const void* func, int threads, size_t lds, int& grid) {
+  int per_cu = 0;
+  DFB_HIP(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, threads, lds));
+  if (per_cu < 1) return fail(h, DFB_ERR_UNSUPPORTED, "kernel does not fit on a compute unit with this shape");
+  grid = std::max(1, std::min(h->n_work, per_cu * h->n_cu));
+  return DFB_OK;
+}
+
+// Launch one frame with the current shape.  Uses the graph when asked.
+dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph) {
+  const int threads = 64 * h->shape.waves;
+  const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap);
+  const size_t lds = dfb::frame_lds_bytes(h->kcap, threads, h->max_k);
+  int grid = 0;
+  dfb_status st = grid_for(h, func, threads, lds, grid);
+  if (st != DFB_OK) return st;
+  if (lds > 64 * 1024) DFB_HIP(h, hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  FrameArgs a = make_args(h, mode);
+  if (use_graph) {
+    const bool rebuild = !h->exec || h->graph_func != func || h->graph_threads != threads ||
+                         h->graph_grid != grid || h->graph_lds != lds;
+    h->graph_args = a;
+    void* params[] = {&h->graph_args};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(func);
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(threads);
+    kp.sharedMemBytes = static_cast<unsigned>(lds);
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    if (rebuild) {
+      if (h->exec) { DFB_HIP(h, hipGraphExecDestroy(h->exec)); h->exec = nullptr; }
+      if (h->graph) { DFB_HIP(h, hipGraphDestroy(h->graph)); h->graph = nullptr; }
+      DFB_HIP(h, hipGraphCreate(&h->graph, 0));
+      DFB_HIP(h, hipGraphAddKernelNode(&h->node, h->graph, nullptr, 0, &kp));
+      DFB_HIP(h, hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+      h->graph_func = func;
+      h->graph_threads = threads;
+      h->graph_grid = grid;
+      h->graph_lds = lds;
+    } else {
+      DFB_HIP(h, hipGraphExecKernelNodeSetParams(h->exec, h->node, &kp));
+    }
+    DFB_HIP(h, hipGraphLaunch(h->exec, h->stream));
+  } else {
+    void* params[] = {&a};
+    DFB_HIP(h, hipLaunchKernel(func, dim3(grid), dim3(threads), params, lds, h->stream));
+  }
+  DFB_HIP(h, hipGetLastError());
+  h->grid = grid;
+  h->q_base += static_cast<unsigned long long>(h->n_work) + static_cast<unsigned long long>(grid);
+  if ((mode & dfb::kModeAccumulate) && h->subs_per_tile > 1) h->done_base += static_cast<uint32_t>(h->subs_per_tile);
+  return DFB_OK;
+}
+
+dfb_status autotune(dfb_ctx* h) {
+  AutotuneKey key{h->device, h->cfg.width, h->cfg.height, h->cfg.tile_w, h->cfg.tile_h,
+                  h->cfg.frag_dtype, h->max_k, h->digest};
+  auto cands = candidates(h->cfg);
+  if (cands.size() == 1) {
+    h->shape = cands[0];
+    h->shape_valid = true;
+    return build_work(h, h->shape);
+  }
+  auto it = g_autotune_cache.find(key);
+  if (it != g_autotune_cache.end()) {
+    h->shape = it->second;
+    h->shape_valid = true;
+    return build_work(h, h->shape);
+  }
+  hipEvent_t e0, e1;
+  DFB_HIP(h, hipEventCreate(&e0));
+  DFB_HIP(h, hipEventCreate(&e1));
+  double best = 1e300;
+  Shape best_s = cands[0];
+  const uint32_t mode = display_mode(h->cfg);
+  for (const Shape& s : cands) {
+    h->shape = s;
+    dfb_status st = build_work(h, s);
+    if (st != DFB_OK) return st;
+    std::vector<float> times;
+    for (int r = 0; r < 10; ++r) {
+      DFB_HIP(h, hipEventRecord(e0, h->stream));
+      st = launch_frame(h, mode, false);
+      if (st != DFB_OK) return st;
+      DFB_HIP(h, hipEventRecord(e1, h->stream));
+      DFB_HIP(h, hipEventSynchronize(e1));
+      float ms = 0.f;
+      DFB_HIP(h, hipEventElapsedTime(&ms, e0, e1));
+      if (r >= 5) times.push_back(ms);  // 5 warm-up, 5 timed
+    }
+    std::sort(times.begin(), times.end());
+    const double med = times[times.size() / 2];
+    if (med < best) { best = med; best_s = s; }
+  }
+  DFB_HIP(h, hipEventDestroy(e0));
+  DFB_HIP(h, hipEventDestroy(e1));
+  g_autotune_cache[key] = best_s;
+  h->shape = best_s;
+  h->shape_valid = true;
+  return build_work(h, best_s);
+}
+
+dfb_status harvest(dfb_ctx* h, int slot) {
+  float ms = 0.f;
+  DFB_HIP(h, hipEventSynchronize(h->ev1[slot]));
+  DFB_HIP(h, hipEventElapsedTime(&ms, h->ev0[slot], h->ev1[slot]));
+  h->time_sum_ms += ms;
+  h->time_n += 1;
+  h->pending[slot] = false;
+  return DFB_OK;
+}
+
+dfb_status prepare_shape(dfb_ctx* h) {
+  if (h->shape_valid && h->work_valid) return DFB_OK;
+  return autotune(h);
+}
+
+// Device NaN scan of every layer's depth plane (DFB_VALIDATE).  Uses the
+// block table already on the device.
+dfb_status scan_nan(dfb_ctx* h, const void* frag_dev, int n_layers) {
+  if (n_layers == 0) return DFB_OK;
+  DFB_HIP(h, hipMemsetAsync(h->d_flag, 0, sizeof(uint32_t), h->stream));
+  dfb::ValidateArgs va{frag_dev, h->d_block, n_layers, h->P, h->d_flag};
+  void* params[] = {&va};
+  DFB_HIP(h, hipLaunchKernel(dfb::validate_kernel(h->cfg.frag_dtype), dim3(n_layers), dim3(256), params, 0,
+                             h->stream));
+  uint32_t bad = 0;
+  DFB_HIP(h, hipMemcpyAsync(&bad, h->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+  DFB_HIP(h, hipStreamSynchronize(h->stream));
+  if (bad) return fail(h, DFB_ERR_BAD_VALUE, "a fragment depth is NaN");
+  return DFB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dfb_status_string(dfb_status s) {
+  switch (s) {
+    case DFB_OK: return "ok";
+    case DFB_ERR_INVALID_ARG: return "invalid argument";
+    case DFB_ERR_STATE: return "call out of order";
+    case DFB_ERR_INCOMPLETE: return "incomplete dependency tree";
+    case DFB_ERR_DUPLICATE: return "duplicate (tile, source)";
+    case DFB_ERR_BAD_VALUE: return "bad value (NaN depth)";
+    case DFB_ERR_OOM: return "out of memory";
+    case DFB_ERR_HIP: return "HIP error";
+    case DFB_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* dfb_last_error(dfb_handle h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+dfb_status dfb_validate_layers(const dfb_config* cfg, int64_t n_blocks, const dfb_layer* layers, int32_t n_layers,
+                               const int32_t* expected, int32_t* counts) {
+  std::vector<int32_t> c;
+  std::string msg;
+  dfb_status s = validate_layers(cfg, n_blocks, layers, n_layers, expected, c, msg);
+  if (s == DFB_OK) {
+    // duplicates: sort (tile, source) pairs
+    std::vector<std::pair<int32_t, uint32_t>> ts(n_layers);
+    for (int i = 0; i < n_layers; ++i) ts[i] = {layers[i].tile_id, layers[i].source_id};
+    std::sort(ts.begin(), ts.end());
+    for (int i = 1; i < n_layers; ++i)
+      if (ts[i] == ts[i - 1]) {
+        msg = "tile " + std::to_string(ts[i].first) + ": source " + std::to_string(ts[i].second) + " appears twice";
+        s = DFB_ERR_DUPLICATE;
+        break;
+      }
+  }
+  if (s == DFB_OK && counts) std::copy(c.begin(), c.end(), counts);
+  g_create_error = msg;
+  return s;
+}
+
+dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) {
+  if (!out) return fail(nullptr, DFB_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  std::string msg;
+  dfb_status s = check_config(cfg, msg);
+  if (s != DFB_OK) return fail(nullptr, s, msg);
+  dfb_ctx* h = new (std::nothrow) dfb_ctx();
+  if (!h) return fail(nullptr, DFB_ERR_OOM, "host allocation failed");
+  h->cfg = *cfg;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  auto bail = [&](dfb_status st) {
+    g_create_error = h->err;
+    dfb_destroy(h);
+    return st;
+  };
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) { hip_fail(h, e, "hipGetDevice"); return bail(DFB_ERR_HIP); }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, h->device);
+  if (e != hipSuccess) { hip_fail(h, e, "hipGetDeviceProperties"); return bail(DFB_ERR_HIP); }
+  h->n_cu = prop.multiProcessorCount;
+  h->tiles_x = (cfg->width + cfg->tile_w - 1) / cfg->tile_w;
+  h->tiles_y = (cfg->height + cfg->tile_h - 1) / cfg->tile_h;
+  h->n_tiles = h->tiles_x * h->tiles_y;
+  h->P = cfg->tile_w * cfg->tile_h;
+  const size_t px = static_cast<size_t>(h->n_tiles) * h->P;
+  if (cfg->flags & DFB_KEEP_FINISHED) {
+    if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->finished), px * 16)) != DFB_OK) return bail(s);
+  }
+  if (cfg->format == DFB_FMT_RGBA8) {
+    if ((s = alloc_plain(h, &h->final_out, px * 4)) != DFB_OK) return bail(s);
+  } else if (cfg->format == DFB_FMT_RGBAF32) {
+    if ((s = alloc_plain(h, &h->final_out, px * 16)) != DFB_OK) return bail(s);
+  }
+  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->tile_var), h->n_tiles * sizeof(float))) != DFB_OK) return bail(s);
+  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_queue), 64)) != DFB_OK) return bail(s);
+  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_tile_done), h->n_tiles * sizeof(uint32_t))) != DFB_OK) return bail(s);
+  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_flag), 64)) != DFB_OK) return bail(s);
+  e = hipMemsetAsync(h->d_queue, 0, 64, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->d_tile_done, 0, h->n_tiles * sizeof(uint32_t), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->tile_var, 0, h->n_tiles * sizeof(float), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) { hip_fail(h, e, "initialising device state"); return bail(DFB_ERR_HIP); }
+  *out = h;
+  return DFB_OK;
+}
+
+dfb_status dfb_destroy(dfb_handle h) {
+  if (!h) return DFB_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(h->stream);
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (int i = 0; i < dfb_ctx::kRing; ++i) {
+    if (h->ev0[i]) (void)hipEventDestroy(h->ev0[i]);
+    if (h->ev1[i]) (void)hipEventDestroy(h->ev1[i]);
+  }
+  void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->d_off,
+                  h->d_block, h->d_work, h->d_var_partial, h->d_queue, h->d_tile_done, h->d_flag};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete h;
+  return DFB_OK;
+}
+
+dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_blocks, const dfb_layer* layers,
+                             int32_t n_layers, const int32_t* expected) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (!frag_dev && n_layers > 0) return fail(h, DFB_ERR_INVALID_ARG, "frag_dev is null");
+  // Fast path: same layer list as the previous frame, only the buffer moves.
+  const bool same = h->state != State::kEmpty && n_layers == h->n_layers && n_blocks == h->n_blocks &&
+                    (expected != nullptr) == h->last_had_expected &&
+                    (n_layers == 0 || std::memcmp(layers, h->last_layers.data(), sizeof(dfb_layer) * n_layers) == 0) &&
+                    (!expected || std::memcmp(expected, h->last_expected.data(), sizeof(int32_t) * h->n_tiles) == 0);
+  if (same) {
+    if (h->cfg.flags & DFB_VALIDATE) {
+      s = scan_nan(h, frag_dev, n_layers);
+      if (s != DFB_OK) return s;
+    }
+    h->frag = frag_dev;
+    h->state = State::kReady;
+    return DFB_OK;
+  }
+  std::vector<int32_t> counts;
+  std::string msg;
+  s = validate_layers(&h->cfg, n_blocks, layers, n_layers, expected, counts, msg);
+  if (s != DFB_OK) return fail(h, s, msg);
+  // CSR: layers grouped by tile, each tile's layers by ascending source id.
+  std::vector<int32_t> off(h->n_tiles + 1, 0);
+  for (int t = 0; t < h->n_tiles; ++t) off[t + 1] = off[t] + counts[t];
+  std::vector<int32_t> idx(n_layers);
+  {
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int32_t i = 0; i < n_layers; ++i) idx[fill[layers[i].tile_id]++] = i;
+  }
+  std::vector<int64_t> block(n_layers);
+  int max_k = 0;
+  for (int t = 0; t < h->n_tiles; ++t) {
+    auto b = idx.begin() + off[t], e = idx.begin() + off[t + 1];
+    std::sort(b, e, [&](int32_t x, int32_t y) { return layers[x].source_id < layers[y].source_id; });
+    for (auto it = b; it != e; ++it) {
+      if (it != b && layers[*it].source_id == layers[*(it - 1)].source_id)
+        return fail(h, DFB_ERR_DUPLICATE, "tile " + std::to_string(t) + ": source " +
+                                              std::to_string(layers[*it].source_id) + " appears twice");
+      block[it - idx.begin()] = layers[*it].block;
+    }
+    max_k = std::max(max_k, counts[t]);
+  }
+  size_t off_cap = 0;
+  if (!h->d_off) {
+    s = ensure(h, h->d_off, off_cap, off.size());
+    if (s != DFB_OK) return s;
+  }
+  s = ensure(h, h->d_block, h->block_cap, block.size());
+  if (s != DFB_OK) return s;
+  DFB_HIP(h, hipStreamSynchronize(h->stream));  // previous frame may still read the tables
+  DFB_HIP(h, hipMemcpy(h->d_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (n_layers) DFB_HIP(h, hipMemcpy(h->d_block, block.data(), block.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  if (h->cfg.flags & DFB_VALIDATE) {
+    s = scan_nan(h, frag_dev, n_layers);
+    if (s != DFB_OK) {
+      h->state = State::kEmpty;
+      h->n_layers = -1;
+      return s;
+    }
+  }
+  if (h->cfg.flags & DFB_KEEP_SORT_ORDER) {
+    s = ensure(h, h->order, h->order_cap, static_cast<size_t>(n_layers) * h->P);
+    if (s != DFB_OK) return s;
+  }
+  // digest of the per-tile layer counts: the autotune cache key
+  uint64_t dg = fnv1a(counts.data(), counts.size() * sizeof(int32_t));
+  if (dg != h->digest || max_k != h->max_k || h->state == State::kEmpty) h->shape_valid = false;
+  h->digest = dg;
+  h->h_off.swap(off);
+  h->h_block.swap(block);
+  h->n_layers = n_layers;
+  h->n_blocks = n_blocks;
+  h->max_k = max_k;
+  h->kcap = kcap_for(max_k);
+  h->frag = frag_dev;
+  h->last_layers.assign(layers, layers + n_layers);
+  h->last_had_expected = expected != nullptr;
+  if (expected) h->last_expected.assign(expected, expected + h->n_tiles);
+  h->work_valid = false;
+  if (!h->shape_valid) {
+    // fixed shapes skip the autotuner
+    auto c = candidates(h->cfg);
+    if (c.size() == 1) { h->shape = c[0]; h->shape_valid = true; }
+  }
+  if (h->shape_valid) {
+    s = build_work(h, h->shape);
+    if (s != DFB_OK) return s;
+  }
+  h->state = State::kReady;
+  return DFB_OK;
+}
+
+dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (h->state == State::kEmpty) return fail(h, DFB_ERR_STATE, "dfb_set_fragments must come first");
+  if (frame_flags & ~DFB_ACCUMULATE) return fail(h, DFB_ERR_INVALID_ARG, "unknown frame flag");
+  s = prepare_shape(h);
+  if (s != DFB_OK) return s;
+  uint32_t mode = display_mode(h->cfg);
+  if (h->cfg.flags & DFB_KEEP_FINISHED) mode |= dfb::kModeKeepFinished;
+  if (h->cfg.flags & DFB_KEEP_SORT_ORDER) mode |= dfb::kModeKeepOrder;
+  if (frame_flags & DFB_ACCUMULATE) {
+    s = ensure_accum(h);
+    if (s != DFB_OK) return s;
+    mode |= dfb::kModeAccumulate;
+    h->acc_n += 1;
+  }
+  const int slot = h->ring_pos;
+  if (h->timing) {
+    if (!h->ev0[slot]) {
+      DFB_HIP(h, hipEventCreate(&h->ev0[slot]));
+      DFB_HIP(h, hipEventCreate(&h->ev1[slot]));
+    }
+    if (h->pending[slot]) {
+      s = harvest(h, slot);
+      if (s != DFB_OK) return s;
+    }
+    DFB_HIP(h, hipEventRecord(h->ev0[slot], h->stream));
+  }
+  s = launch_frame(h, mode, true);
+  if (s != DFB_OK) return s;
+  if (h->timing) {
+    DFB_HIP(h, hipEventRecord(h->ev1[slot], h->stream));
+    h->pending[slot] = true;
+    h->ring_pos = (slot + 1) % dfb_ctx::kRing;
+  }
+  h->have_finished = (h->cfg.flags & DFB_KEEP_FINISHED) != 0;
+  h->state = State::kComposited;
+  return DFB_OK;
+}
+
+dfb_status dfb_accumulate(dfb_handle h) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (h->state != State::kComposited || !h->have_finished)
+    return fail(h, DFB_ERR_STATE, "dfb_accumulate needs a composited frame with DFB_KEEP_FINISHED");
+  s = ensure_accum(h);
+  if (s != DFB_OK) return s;
+  h->acc_n += 1;
+  dfb::AccumArgs a{};
+  a.finished = h->finished;
+  a.accum = h->accum;
+  a.m2 = h->m2;
+  a.tile_var = h->tile_var;
+  a.final_out = h->final_out;
+  a.width = h->cfg.width;
+  a.height = h->cfg.height;
+  a.tiles_x = h->tiles_x;
+  a.n_tiles = h->n_tiles;
+  a.tile_w = h->cfg.tile_w;
+  a.tile_h = h->cfg.tile_h;
+  a.P = h->P;
+  a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
+  a.mode = display_mode(h->cfg);
+  a.n_acc = h->acc_n;
+  a.inv_n = 1.f / static_cast<float>(h->acc_n);
+  void* params[] = {&a};
+  DFB_HIP(h, hipLaunchKernel(dfb::accumulate_kernel(), dim3(h->n_tiles), dim3(256), params, 0, h->stream));
+  DFB_HIP(h, hipGetLastError());
+  h->have_finished = false;  // one accumulation per finished frame
+  return DFB_OK;
+}
+
+dfb_status dfb_reset_accumulation(dfb_handle h) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  h->acc_n = 0;
+  return DFB_OK;
+}
+
+int64_t dfb_buffer_bytes(dfb_handle h, dfb_buffer which, int32_t first, int32_t n) {
+  if (!h || first < 0 || n < 0 || first + n > h->n_tiles) return 0;
+  const int64_t P = h->P;
+  switch (which) {
+    case DFB_BUF_FINAL:
+      if (!h->final_out) return 0;
+      return n * P * (h->cfg.format == DFB_FMT_RGBA8 ? 4 : 16);
+    case DFB_BUF_FINISHED_F32: return h->finished ? n * P * 16 : 0;
+    case DFB_BUF_ACCUM_F32: return h->accum ? n * P * 16 : 0;
+    case DFB_BUF_M2_F32: return h->m2 ? n * P * 12 : 0;
+    case DFB_BUF_TILE_VARIANCE: return n * 4;
+    case DFB_BUF_SORT_ORDER:
+      if (!h->order || h->h_off.empty()) return 0;
+      return (static_cast<int64_t>(h->h_off[first + n]) - h->h_off[first]) * P * 2;
+  }
+  return 0;
+}
+
+dfb_status dfb_read_tiles(dfb_handle h, dfb_buffer which, int32_t first, int32_t n, void* dst, int dst_is_device) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (!dst || first < 0 || n < 0 || first + n > h->n_tiles) return fail(h, DFB_ERR_INVALID_ARG, "bad tile range or dst");
+  if (h->state != State::kComposited) return fail(h, DFB_ERR_STATE, "no composited frame to read");
+  const int64_t bytes = dfb_buffer_bytes(h, which, first, n);
+  if (bytes == 0 && n > 0) return fail(h, DFB_ERR_STATE, "buffer not available (flag or format not enabled)");
+  const int64_t P = h->P;
+  const char* src = nullptr;
+  switch (which) {
+    case DFB_BUF_FINAL: src = static_cast<const char*>(h->final_out) + first * P * (h->cfg.format == DFB_FMT_RGBA8 ? 4 : 16); break;
+    case DFB_BUF_FINISHED_F32: src = reinterpret_cast<const char*>(h->finished) + first * P * 16; break;
+    case DFB_BUF_ACCUM_F32: src = reinterpret_cast<const char*>(h->accum) + first * P * 16; break;
+    case DFB_BUF_M2_F32: src = reinterpret_cast<const char*>(h->m2) + first * P * 12; break;
+    case DFB_BUF_TILE_VARIANCE: src = reinterpret_cast<const char*>(h->tile_var) + first * 4; break;
+    case DFB_BUF_SORT_ORDER: src = reinterpret_cast<const char*>(h->order) + static_cast<int64_t>(h->h_off[first]) * P * 2; break;
+    default: return fail(h, DFB_ERR_INVALID_ARG, "unknown buffer");
+  }
+  if (bytes > 0)
+    DFB_HIP(h, hipMemcpyAsync(dst, src, static_cast<size_t>(bytes),
+                              dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  return DFB_OK;
+}
+
+dfb_status dfb_synchronize(dfb_handle h) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  DFB_HIP(h, hipStreamSynchronize(h->stream));
+  return DFB_OK;
+}
+
+dfb_status dfb_get_info(dfb_handle h, dfb_info* out) {
+  if (!h || !out) return DFB_ERR_INVALID_ARG;
+  out->n_tiles = h->n_tiles;
+  out->tiles_x = h->tiles_x;
+  out->tiles_y = h->tiles_y;
+  out->n_layers = h->n_layers < 0 ? 0 : h->n_layers;
+  out->max_layers_per_tile = h->max_k;
+  out->work_w = h->shape.work_w;
+  out->work_h = h->shape.work_h;
+  out->waves_per_tile = h->shape.waves;
+  out->accumulation_id = h->acc_n;
+  out->grid_size = h->grid;
+  out->n_fragments = static_cast<int64_t>(out->n_layers) * h->P;
+  return DFB_OK;
+}
+
+dfb_status dfb_set_timing(dfb_handle h, int enable) {
+  if (!h) return DFB_ERR_INVALID_ARG;
+  h->timing = enable != 0;
+  h->time_sum_ms = 0.0;
+  h->time_n = 0;
+  for (int i = 0; i < dfb_ctx::kRing; ++i) h->pending[i] = false;
+  return DFB_OK;
+}
+
+double dfb_kernel_ms(dfb_handle h) {
+  if (!h) return -1.0;
+  for (int i = 0; i < dfb_ctx::kRing; ++i)
+    if (h->pending[i] && harvest(h, i) != DFB_OK) return -1.0;
+  return h->time_n ? h->time_sum_ms / h->time_n : -1.0;
+}
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+"""GPU parity of the compositing path (through the C ABI) against the FP64
+oracle: sort order bit-exact, colour within 1e-5 of the per-pixel magnitude
+sum, RGBA8 within 1 LSB, accumulation / variance against the oracle's
+Welford.  Inputs come from the seeded generators in ``workloads``."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_helpers import (assert_colour, assert_rgba8, order_as_sources, stream_handle, torch_dev,
+                         upload)
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def dfb():
+    torch_dev()
+    import paper_2305_07083_amd as m
+    m.load()
+    return m
+
+
+def composite_gpu(dfb, f, *, work=64, waves=4, bg=(0, 0, 0, 0), flags=None, fmt=None, dtype=None,
+                  gamma=1.0, layers=None):
+    flags = (dfb.DFB_KEEP_FINISHED | dfb.DFB_KEEP_SORT_ORDER) if flags is None else flags
+    fmt = dfb.DFB_FMT_RGBA8 if fmt is None else fmt
+    dt = dfb.DFB_F16 if f.frag.dtype == np.float16 else dfb.DFB_F32
+    cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=work, waves=waves, dtype=dt,
+                          fmt=fmt, background=bg, gamma=gamma, flags=flags)
+    frag = upload(f.frag)
+    out = {}
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        c.set_fragments(frag, f.frag.shape[0], f.layers if layers is None else layers, f.expected)
+        c.composite()
+        if flags & dfb.DFB_KEEP_FINISHED:
+            out["finished"] = c.read(dfb.DFB_BUF_FINISHED_F32)
+        if flags & dfb.DFB_KEEP_SORT_ORDER:
+            out["order"] = c.read(dfb.DFB_BUF_SORT_ORDER)
+        if fmt != dfb.DFB_FMT_NONE:
+            out["final"] = c.read(dfb.DFB_BUF_FINAL)
+        out["info"] = c.info()
+    return out
+
+
+def check_frame(dfb, f, bg=(0, 0, 0, 0), **kw):
+    g = composite_gpu(dfb, f, bg=bg, **kw)
+    ref = oracle.composite(f.frag, f.layers, f.width, f.height, f.tile_w, f.tile_h,
+                           expected=f.expected, background=bg, want_mag=True, want_order=True)
+    assert_colour(g["finished"], ref["rgba"], ref["mag"], f.name)
+    assert_rgba8(g["final"], ref["rgba"], what=f.name)
+    counts = f.expected
+    tiles = np.arange(f.n_tiles)
+    gord = order_as_sources(g["order"], f.layers, tiles, counts, f.P)
+    for t in tiles:
+        K = int(counts[t])
+        assert np.array_equal(gord[t], ref["order"][t, :, :K]), "sort order differs in tile %d" % t
+    return g, ref
+
+
+# ----------------------------------------------------------------- frames
+def test_worked_example_bit_exact(dfb):
+    ex = json.load(open(os.path.join(HERE, "golden", "worked_example.json")))
+    K = len(ex["fragments"])
+    frag = np.zeros((K, 5, 1), dtype=np.float32)
+    layers = np.empty(K, dtype=workloads.LAYER_DTYPE)
+    for l, fr in enumerate(ex["fragments"]):
+        frag[l, :, 0] = (fr["colour"], fr["colour"], fr["colour"], fr["alpha"], fr["depth"])
+        layers[l] = (0, fr["source_id"], l)
+    f = workloads.Frame(1, 1, 1, 1, frag, layers, np.array([K], np.int32), name="worked example")
+    for bg in [(0, 0, 0, 0), (1, 0.5, 0.25, 1)]:
+        g = composite_gpu(dfb, f, work=0, waves=1, bg=bg)
+        assert list(g["finished"][0, 0]) == ex["final_rgba"]
+        assert list(g["final"][0, 0]) == ex["final_rgba8"]
+        srcs = order_as_sources(g["order"], layers, [0], [K], 1)[0][0]
+        assert list(srcs) == ex["sorted_source_ids"]
+
+
+def test_uniform_256_four_ranks(dfb):
+    check_frame(dfb, workloads.c1(), bg=(0.1, 0.2, 0.3, 0.4))
+
+
+@pytest.mark.parametrize("work,waves", [(32, 1), (32, 2), (64, 1), (64, 4)])
+def test_launch_shapes_give_identical_results(dfb, work, waves):
+    f = workloads.brick_frame(256, 256, (4, 4, 4), 64, seed=1)
+    base = composite_gpu(dfb, f, work=64, waves=4)
+    g = composite_gpu(dfb, f, work=work, waves=waves)
+    assert np.array_equal(base["finished"], g["finished"])
+    assert np.array_equal(base["order"], g["order"])
+    assert np.array_equal(base["final"], g["final"])
+
+
+def test_bricks_512_and_arrival_order_invariance(dfb):
+    f = workloads.brick_frame(512, 512, (4, 4, 4), 64, seed=2)
+    g, _ = check_frame(dfb, f, bg=(0.0, 0.0, 0.2, 0.5))
+    rng = np.random.default_rng(9)
+    g2 = composite_gpu(dfb, f, bg=(0.0, 0.0, 0.2, 0.5), layers=f.layers[rng.permutation(len(f.layers))])
+    assert np.array_equal(g["finished"], g2["finished"])
+    assert np.array_equal(g["order"], g2["order"])
+
+
+def test_ragged_frame_edges(dfb):
+    f = workloads.brick_frame(200, 136, (4, 4, 4), 64, seed=4, name="200x136 ragged")
+    check_frame(dfb, f, work=32, waves=2)
+
+
+def test_small_tiles_ragged_rows(dfb):
+    f = workloads.uniform_frame(96, 80, 32, ranks=5, seed=8)
+    f = workloads.Frame(96, 80, 32, 32, f.frag, f.layers, f.expected, f.covered, "96x80 tiles 32")
+    check_frame(dfb, f, work=32, waves=1)
+
+
+def test_fp16_planes(dfb):
+    f = workloads.brick_frame(512, 128, (8, 8, 4), 64, seed=5, name="512x128 8x8x4 fp16").as_dtype(np.float16)
+    check_frame(dfb, f)
+
+
+@pytest.mark.parametrize("ranks", [9, 17, 31, 32, 33, 64, 100, 257])
+def test_layer_counts_across_register_and_lds_paths(dfb, ranks):
+    f = workloads.uniform_frame(128, 64, 64, ranks=ranks, seed=ranks)
+    check_frame(dfb, f, bg=(0.3, 0.2, 0.1, 0.9))
+
+
+@pytest.mark.parametrize("ranks", [6, 40])
+def test_depth_ties_break_by_source(dfb, ranks):
+    f = workloads.uniform_frame(64, 64, 64, ranks=ranks, seed=3)
+    frag = f.frag.copy()
+    frag[:, 4, :] = np.round(frag[:, 4, :] * 4) / 4   # five depth values: many ties
+    check_frame(dfb, workloads.Frame(64, 64, 64, 64, frag, f.layers, f.expected, None, "ties"))
+
+
+def test_special_depth_values(dfb):
+    f = workloads.uniform_frame(64, 64, 64, ranks=12, seed=12)
+    frag = f.frag.copy()
+    rng = np.random.default_rng(0)
+    special = np.array([np.nan, 0.0, -0.0, np.inf, -np.inf, 1e-40, -1e-40, -1.0], dtype=np.float32)
+    mask = rng.random(frag[:, 4, :].shape) < 0.3
+    frag[:, 4, :][mask] = special[rng.integers(0, len(special), int(mask.sum()))]
+    check_frame(dfb, workloads.Frame(64, 64, 64, 64, frag, f.layers, f.expected, None, "special depths"))
+
+
+def test_empty_tiles_show_background(dfb):
+    f = workloads.brick_frame(256, 256, (4, 4, 4), 64, seed=6)
+    keep = f.layers["tile_id"] % 3 != 0
+    layers = f.layers[keep]
+    expected = np.zeros(f.n_tiles, np.int32)
+    np.add.at(expected, layers["tile_id"], 1)
+    g = workloads.Frame(f.width, f.height, 64, 64, f.frag, layers, expected, None, "holes")
+    _, ref = check_frame(dfb, g, bg=(0.25, 0.5, 0.75, 1.0))
+    for t in range(f.n_tiles):
+        if expected[t] == 0:
+            assert np.all(ref["rgba"][t] == [0.25, 0.5, 0.75, 1.0])
+
+
+def test_opaque_and_transparent_fragments(dfb):
+    f = workloads.uniform_frame(64, 64, 64, ranks=7, seed=21)
+    frag = f.frag.copy()
+    frag[2, 3, :2048] = 1.0      # an opaque layer over half the tile
+    frag[4, :4, 1000:3000] = 0.0  # an empty layer over another part
+    check_frame(dfb, workloads.Frame(64, 64, 64, 64, frag, f.layers, f.expected, None, "opaque"))
+
+
+def test_gamma_and_float_formats(dfb):
+    f = workloads.c1()
+    g = composite_gpu(dfb, f, gamma=2.2)
+    ref = oracle.composite(f.frag, f.layers, 256, 256, 64, 64)
+    assert_rgba8(g["final"], ref["rgba"], gamma=2.2, what="gamma 2.2")
+    g = composite_gpu(dfb, f, fmt=dfb.DFB_FMT_RGBAF32)
+    assert np.array_equal(g["final"], g["finished"])
+    g = composite_gpu(dfb, f, fmt=dfb.DFB_FMT_NONE)
+    assert "final" not in g
+
+
+# -------------------------------------------------------------- accumulation
+def run_progressive(dfb, f, sigma, frames, seed, *, fused=True, dtype=np.float32, work=64, waves=4):
+    dt = dfb.DFB_F16 if dtype == np.float16 else dfb.DFB_F32
+    cfg = dfb.make_config(f.width, f.height, 64, work=work, waves=waves, dtype=dt,
+                          flags=dfb.DFB_KEEP_FINISHED)
+    mu = np.zeros((f.n_tiles, f.P, 4))
+    m2 = np.zeros((f.n_tiles, f.P, 3))
+    tiles = np.arange(f.n_tiles)
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        for k in range(frames):
+            x = workloads.noisy_colour(f, sigma, seed, k, dtype=dtype)
+            c.set_fragments(upload(x), x.shape[0], f.layers, f.expected)
+            if fused:
+                c.composite(accumulate=True)
+            else:
+                c.composite()
+                c.accumulate()
+            ref = oracle.composite(x, f.layers, f.width, f.height, 64, 64, want_mag=True)
+            oracle.accumulate(mu, m2, ref["rgba"], k + 1)
+            g_mu = c.read(dfb.DFB_BUF_ACCUM_F32)
+            g_m2 = c.read(dfb.DFB_BUF_M2_F32).transpose(0, 2, 1)
+            g_v = c.read(dfb.DFB_BUF_TILE_VARIANCE)
+            g_8 = c.read(dfb.DFB_BUF_FINAL)
+            assert c.info().accumulation_id == k + 1
+            # mean: within 1e-5 of the magnitude scale (noise makes colours cancel)
+            scale = np.maximum(ref["mag"], np.abs(mu)) + 1e-6
+            assert np.all(np.abs(g_mu - mu) <= 1e-5 * scale * 4), "mean differs at frame %d" % k
+            assert_rgba8(g_8, mu, what="frame %d" % k)
+            v_ref = oracle.tile_variance(m2, tiles, f.width, f.height, 64, 64, k + 1)
+            if k == 0:
+                assert np.all(np.isinf(g_v))
+                assert np.all(g_m2 == 0)
+            else:
+                np.testing.assert_allclose(g_v, v_ref, rtol=1e-4)
+                np.testing.assert_allclose(g_m2, m2, rtol=2e-3, atol=1e-7 * (k + 1))
+    return mu
+
+
+def test_progressive_fused_fp32(dfb):
+    f = workloads.brick_frame(512, 128, (8, 8, 4), 64, seed=7)
+    run_progressive(dfb, f, 0.1, 16, seed=100)
+
+
+def test_progressive_fused_fp16(dfb):
+    f = workloads.brick_frame(512, 128, (8, 8, 4), 64, seed=7)
+    run_progressive(dfb, f, 0.1, 16, seed=101, dtype=np.float16)
+
+
+def test_progressive_with_sub_tile_units(dfb):
+    f = workloads.brick_frame(256, 192, (4, 4, 4), 64, seed=9)
+    run_progressive(dfb, f, 0.1, 5, seed=102, work=32, waves=1)
+
+
+def test_unfused_accumulate_matches_fused(dfb):
+    f = workloads.brick_frame(256, 256, (4, 4, 4), 64, seed=10)
+    res = []
+    for fused in (True, False):
+        cfg = dfb.make_config(256, 256, 64, work=64, waves=2, flags=dfb.DFB_KEEP_FINISHED)
+        with dfb.Compositor(cfg, stream_handle()) as c:
+            for k in range(4):
+                x = workloads.noisy_colour(f, 0.1, 5, k)
+                c.set_fragments(upload(x), x.shape[0], f.layers, f.expected)
+                if fused:
+                    c.composite(accumulate=True)
+                else:
+                    c.composite()
+                    c.accumulate()
+            res.append((c.read(dfb.DFB_BUF_ACCUM_F32), c.read(dfb.DFB_BUF_M2_F32),
+                        c.read(dfb.DFB_BUF_TILE_VARIANCE), c.read(dfb.DFB_BUF_FINAL)))
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_reset_restarts_the_mean(dfb):
+    f = workloads.c1()
+    cfg = dfb.make_config(256, 256, 64, work=64, waves=4, flags=dfb.DFB_KEEP_FINISHED)
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        c.set_fragments(upload(f.frag), f.frag.shape[0], f.layers, f.expected)
+        c.composite(accumulate=True)
+        c.composite(accumulate=True)
+        c.reset()
+        c.composite(accumulate=True)
+        assert c.info().accumulation_id == 1
+        assert np.array_equal(c.read(dfb.DFB_BUF_ACCUM_F32), c.read(dfb.DFB_BUF_FINISHED_F32))
+        assert np.all(np.isinf(c.read(dfb.DFB_BUF_TILE_VARIANCE)))
+
+
+# ------------------------------------------------------------------ errors
+def test_errors_are_reported(dfb):
+    f = workloads.c1()
+    frag = upload(f.frag)
+    cfg = dfb.make_config(256, 256, 64, work=64, waves=4, flags=dfb.DFB_VALIDATE)
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        with pytest.raises(dfb.DfbError) as e:
+            c.composite()
+        assert e.value.status == dfb.DFB_ERR_STATE
+        with pytest.raises(dfb.DfbError) as e:
+            c.set_fragments(frag, f.frag.shape[0], f.layers[1:], f.expected)
+        assert e.value.status == dfb.DFB_ERR_INCOMPLETE
+        dup = f.layers.copy()
+        dup[1] = (dup[0]["tile_id"], dup[0]["source_id"], dup[1]["block"])
+        with pytest.raises(dfb.DfbError) as e:
+            c.set_fragments(frag, f.frag.shape[0], dup)
+        assert e.value.status == dfb.DFB_ERR_DUPLICATE
+        bad = f.layers.copy()
+        bad[3]["block"] = f.frag.shape[0]
+        with pytest.raises(dfb.DfbError) as e:
+            c.set_fragments(frag, f.frag.shape[0], bad)
+        assert e.value.status == dfb.DFB_ERR_INVALID_ARG
+        nan = f.frag.copy()
+        nan[5, 4, 77] = np.nan
+        with pytest.raises(dfb.DfbError) as e:
+            c.set_fragments(upload(nan), f.frag.shape[0], f.layers, f.expected)
+        assert e.value.status == dfb.DFB_ERR_BAD_VALUE
+        with pytest.raises(dfb.DfbError) as e:
+            c.accumulate()
+        assert e.value.status == dfb.DFB_ERR_STATE
+        # the handle still works after rejected input
+        c.set_fragments(frag, f.frag.shape[0], f.layers, f.expected)
+        c.composite()
+        assert c.read(dfb.DFB_BUF_FINAL).shape == (16, 4096, 4)
