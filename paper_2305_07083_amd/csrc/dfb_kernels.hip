@@ -342,21 +342,71 @@ __device__ __forceinline__ float variance_of_mean(float sum, int inside_px, int 
                 static_cast<float>(n - 1));
 }
 
+// Next work unit: lane 0 of the calling wave takes a ticket, the wave agrees
+// on it.  Call from wave-uniform code only.
+__device__ __forceinline__ int pop_unit(const FrameArgs& a) {
+  unsigned long long v = 0;
+  if (__lane_id() == 0) v = atomicAdd(a.queue, 1ull);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  const unsigned long long d = ((static_cast<unsigned long long>(hi) << 32) | lo) - a.q_base;
+  return d < static_cast<unsigned long long>(a.n_work) ? static_cast<int>(d) : a.n_work;
+}
+
+// Per-tile variance of the mean once a unit's M2 sum is known.  Runs on all
+// 64 lanes of one wave (wave-uniform control flow; lane-0-only work is a
+// single store or atomic).  Units of a tile leave partial sums; the one that
+// completes the tile adds them in unit order.
+__device__ __forceinline__ void finish_variance(const FrameArgs& a, const Unit& u, int w,
+                                                const float* s_red, int n_waves) {
+  float sum = 0.f;
+  for (int i = 0; i < 4; ++i)
+    if (i < n_waves) sum += s_red[i];
+  const int wx = a.width - u.x0, wy = a.height - u.y0;
+  const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
+  const bool lane0 = __lane_id() == 0;
+  if (a.subs_per_tile == 1) {
+    if (lane0) a.tile_var[u.t] = variance_of_mean(sum, inside, a.n_acc);
+    return;
+  }
+  if (lane0) __hip_atomic_store(a.var_partial + w, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
+  uint32_t old = 0;
+  if (lane0) old = atomicAdd(a.tile_done + u.t, 1u);
+  old = __builtin_amdgcn_readfirstlane(old);
+  if (old != a.done_base + static_cast<uint32_t>(a.subs_per_tile) - 1u) return;
+  __threadfence();
+  float tot = 0.f;
+  for (int base = 0; base < a.subs_per_tile; base += 64) {
+    const int i = base + static_cast<int>(__lane_id());
+    float p = 0.f;
+    if (i < a.subs_per_tile)
+      p = __hip_atomic_load(a.var_partial + u.t * a.subs_per_tile + i, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    tot += wave_sum(p);
+  }
+  if (lane0) a.tile_var[u.t] = variance_of_mean(tot, inside, a.n_acc);
+}
+
+// The persistent frame kernel.  Control flow that contains barriers is
+// uniform across the workgroup; code that only lane 0 runs is a single
+// store or atomic, so no lane can be left behind in a loop that holds a
+// barrier.
 template <typename FT, int KCAP>
 __global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
   __shared__ float s_red[4];
   const int tid = threadIdx.x;
-  for (;;) {
-    if (tid == 0) {
-      const unsigned long long v = atomicAdd(a.queue, 1ull) - a.q_base;
-      s_item = v < static_cast<unsigned long long>(a.n_work) ? static_cast<int>(v) : a.n_work;
-    }
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (it >= a.n_work) break;
+  const int n_waves = static_cast<int>(blockDim.x >> 6);
+  const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < 64;  // uniform per wave
+  if (wave0) {
+    const int v = pop_unit(a);
+    if (__lane_id() == 0) s_item = v;
+  }
+  __syncthreads();
+  int it = __builtin_amdgcn_readfirstlane(s_item);
+  while (it < a.n_work) {
     const int w = a.work_list[it];
     Unit u;
     u.t = w / a.subs_per_tile;
@@ -382,33 +432,19 @@ __global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
     else if (KCAP >= 32 && K <= 24) vs = unit_reg<FT, (KCAP >= 32 ? 24 : 1)>(a, u, blk, K, off, wl);
     else if (KCAP >= 32 && K <= 32) vs = unit_reg<FT, (KCAP >= 32 ? 32 : 1)>(a, u, blk, K, off, wl);
     else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
-    if (a.mode & kModeAccumulate) {
-      // per-tile variance of the mean: fixed-order reductions only
-      vs = wave_sum(vs);
+    const bool acc = (a.mode & kModeAccumulate) != 0;
+    if (acc) {
+      vs = wave_sum(vs);  // fixed-order reductions only: deterministic
       if ((tid & 63) == 0) s_red[tid >> 6] = vs;
-      __syncthreads();
-      if (tid == 0) {
-        float sum = 0.f;
-        for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) sum += s_red[i];
-        const int wx = a.width - u.x0, wy = a.height - u.y0;
-        const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
-        if (a.subs_per_tile == 1) {
-          a.tile_var[u.t] = variance_of_mean(sum, inside, a.n_acc);
-        } else {
-          __hip_atomic_store(a.var_partial + w, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __threadfence();
-          const uint32_t old = atomicAdd(a.tile_done + u.t, 1u);
-          if (old == a.done_base + static_cast<uint32_t>(a.subs_per_tile) - 1u) {
-            __threadfence();
-            float tot = 0.f;
-            for (int i = 0; i < a.subs_per_tile; ++i)
-              tot += __hip_atomic_load(a.var_partial + u.t * a.subs_per_tile + i,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            a.tile_var[u.t] = variance_of_mean(tot, inside, a.n_acc);
-          }
-        }
-      }
     }
+    __syncthreads();  // s_red complete; every lane has read s_item
+    if (wave0) {
+      if (acc) finish_variance(a, u, w, s_red, n_waves);
+      const int v = pop_unit(a);
+      if (__lane_id() == 0) s_item = v;
+    }
+    __syncthreads();
+    it = __builtin_amdgcn_readfirstlane(s_item);
   }
 }
 
@@ -430,12 +466,14 @@ __global__ void __launch_bounds__(256) accumulate_kernel_t(AccumArgs a) {
   vs = wave_sum(vs);
   if ((tid & 63) == 0) s_red[tid >> 6] = vs;
   __syncthreads();
-  if (tid == 0) {
+  if (__builtin_amdgcn_readfirstlane(tid) < 64) {
+    const int n_waves = static_cast<int>(blockDim.x >> 6);
     float sum = 0.f;
-    for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) sum += s_red[i];
+    for (int i = 0; i < 4; ++i)
+      if (i < n_waves) sum += s_red[i];
     const int wx = a.width - x0, wy = a.height - y0;
     const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
-    a.tile_var[t] = variance_of_mean(sum, inside, a.n_acc);
+    if (__lane_id() == 0) a.tile_var[t] = variance_of_mean(sum, inside, a.n_acc);
   }
 }
 
