@@ -1,0 +1,163 @@
+"""Throughput of the per-tile sort-last compositing path on one MI355X.
+
+One step = one frame of the 2048x2048, 64x64-tile, 4x4x4-brick (64 ranks)
+fragment set through the whole path in one persistent graph launch: per-pixel
+depth sort, front-to-back over with the background, Welford accumulation,
+per-tile variance and RGBA8 tonemapping.  Inputs are resident in HBM before
+the timed region; four copies rotate so the 555 MB working set cannot stay in
+the 256 MB last-level cache.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3f16|c1] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "composited fragments/s + HBM GB/s % peak; frames-to-PSNR denoised vs plain"
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3f16"])
+    ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--plain", action="store_true", help="composite only (no accumulation)")
+    return ap.parse_args()
+
+
+def make_frame(name):
+    import numpy as np
+    import workloads
+    if name == "c1":
+        f = workloads.c1()
+        desc = "256x256 frame, 64x64 tiles, 4 ranks on every tile, fp32"
+    elif name == "c2":
+        f = workloads.c2()
+        desc = "2048x2048 frame, 64x64 tiles, 4x4x4 bricks (64 ranks), fp32"
+    else:
+        f = workloads.c3()
+        desc = "4096x1024 frame, 64x64 tiles, 8x8x4 bricks (256 ranks), fp32"
+        if name == "c3f16":
+            f = f.as_dtype(np.float16)
+            desc = desc.replace("fp32", "fp16")
+    return f, desc
+
+
+def cpu_baseline(f, accumulate, budget_s=12.0):
+    """The FP64 oracle as it stands, on whole frames, repeated for about
+    ``budget_s`` seconds on this host's cores."""
+    import numpy as np
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    mu = np.zeros((f.n_tiles, f.P, 4))
+    m2 = np.zeros((f.n_tiles, f.P, 3))
+    frames = 0
+    t0 = time.perf_counter()
+    while True:
+        r = oracle.composite(f.frag, f.layers, f.width, f.height, f.tile_w, f.tile_h,
+                             expected=f.expected, threads=threads)
+        if accumulate:
+            oracle.accumulate(mu, m2, r["rgba"], frames + 1)
+            oracle.tile_variance(m2, np.arange(f.n_tiles), f.width, f.height, f.tile_w, f.tile_h, frames + 1)
+            oracle.tonemap(mu)
+        else:
+            oracle.tonemap(r["rgba"])
+        frames += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
+    return {"value": f.n_fragments * frames / dt, "unit": "fragments/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d whole frames of the same fragment set (%d fragments each), %s, %.1f s"
+                      % (frames, f.n_fragments,
+                         "composite+accumulate+variance+tonemap" if accumulate else "composite+tonemap", dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+              "(the per-tile exchange between GPUs is not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2305_07083_amd as dfb
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dfb.load()
+    f, desc = make_frame(args.workload)
+    dev = torch.device("cuda:0")
+    copies = [torch.from_numpy(f.frag).to(dev) for _ in range(max(1, args.copies))]
+    torch.cuda.synchronize()
+    f16 = f.frag.dtype == np.float16
+    cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=0, waves=0,
+                          dtype=dfb.DFB_F16 if f16 else dfb.DFB_F32, fmt=dfb.DFB_FMT_RGBA8)
+    stream = torch.cuda.current_stream().cuda_stream
+    accumulate = not args.plain
+    n_blocks = f.frag.shape[0]
+    with dfb.Compositor(cfg, stream) as c:
+        c.set_fragments(copies[0], n_blocks, f.layers, f.expected)
+        c.composite(accumulate=False)     # first frame of a new layout: autotunes the launch shape
+        torch.cuda.synchronize()
+        for i in range(args.warmup):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite(accumulate=accumulate)
+        torch.cuda.synchronize()
+        dfb.dfb_set_timing(c.h, True)
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite(accumulate=accumulate)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kernel_ms = dfb.dfb_kernel_ms(c.h)
+        info = c.info()
+    frag_bytes = 10 if f16 else 20
+    px = f.n_tiles * f.P
+    per_px = 4 + (56 if accumulate else 0)       # RGBA8 out (+ mean and M2 read and written)
+    alg_bytes = f.n_fragments * frag_bytes + px * per_px + f.n_tiles * 4 + len(f.layers) * 8
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    ms_per_step = wall / args.steps * 1e3
+    value = f.n_fragments * args.steps / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "fragments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16" if f16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": desc + (", composite + accumulate + per-tile variance + RGBA8" if accumulate
+                                       else ", composite + RGBA8"),
+                   "fragments_per_frame": f.n_fragments, "layers": len(f.layers),
+                   "max_layers_per_tile": int(f.expected.max()),
+                   "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
+                   "grid": info.grid_size},
+        "kernel_ms": kernel_ms,
+        "hbm_gbps_algorithmic": achieved,
+        "hbm_frac_of_peak": achieved / HBM_PEAK_GBPS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(f, accumulate)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

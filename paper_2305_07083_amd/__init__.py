@@ -136,7 +136,10 @@ def make_config(width, height, tile_w=64, tile_h=None, *, work=0, waves=0, dtype
 
 
 def as_layers(layers):
-    """numpy record array with fields tile_id, source_id, block -> C layout."""
+    """numpy record array with fields tile_id, source_id, block -> C layout
+    (returned as is when it already is one)."""
+    if isinstance(layers, np.ndarray) and layers.dtype == LAYER_DTYPE and layers.flags.c_contiguous:
+        return layers
     out = np.empty(len(layers), dtype=LAYER_DTYPE)
     for f in LAYER_DTYPE.names:
         out[f] = np.asarray(layers[f])

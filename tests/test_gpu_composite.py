@@ -244,8 +244,10 @@ def test_unfused_accumulate_matches_fused(dfb):
                     c.accumulate()
             res.append((c.read(dfb.DFB_BUF_ACCUM_F32), c.read(dfb.DFB_BUF_M2_F32),
                         c.read(dfb.DFB_BUF_TILE_VARIANCE), c.read(dfb.DFB_BUF_FINAL)))
-    for a, b in zip(*res):
-        assert np.array_equal(a, b)
+    (mu_a, m2_a, v_a, f_a), (mu_b, m2_b, v_b, f_b) = res
+    assert np.array_equal(mu_a, mu_b) and np.array_equal(m2_a, m2_b) and np.array_equal(f_a, f_b)
+    # the per-tile sums run over a different reduction tree (workgroup sizes differ)
+    np.testing.assert_allclose(v_a, v_b, rtol=1e-6)
 
 
 def test_reset_restarts_the_mean(dfb):
