@@ -78,7 +78,7 @@ typedef struct {
                               are stored whole, pixels past the image edge are composited but
                               excluded from the variance. */
   int32_t work_w, work_h;  /* GPU scheduling unit inside a tile; must divide tile_w / tile_h.
-                              0,0 = autotune over {32,64,128}^2 (those that divide the tile). */
+                              0,0 = autotune over {16,32,64,128}^2 (those that divide the tile). */
   int32_t waves_per_tile;  /* 64-lane waves per work unit: 1, 2 or 4; 0 = autotune */
   int32_t frag_dtype;      /* dfb_dtype */
   int32_t format;          /* dfb_format */

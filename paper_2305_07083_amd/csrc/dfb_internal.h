@@ -24,21 +24,23 @@ enum ModeBits : uint32_t {
   kModeGamma = 32u,         // colour ^ (1/gamma) before quantising
 };
 
-// Everything one frame launch needs; passed by value (a graph node's
-// parameters are updated per frame).
+// Everything one frame launch needs besides the three read-only tables,
+// which are separate __restrict__ kernel arguments so that their uniform
+// reads become scalar loads:
+//   tile_off   [n_tiles + 1] CSR offsets into layer_off
+//   layer_off  [n_layers] element offset of each layer's block (block*5*P);
+//              per tile ordered by source id
+//   work_list  [n_work] work-unit ids, longest tile first
+// Passed by value (a graph node's parameters are updated per frame).
 struct FrameArgs {
   const void* frag;            // fragment blocks (caller's buffer)
-  const int32_t* tile_off;     // [n_tiles + 1] CSR offsets into layer_block
-  const int64_t* layer_block;  // [n_layers] block of each layer; per tile ordered by source id
-  const int32_t* work_list;    // [n_work] work-unit ids, longest tile first
   unsigned long long* queue;   // work-queue counter (monotonic across frames)
-  uint32_t* tile_done;         // [n_tiles] finished work units (monotonic across frames)
   unsigned long long q_base;   // queue value at this frame's start
-  uint32_t done_base;          // tile_done value at this frame's start
   int32_t n_work;
   int32_t width, height, tiles_x, n_tiles;
   int32_t tile_w, tile_h, P;
   int32_t work_w, work_h, subs_x, subs_per_tile, work_px;
+  int32_t work_shift;          // log2(work_w) if a power of two, else -1
   float bg[4];
   float inv_gamma;
   uint32_t mode;
@@ -48,7 +50,7 @@ struct FrameArgs {
   float* accum;                // [n_tiles][P][4]
   float* m2;                   // [n_tiles][3][P]
   float* tile_var;             // [n_tiles]
-  float* var_partial;          // [n_work]
+  float* var_partial;          // [n_work] M2 sum of each unit (accumulating frames)
   void* final_out;             // RGBA8 uint32[n_tiles][P] or float4[n_tiles][P]
   uint16_t* order;             // [n_layers][P]
 };
@@ -66,9 +68,15 @@ struct AccumArgs {
   float inv_n;
 };
 
+struct VarianceArgs {
+  const float* var_partial;    // [n_tiles * subs_per_tile]
+  float* tile_var;             // [n_tiles]
+  int32_t n_tiles, subs_per_tile, tiles_x, width, height, tile_w, tile_h, n_acc;
+};
+
 struct ValidateArgs {
   const void* frag;
-  const int64_t* layer_block;
+  const int64_t* layer_off;
   int32_t n_layers, P;
   uint32_t* bad;   // set to 1 if a NaN depth is seen
 };
@@ -77,6 +85,7 @@ struct ValidateArgs {
 // dtype: 0 f32, 1 f16.  kcap: 8, 16 or 32 (layers handled in registers).
 const void* frame_kernel(int dtype, int kcap);
 const void* accumulate_kernel();
+const void* tile_variance_kernel();
 const void* validate_kernel(int dtype);
 
 // Dynamic LDS bytes a frame launch needs.

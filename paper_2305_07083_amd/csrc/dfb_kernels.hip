@@ -27,15 +27,43 @@
 namespace dfb {
 namespace {
 
+// Fragment planes are read exactly once per frame: streaming (non-temporal)
+// loads keep them from displacing the outputs in L2.
+#ifndef DFB_NT_LOADS
+#define DFB_NT_LOADS 1
+#endif
+// Minimum waves per SIMD requested from the register allocator, per
+// register-sort capacity (0 = no request).
+#ifndef DFB_WAVES_K8
+#define DFB_WAVES_K8 0
+#endif
+#ifndef DFB_WAVES_K16
+#define DFB_WAVES_K16 0
+#endif
+#ifndef DFB_WAVES_K32
+#define DFB_WAVES_K32 0
+#endif
+
+// Plane loads: `base` is uniform across the wave (a layer's block start) and
+// `i` a 32-bit element offset inside the block, so each load is one
+// instruction with a scalar base address.
 template <typename FT>
-__device__ __forceinline__ float ldf(const void* base, size_t i);
+__device__ __forceinline__ float ldf(const FT* __restrict__ base, uint32_t i);
 template <>
-__device__ __forceinline__ float ldf<float>(const void* base, size_t i) {
-  return static_cast<const float*>(base)[i];
+__device__ __forceinline__ float ldf<float>(const float* __restrict__ base, uint32_t i) {
+#if DFB_NT_LOADS
+  return __builtin_nontemporal_load(base + i);
+#else
+  return base[i];
+#endif
 }
 template <>
-__device__ __forceinline__ float ldf<_Float16>(const void* base, size_t i) {
-  return static_cast<float>(static_cast<const _Float16*>(base)[i]);
+__device__ __forceinline__ float ldf<_Float16>(const _Float16* __restrict__ base, uint32_t i) {
+#if DFB_NT_LOADS
+  return static_cast<float>(__builtin_nontemporal_load(base + i));
+#else
+  return static_cast<float>(base[i]);
+#endif
 }
 
 // Order-preserving map of a depth to 32 bits: NaN above everything, -0 == +0.
@@ -109,7 +137,7 @@ struct Unit {
 };
 
 __device__ __forceinline__ int unit_pixel(const FrameArgs& a, const Unit& u, int q, bool& inside) {
-  const int qy = q / a.work_w;
+  const int qy = a.work_shift >= 0 ? (q >> a.work_shift) : q / a.work_w;
   const int qx = q - qy * a.work_w;
   const int ty = u.sy0 + qy, tx = u.sx0 + qx;
   inside = (u.x0 + tx < a.width) && (u.y0 + ty < a.height);
@@ -125,22 +153,89 @@ __device__ __forceinline__ float finish_px(const FrameArgs& a, const Unit& u, in
 }
 
 // ---------------------------------------------------------------- K <= 32
-// One lane per pixel.  wl points at this lane's column of a [KMAX][NT] LDS
-// array: the lane writes alpha of layer l to wl[l*NT], later overwrites it
-// with the transmittance in front of layer l.  No lane reads another lane's
+// One lane per pixel.  All five planes of the pixel's K fragments are loaded
+// up front (one memory round trip per pixel, 5K loads in flight); colours
+// stay in registers indexed by layer, so only the sorted walk needs dynamic
+// indexing: wl points at this lane's column of a [KMAX][NT] LDS array, the
+// lane writes alpha of layer l to wl[l*NT] and the walk overwrites it with
+// the transmittance in front of layer l.  No lane reads another lane's
 // column, so no barrier is needed.
 template <typename FT, int KMAX>
-__device__ __forceinline__ float4 composite_px(const FrameArgs& a, const int64_t* __restrict__ blk,
-                                               int K, int off, int p, float* __restrict__ wl,
-                                               int NT) {
-  const size_t P = static_cast<size_t>(a.P);
+__device__ __forceinline__ float4 composite_px_upfront(const FrameArgs& a,
+                                                       const int64_t* __restrict__ loff, int K,
+                                                       int off, int p, float* __restrict__ wl,
+                                                       int NT) {
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
+  const uint32_t up = static_cast<uint32_t>(p);
+  float dep[KMAX], alp[KMAX], cr[KMAX], cg[KMAX], cb[KMAX];
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l < K) {
+      const FT* __restrict__ b = frag + loff[l];
+      dep[l] = ldf<FT>(b, 4 * P + up);
+      alp[l] = ldf<FT>(b, 3 * P + up);
+      cr[l] = ldf<FT>(b, up);
+      cg[l] = ldf<FT>(b, P + up);
+      cb[l] = ldf<FT>(b, 2 * P + up);
+    }
+  }
   uint64_t key[KMAX];
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
     if (l < K) {
-      const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p;
-      const float d = ldf<FT>(a.frag, base + 4 * P);
-      const float al = ldf<FT>(a.frag, base + 3 * P);
+      key[l] = (static_cast<uint64_t>(depth_bits(dep[l])) << 32) | static_cast<uint32_t>(l);
+      wl[l * NT] = alp[l];
+    } else {
+      key[l] = ~0ull;
+    }
+  }
+  sort_network<KMAX>(key);
+  float T = 1.f, A = 0.f;
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) {
+    if (i < K) {
+      const int l = static_cast<int>(static_cast<uint32_t>(key[i]));
+      const float al = wl[l * NT];
+      wl[l * NT] = T;
+      A = fmaf(T, al, A);
+      T = T * (1.f - al);
+      if (a.mode & kModeKeepOrder)
+        a.order[static_cast<size_t>(off + i) * P + p] = static_cast<uint16_t>(l);
+    }
+  }
+  float R = 0.f, G = 0.f, B = 0.f;
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l < K) {
+      const float w = wl[l * NT];
+      R = fmaf(w, cr[l], R);
+      G = fmaf(w, cg[l], G);
+      B = fmaf(w, cb[l], B);
+    }
+  }
+  return make_float4(fmaf(T, a.bg[0], R), fmaf(T, a.bg[1], G), fmaf(T, a.bg[2], B),
+                     fmaf(T, a.bg[3], A));
+}
+
+// Larger K: 5K values per lane no longer fit the register file next to the
+// keys, so depth and alpha are loaded first and the colours only after the
+// walk (two memory round trips per pixel, half the registers).
+template <typename FT, int KMAX>
+__device__ __forceinline__ float4 composite_px_two_phase(const FrameArgs& a,
+                                                         const int64_t* __restrict__ loff, int K,
+                                                         int off, int p, float* __restrict__ wl,
+                                                         int NT) {
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
+  const uint32_t up = static_cast<uint32_t>(p);
+  uint64_t key[KMAX];
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l) {
+    if (l < K) {
+      const FT* __restrict__ b = frag + loff[l];
+      const float d = ldf<FT>(b, 4 * P + up);
+      const float al = ldf<FT>(b, 3 * P + up);
       key[l] = (static_cast<uint64_t>(depth_bits(d)) << 32) | static_cast<uint32_t>(l);
       wl[l * NT] = al;
     } else {
@@ -165,11 +260,11 @@ __device__ __forceinline__ float4 composite_px(const FrameArgs& a, const int64_t
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
     if (l < K) {
-      const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p;
+      const FT* __restrict__ b = frag + loff[l];
       const float w = wl[l * NT];
-      R = fmaf(w, ldf<FT>(a.frag, base), R);
-      G = fmaf(w, ldf<FT>(a.frag, base + P), G);
-      B = fmaf(w, ldf<FT>(a.frag, base + 2 * P), B);
+      R = fmaf(w, ldf<FT>(b, up), R);
+      G = fmaf(w, ldf<FT>(b, P + up), G);
+      B = fmaf(w, ldf<FT>(b, 2 * P + up), B);
     }
   }
   return make_float4(fmaf(T, a.bg[0], R), fmaf(T, a.bg[1], G), fmaf(T, a.bg[2], B),
@@ -177,14 +272,22 @@ __device__ __forceinline__ float4 composite_px(const FrameArgs& a, const int64_t
 }
 
 template <typename FT, int KMAX>
-__device__ float unit_reg(const FrameArgs& a, const Unit& u, const int64_t* blk, int K, int off,
+__device__ __forceinline__ float4 composite_px(const FrameArgs& a, const int64_t* __restrict__ loff,
+                                               int K, int off, int p, float* __restrict__ wl,
+                                               int NT) {
+  if constexpr (KMAX <= 16) return composite_px_upfront<FT, KMAX>(a, loff, K, off, p, wl, NT);
+  else return composite_px_two_phase<FT, KMAX>(a, loff, K, off, p, wl, NT);
+}
+
+template <typename FT, int KMAX>
+__device__ float unit_reg(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff, int K, int off,
                           float* lds) {
   const int NT = blockDim.x, tid = threadIdx.x;
   float vs = 0.f;
   for (int q = tid; q < a.work_px; q += NT) {
     bool inside;
     const int p = unit_pixel(a, u, q, inside);
-    const float4 x = composite_px<FT, KMAX>(a, blk, K, off, p, lds + tid, NT);
+    const float4 x = composite_px<FT, KMAX>(a, loff, K, off, p, lds + tid, NT);
     vs += finish_px(a, u, p, inside, x);
   }
   return vs;
@@ -209,10 +312,11 @@ __device__ float unit_background(const FrameArgs& a, const Unit& u) {
 // pixel for the front-to-back walk (a product scan over S chunks) and for the
 // colour sums (a fixed-order reduction).
 template <typename FT>
-__device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ blk,
+__device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff,
                            int K, int off, char* lds) {
   const int NT = blockDim.x, tid = threadIdx.x;
-  const size_t P = static_cast<size_t>(a.P);
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
   int Kp = 64;
   while (Kp < K) Kp <<= 1;
   int G = kBigLdsBytes / (Kp * 12);
@@ -236,10 +340,10 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       if (l < K && q < a.work_px) {
         bool in;
         const int p = unit_pixel(a, u, q, in);
-        const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p;
-        key = (static_cast<uint64_t>(depth_bits(ldf<FT>(a.frag, base + 4 * P))) << 32) |
+        const FT* __restrict__ b = frag + loff[l];
+        key = (static_cast<uint64_t>(depth_bits(ldf<FT>(b, 4 * P + p))) << 32) |
               static_cast<uint32_t>(l);
-        al = ldf<FT>(a.frag, base + 3 * P);
+        al = ldf<FT>(b, 3 * P + p);
       }
       const int col = l ^ (g & 15);
       keys[g * Kp + col] = key;
@@ -299,11 +403,11 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     float R = 0.f, Gc = 0.f, B = 0.f;
     if (live) {
       for (int l = sm; l < K; l += S) {
-        const size_t base = static_cast<size_t>(blk[l]) * 5 * P + p_me;
+        const FT* __restrict__ b = frag + loff[l];
         const float w = wrow[l ^ sw];
-        R = fmaf(w, ldf<FT>(a.frag, base), R);
-        Gc = fmaf(w, ldf<FT>(a.frag, base + P), Gc);
-        B = fmaf(w, ldf<FT>(a.frag, base + 2 * P), B);
+        R = fmaf(w, ldf<FT>(b, p_me), R);
+        Gc = fmaf(w, ldf<FT>(b, P + p_me), Gc);
+        B = fmaf(w, ldf<FT>(b, 2 * P + p_me), B);
       }
     }
     // lanes whose chunk is the last non-empty one hold the final T
@@ -342,58 +446,46 @@ __device__ __forceinline__ float variance_of_mean(float sum, int inside_px, int 
                 static_cast<float>(n - 1));
 }
 
-// Next work unit: lane 0 of the calling wave takes a ticket, the wave agrees
-// on it.  Call from wave-uniform code only.
-__device__ __forceinline__ int pop_unit(const FrameArgs& a) {
+// Work queue.  take_ticket: lane 0 of the calling wave issues the atomic; the
+// result is only read (ticket_to_unit) at the end of the current unit, so the
+// atomic's latency overlaps the unit's work.  Call both from wave-uniform code.
+__device__ __forceinline__ unsigned long long take_ticket(const FrameArgs& a) {
   unsigned long long v = 0;
   if (__lane_id() == 0) v = atomicAdd(a.queue, 1ull);
+  return v;
+}
+
+__device__ __forceinline__ int ticket_to_unit(const FrameArgs& a, unsigned long long v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
   const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
   const unsigned long long d = ((static_cast<unsigned long long>(hi) << 32) | lo) - a.q_base;
   return d < static_cast<unsigned long long>(a.n_work) ? static_cast<int>(d) : a.n_work;
 }
 
-// Per-tile variance of the mean once a unit's M2 sum is known.  Runs on all
-// 64 lanes of one wave (wave-uniform control flow; lane-0-only work is a
-// single store or atomic).  Units of a tile leave partial sums; the one that
-// completes the tile adds them in unit order.
-__device__ __forceinline__ void finish_variance(const FrameArgs& a, const Unit& u, int w,
-                                                const float* s_red, int n_waves) {
+// A unit's M2 sum (all waves) -> var_partial[w].  Runs on all lanes of wave
+// 0; the combine into per-tile values is a separate kernel (no fences here).
+__device__ __forceinline__ void store_partial(const FrameArgs& a, int w, const float* s_red,
+                                              int n_waves) {
   float sum = 0.f;
   for (int i = 0; i < 4; ++i)
     if (i < n_waves) sum += s_red[i];
-  const int wx = a.width - u.x0, wy = a.height - u.y0;
-  const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
-  const bool lane0 = __lane_id() == 0;
-  if (a.subs_per_tile == 1) {
-    if (lane0) a.tile_var[u.t] = variance_of_mean(sum, inside, a.n_acc);
-    return;
-  }
-  if (lane0) __hip_atomic_store(a.var_partial + w, sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
-  uint32_t old = 0;
-  if (lane0) old = atomicAdd(a.tile_done + u.t, 1u);
-  old = __builtin_amdgcn_readfirstlane(old);
-  if (old != a.done_base + static_cast<uint32_t>(a.subs_per_tile) - 1u) return;
-  __threadfence();
-  float tot = 0.f;
-  for (int base = 0; base < a.subs_per_tile; base += 64) {
-    const int i = base + static_cast<int>(__lane_id());
-    float p = 0.f;
-    if (i < a.subs_per_tile)
-      p = __hip_atomic_load(a.var_partial + u.t * a.subs_per_tile + i, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-    tot += wave_sum(p);
-  }
-  if (lane0) a.tile_var[u.t] = variance_of_mean(tot, inside, a.n_acc);
+  if (__lane_id() == 0) a.var_partial[w] = sum;
 }
 
 // The persistent frame kernel.  Control flow that contains barriers is
 // uniform across the workgroup; code that only lane 0 runs is a single
 // store or atomic, so no lane can be left behind in a loop that holds a
 // barrier.
+constexpr int min_waves(int kcap) {
+  return kcap <= 8 ? (DFB_WAVES_K8 > 0 ? DFB_WAVES_K8 : 1)
+                   : kcap <= 16 ? (DFB_WAVES_K16 > 0 ? DFB_WAVES_K16 : 1)
+                                : (DFB_WAVES_K32 > 0 ? DFB_WAVES_K32 : 1);
+}
+
 template <typename FT, int KCAP>
-__global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(KCAP))))
+frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
+               const int64_t* __restrict__ layer_off, const int32_t* __restrict__ work_list) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
   __shared__ float s_red[4];
@@ -401,13 +493,15 @@ __global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
   const int n_waves = static_cast<int>(blockDim.x >> 6);
   const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < 64;  // uniform per wave
   if (wave0) {
-    const int v = pop_unit(a);
+    const int v = ticket_to_unit(a, take_ticket(a));
     if (__lane_id() == 0) s_item = v;
   }
   __syncthreads();
   int it = __builtin_amdgcn_readfirstlane(s_item);
   while (it < a.n_work) {
-    const int w = a.work_list[it];
+    // the next unit's ticket is taken now and read after this unit's work
+    const unsigned long long next = wave0 ? take_ticket(a) : 0ull;
+    const int w = work_list[it];
     Unit u;
     u.t = w / a.subs_per_tile;
     const int s = w - u.t * a.subs_per_tile;
@@ -415,9 +509,9 @@ __global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
     u.sx0 = (s - (s / a.subs_x) * a.subs_x) * a.work_w;
     u.y0 = (u.t / a.tiles_x) * a.tile_h;
     u.x0 = (u.t - (u.t / a.tiles_x) * a.tiles_x) * a.tile_w;
-    const int off = a.tile_off[u.t];
-    const int K = a.tile_off[u.t + 1] - off;
-    const int64_t* blk = a.layer_block + off;
+    const int off = tile_off[u.t];
+    const int K = tile_off[u.t + 1] - off;
+    const int64_t* __restrict__ blk = layer_off + off;
     float* wl = reinterpret_cast<float*>(lds);
     float vs;
     if (K == 0) vs = unit_background(a, u);
@@ -439,13 +533,26 @@ __global__ void __launch_bounds__(256) frame_kernel_t(FrameArgs a) {
     }
     __syncthreads();  // s_red complete; every lane has read s_item
     if (wave0) {
-      if (acc) finish_variance(a, u, w, s_red, n_waves);
-      const int v = pop_unit(a);
+      if (acc) store_partial(a, w, s_red, n_waves);
+      const int v = ticket_to_unit(a, next);
       if (__lane_id() == 0) s_item = v;
     }
     __syncthreads();
     it = __builtin_amdgcn_readfirstlane(s_item);
   }
+}
+
+// Per-tile variance of the mean from the units' partial M2 sums, added in
+// unit order (deterministic): one thread per tile.
+__global__ void __launch_bounds__(256) tile_variance_kernel_t(VarianceArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_tiles) return;
+  float sum = 0.f;
+  for (int i = 0; i < a.subs_per_tile; ++i) sum += a.var_partial[t * a.subs_per_tile + i];
+  const int x0 = (t % a.tiles_x) * a.tile_w, y0 = (t / a.tiles_x) * a.tile_h;
+  const int wx = a.width - x0, wy = a.height - y0;
+  const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
+  a.tile_var[t] = variance_of_mean(sum, inside, a.n_acc);
 }
 
 // Unfused accumulation of the stored finished tiles: one workgroup per tile.
@@ -482,10 +589,10 @@ template <typename FT>
 __global__ void __launch_bounds__(256) validate_kernel_t(ValidateArgs a) {
   const int l = blockIdx.x;
   if (l >= a.n_layers) return;
-  const size_t base = static_cast<size_t>(a.layer_block[l]) * 5 * a.P + 4 * static_cast<size_t>(a.P);
+  const FT* __restrict__ b = static_cast<const FT*>(a.frag) + a.layer_off[l];
   bool bad = false;
   for (int p = threadIdx.x; p < a.P; p += blockDim.x) {
-    const float d = ldf<FT>(a.frag, base + p);
+    const float d = ldf<FT>(b, 4 * static_cast<uint32_t>(a.P) + p);
     bad |= (d != d);
   }
   if (bad) atomicOr(a.bad, 1u);
@@ -505,6 +612,8 @@ const void* frame_kernel(int dtype, int kcap) {
 }
 
 const void* accumulate_kernel() { return reinterpret_cast<const void*>(&accumulate_kernel_t); }
+
+const void* tile_variance_kernel() { return reinterpret_cast<const void*>(&tile_variance_kernel_t); }
 
 const void* validate_kernel(int dtype) {
   return dtype == 0 ? reinterpret_cast<const void*>(&validate_kernel_t<float>)

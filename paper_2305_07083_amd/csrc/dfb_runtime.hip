@@ -78,10 +78,8 @@ struct dfb_ctx {
   float* d_var_partial = nullptr;
   size_t partial_cap = 0;
   unsigned long long* d_queue = nullptr;
-  uint32_t* d_tile_done = nullptr;
   uint32_t* d_flag = nullptr;
   unsigned long long q_base = 0;
-  uint32_t done_base = 0;
 
   // launch shape
   Shape shape{0, 0, 0};
@@ -92,14 +90,21 @@ struct dfb_ctx {
   int subs_x = 1, subs_per_tile = 1;
   bool work_valid = false;  // d_work matches shape + layer table
 
-  // graph
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node = nullptr;
-  const void* graph_func = nullptr;
-  int graph_threads = 0, graph_grid = 0;
-  size_t graph_lds = 0;
+  // graphs: [0] plain frames, [1] accumulating frames (frame kernel ->
+  // per-tile variance combine)
+  struct GraphSlot {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t frame_node = nullptr, var_node = nullptr;
+    const void* func = nullptr;
+    int threads = 0, grid = 0;
+    size_t lds = 0;
+  } gslot[2];
   FrameArgs graph_args{};
+  const int32_t* tab_off = nullptr;
+  const int64_t* tab_layer = nullptr;
+  const int32_t* tab_work = nullptr;
+  dfb::VarianceArgs var_args{};
 
   // timing: a ring of event pairs, harvested when a slot is reused
   static constexpr int kRing = 64;
@@ -254,7 +259,7 @@ std::vector<Shape> candidates(const dfb_config& c) {
   if (c.work_w) {
     sizes.push_back({c.work_w, c.work_h});
   } else {
-    for (int s : {32, 64, 128})
+    for (int s : {16, 32, 64, 128})
       if (c.tile_w % s == 0 && c.tile_h % s == 0) sizes.push_back({s, s});
     if (sizes.empty()) sizes.push_back({c.tile_w, c.tile_h});
   }
@@ -306,13 +311,8 @@ dfb_status ensure_accum(dfb_ctx* h) {
 FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   FrameArgs a{};
   a.frag = h->frag;
-  a.tile_off = h->d_off;
-  a.layer_block = h->d_block;
-  a.work_list = h->d_work;
   a.queue = h->d_queue;
-  a.tile_done = h->d_tile_done;
   a.q_base = h->q_base;
-  a.done_base = h->done_base;
   a.n_work = h->n_work;
   a.width = h->cfg.width;
   a.height = h->cfg.height;
@@ -326,6 +326,9 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   a.subs_x = h->subs_x;
   a.subs_per_tile = h->subs_per_tile;
   a.work_px = h->shape.work_w * h->shape.work_h;
+  a.work_shift = -1;
+  for (int k = 0; k < 16; ++k)
+    if ((1 << k) == h->shape.work_w) a.work_shift = k;
   for (int c = 0; c < 4; ++c) a.bg[c] = h->cfg.background[c];
   a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
   a.mode = mode;
@@ -357,50 +360,80 @@ dfb_status grid_for(dfb_ctx* h, const void* func, int threads, size_t lds, int& 
   return DFB_OK;
 }
 
-// Launch one frame with the current shape.  Uses the graph when asked.
+dfb::VarianceArgs make_var_args(dfb_ctx* h) {
+  dfb::VarianceArgs v{};
+  v.var_partial = h->d_var_partial;
+  v.tile_var = h->tile_var;
+  v.n_tiles = h->n_tiles;
+  v.subs_per_tile = h->subs_per_tile;
+  v.tiles_x = h->tiles_x;
+  v.width = h->cfg.width;
+  v.height = h->cfg.height;
+  v.tile_w = h->cfg.tile_w;
+  v.tile_h = h->cfg.tile_h;
+  v.n_acc = h->acc_n;
+  return v;
+}
+
+// Launch one frame with the current shape: the persistent frame kernel, then
+// (accumulating frames) the per-tile variance combine.  As a HIP graph when
+// asked, with the node parameters updated per frame.
 dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph) {
   const int threads = 64 * h->shape.waves;
   const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap);
   const size_t lds = dfb::frame_lds_bytes(h->kcap, threads, h->max_k);
+  const bool acc = (mode & dfb::kModeAccumulate) != 0;
   int grid = 0;
   dfb_status st = grid_for(h, func, threads, lds, grid);
   if (st != DFB_OK) return st;
   if (lds > 64 * 1024) DFB_HIP(h, hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  FrameArgs a = make_args(h, mode);
+  h->graph_args = make_args(h, mode);
+  h->var_args = make_var_args(h);
+  h->tab_off = h->d_off;
+  h->tab_layer = h->d_block;
+  h->tab_work = h->d_work;
+  void* fparams[] = {&h->graph_args, &h->tab_off, &h->tab_layer, &h->tab_work};
+  void* vparams[] = {&h->var_args};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(func);
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(threads);
+  kp.sharedMemBytes = static_cast<unsigned>(lds);
+  kp.kernelParams = fparams;
+  kp.extra = nullptr;
+  hipKernelNodeParams vp{};
+  vp.func = const_cast<void*>(dfb::tile_variance_kernel());
+  vp.gridDim = dim3((h->n_tiles + 255) / 256);
+  vp.blockDim = dim3(256);
+  vp.sharedMemBytes = 0;
+  vp.kernelParams = vparams;
+  vp.extra = nullptr;
   if (use_graph) {
-    const bool rebuild = !h->exec || h->graph_func != func || h->graph_threads != threads ||
-                         h->graph_grid != grid || h->graph_lds != lds;
-    h->graph_args = a;
-    void* params[] = {&h->graph_args};
-    hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(func);
-    kp.gridDim = dim3(grid);
-    kp.blockDim = dim3(threads);
-    kp.sharedMemBytes = static_cast<unsigned>(lds);
-    kp.kernelParams = params;
-    kp.extra = nullptr;
+    dfb_ctx::GraphSlot& g = h->gslot[acc ? 1 : 0];
+    const bool rebuild = !g.exec || g.func != func || g.threads != threads || g.grid != grid || g.lds != lds;
     if (rebuild) {
-      if (h->exec) { DFB_HIP(h, hipGraphExecDestroy(h->exec)); h->exec = nullptr; }
-      if (h->graph) { DFB_HIP(h, hipGraphDestroy(h->graph)); h->graph = nullptr; }
-      DFB_HIP(h, hipGraphCreate(&h->graph, 0));
-      DFB_HIP(h, hipGraphAddKernelNode(&h->node, h->graph, nullptr, 0, &kp));
-      DFB_HIP(h, hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
-      h->graph_func = func;
-      h->graph_threads = threads;
-      h->graph_grid = grid;
-      h->graph_lds = lds;
+      if (g.exec) { DFB_HIP(h, hipGraphExecDestroy(g.exec)); g.exec = nullptr; }
+      if (g.graph) { DFB_HIP(h, hipGraphDestroy(g.graph)); g.graph = nullptr; }
+      DFB_HIP(h, hipGraphCreate(&g.graph, 0));
+      DFB_HIP(h, hipGraphAddKernelNode(&g.frame_node, g.graph, nullptr, 0, &kp));
+      if (acc) DFB_HIP(h, hipGraphAddKernelNode(&g.var_node, g.graph, &g.frame_node, 1, &vp));
+      DFB_HIP(h, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+      g.func = func;
+      g.threads = threads;
+      g.grid = grid;
+      g.lds = lds;
     } else {
-      DFB_HIP(h, hipGraphExecKernelNodeSetParams(h->exec, h->node, &kp));
+      DFB_HIP(h, hipGraphExecKernelNodeSetParams(g.exec, g.frame_node, &kp));
+      if (acc) DFB_HIP(h, hipGraphExecKernelNodeSetParams(g.exec, g.var_node, &vp));
     }
-    DFB_HIP(h, hipGraphLaunch(h->exec, h->stream));
+    DFB_HIP(h, hipGraphLaunch(g.exec, h->stream));
   } else {
-    void* params[] = {&a};
-    DFB_HIP(h, hipLaunchKernel(func, dim3(grid), dim3(threads), params, lds, h->stream));
+    DFB_HIP(h, hipLaunchKernel(func, dim3(grid), dim3(threads), fparams, lds, h->stream));
+    if (acc) DFB_HIP(h, hipLaunchKernel(vp.func, vp.gridDim, vp.blockDim, vparams, 0, h->stream));
   }
   DFB_HIP(h, hipGetLastError());
   h->grid = grid;
   h->q_base += static_cast<unsigned long long>(h->n_work) + static_cast<unsigned long long>(grid);
-  if ((mode & dfb::kModeAccumulate) && h->subs_per_tile > 1) h->done_base += static_cast<uint32_t>(h->subs_per_tile);
   return DFB_OK;
 }
 
@@ -562,10 +595,8 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
   }
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->tile_var), h->n_tiles * sizeof(float))) != DFB_OK) return bail(s);
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_queue), 64)) != DFB_OK) return bail(s);
-  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_tile_done), h->n_tiles * sizeof(uint32_t))) != DFB_OK) return bail(s);
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_flag), 64)) != DFB_OK) return bail(s);
   e = hipMemsetAsync(h->d_queue, 0, 64, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->d_tile_done, 0, h->n_tiles * sizeof(uint32_t), h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->tile_var, 0, h->n_tiles * sizeof(float), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) { hip_fail(h, e, "initialising device state"); return bail(DFB_ERR_HIP); }
@@ -576,14 +607,16 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
 dfb_status dfb_destroy(dfb_handle h) {
   if (!h) return DFB_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(h->stream);
-  if (h->exec) (void)hipGraphExecDestroy(h->exec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (auto& g : h->gslot) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
   for (int i = 0; i < dfb_ctx::kRing; ++i) {
     if (h->ev0[i]) (void)hipEventDestroy(h->ev0[i]);
     if (h->ev1[i]) (void)hipEventDestroy(h->ev1[i]);
   }
   void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->d_off,
-                  h->d_block, h->d_work, h->d_var_partial, h->d_queue, h->d_tile_done, h->d_flag};
+                  h->d_block, h->d_work, h->d_var_partial, h->d_queue, h->d_flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete h;
@@ -630,7 +663,7 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
       if (it != b && layers[*it].source_id == layers[*(it - 1)].source_id)
         return fail(h, DFB_ERR_DUPLICATE, "tile " + std::to_string(t) + ": source " +
                                               std::to_string(layers[*it].source_id) + " appears twice");
-      block[it - idx.begin()] = layers[*it].block;
+      block[it - idx.begin()] = layers[*it].block * 5 * static_cast<int64_t>(h->P);
     }
     max_k = std::max(max_k, counts[t]);
   }

@@ -16,8 +16,9 @@ constexpr int pow2_ceil(int n) { return n <= 1 ? 1 : 2 * pow2_ceil((n + 1) / 2);
 
 template <typename K>
 __host__ __device__ __forceinline__ void compare_exchange(K& a, K& b) {
-  const K lo = a < b ? a : b;
-  const K hi = a < b ? b : a;
+  const bool lt = a < b;  // one compare, two selects per word
+  const K lo = lt ? a : b;
+  const K hi = lt ? b : a;
   a = lo;
   b = hi;
 }
