@@ -31,7 +31,41 @@ def parse():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain", action="store_true", help="composite only (no accumulation)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 1 GiB device to device (the reference kernel for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ["dfb_kernels.hip", "dfb_internal.h", "sortnet.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_07083_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, accumulate):
+    """HBM bytes per frame-kernel launch from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "frame_kernel_%s_%s_counters.txt"
+                        % (workload, "acc" if accumulate else "plain"))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+    write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+    return (fetch + write) * 1024.0
 
 
 def make_frame(name):
@@ -151,9 +185,15 @@ def main():
         "hbm_gbps_algorithmic": achieved,
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBPS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(args.workload, accumulate),
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, accumulate)
     print(json.dumps(out), flush=True)

@@ -169,9 +169,10 @@ dfb_status dfb_synchronize(dfb_handle h);
 /* Shape of the current frame and launch. */
 dfb_status dfb_get_info(dfb_handle h, dfb_info* out);
 
-/* Average device time (ms) of the last n composite launches, measured with
- * HIP events on the handle's stream; -1 if none were timed.  Timing is on
- * while enable != 0 (dfb_set_timing). */
+/* Average device time (ms) of the frame kernel over the composites since
+ * timing was enabled (dfb_set_timing(h, 1)), measured with HIP events that
+ * the frame's graph records right before and after the frame kernel on the
+ * handle's stream; -1 if none were timed. */
 dfb_status dfb_set_timing(dfb_handle h, int enable);
 double dfb_kernel_ms(dfb_handle h);
 

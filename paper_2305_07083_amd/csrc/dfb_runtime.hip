@@ -95,7 +95,7 @@ struct dfb_ctx {
   struct GraphSlot {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t frame_node = nullptr, var_node = nullptr;
+    hipGraphNode_t ev_start = nullptr, frame_node = nullptr, ev_end = nullptr, var_node = nullptr;
     const void* func = nullptr;
     int threads = 0, grid = 0;
     size_t lds = 0;
@@ -110,6 +110,7 @@ struct dfb_ctx {
   static constexpr int kRing = 64;
   bool timing = false;
   hipEvent_t ev0[kRing] = {}, ev1[kRing] = {};
+  hipEvent_t idle0 = nullptr, idle1 = nullptr;  // recorded by the graph when not timing
   bool pending[kRing] = {};
   int ring_pos = 0;
   double time_sum_ms = 0.0;
@@ -377,8 +378,11 @@ dfb::VarianceArgs make_var_args(dfb_ctx* h) {
 
 // Launch one frame with the current shape: the persistent frame kernel, then
 // (accumulating frames) the per-tile variance combine.  As a HIP graph when
-// asked, with the node parameters updated per frame.
-dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph) {
+// asked -- event record -> frame kernel -> event record [-> variance] -- with
+// the node parameters (and the two events, t0/t1 when timing) updated per
+// frame, so the events bracket the frame kernel alone.
+dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0 = nullptr,
+                        hipEvent_t t1 = nullptr) {
   const int threads = 64 * h->shape.waves;
   const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap);
   const size_t lds = dfb::frame_lds_bytes(h->kcap, threads, h->max_k);
@@ -409,14 +413,21 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph) {
   vp.kernelParams = vparams;
   vp.extra = nullptr;
   if (use_graph) {
+    if (!h->idle0) {
+      DFB_HIP(h, hipEventCreateWithFlags(&h->idle0, hipEventDisableTiming));
+      DFB_HIP(h, hipEventCreateWithFlags(&h->idle1, hipEventDisableTiming));
+    }
+    hipEvent_t e0 = t0 ? t0 : h->idle0, e1 = t1 ? t1 : h->idle1;
     dfb_ctx::GraphSlot& g = h->gslot[acc ? 1 : 0];
     const bool rebuild = !g.exec || g.func != func || g.threads != threads || g.grid != grid || g.lds != lds;
     if (rebuild) {
       if (g.exec) { DFB_HIP(h, hipGraphExecDestroy(g.exec)); g.exec = nullptr; }
       if (g.graph) { DFB_HIP(h, hipGraphDestroy(g.graph)); g.graph = nullptr; }
       DFB_HIP(h, hipGraphCreate(&g.graph, 0));
-      DFB_HIP(h, hipGraphAddKernelNode(&g.frame_node, g.graph, nullptr, 0, &kp));
-      if (acc) DFB_HIP(h, hipGraphAddKernelNode(&g.var_node, g.graph, &g.frame_node, 1, &vp));
+      DFB_HIP(h, hipGraphAddEventRecordNode(&g.ev_start, g.graph, nullptr, 0, e0));
+      DFB_HIP(h, hipGraphAddKernelNode(&g.frame_node, g.graph, &g.ev_start, 1, &kp));
+      DFB_HIP(h, hipGraphAddEventRecordNode(&g.ev_end, g.graph, &g.frame_node, 1, e1));
+      if (acc) DFB_HIP(h, hipGraphAddKernelNode(&g.var_node, g.graph, &g.ev_end, 1, &vp));
       DFB_HIP(h, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
       g.func = func;
       g.threads = threads;
@@ -426,6 +437,8 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph) {
       DFB_HIP(h, hipGraphExecKernelNodeSetParams(g.exec, g.frame_node, &kp));
       if (acc) DFB_HIP(h, hipGraphExecKernelNodeSetParams(g.exec, g.var_node, &vp));
     }
+    DFB_HIP(h, hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_start, e0));
+    DFB_HIP(h, hipGraphExecEventRecordNodeSetEvent(g.exec, g.ev_end, e1));
     DFB_HIP(h, hipGraphLaunch(g.exec, h->stream));
   } else {
     DFB_HIP(h, hipLaunchKernel(func, dim3(grid), dim3(threads), fparams, lds, h->stream));
@@ -615,6 +628,8 @@ dfb_status dfb_destroy(dfb_handle h) {
     if (h->ev0[i]) (void)hipEventDestroy(h->ev0[i]);
     if (h->ev1[i]) (void)hipEventDestroy(h->ev1[i]);
   }
+  if (h->idle0) (void)hipEventDestroy(h->idle0);
+  if (h->idle1) (void)hipEventDestroy(h->idle1);
   void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->d_off,
                   h->d_block, h->d_work, h->d_var_partial, h->d_queue, h->d_flag};
   for (void* b : bufs)
@@ -734,6 +749,7 @@ dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
     h->acc_n += 1;
   }
   const int slot = h->ring_pos;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
   if (h->timing) {
     if (!h->ev0[slot]) {
       DFB_HIP(h, hipEventCreate(&h->ev0[slot]));
@@ -743,12 +759,12 @@ dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
       s = harvest(h, slot);
       if (s != DFB_OK) return s;
     }
-    DFB_HIP(h, hipEventRecord(h->ev0[slot], h->stream));
+    t0 = h->ev0[slot];
+    t1 = h->ev1[slot];
   }
-  s = launch_frame(h, mode, true);
+  s = launch_frame(h, mode, true, t0, t1);
   if (s != DFB_OK) return s;
   if (h->timing) {
-    DFB_HIP(h, hipEventRecord(h->ev1[slot], h->stream));
     h->pending[slot] = true;
     h->ring_pos = (slot + 1) % dfb_ctx::kRing;
   }
