@@ -60,7 +60,8 @@ typedef enum {
   DFB_BUF_ACCUM_F32 = 2,      /* running mean, float[n][P][4] */
   DFB_BUF_M2_F32 = 3,         /* Welford M2 of R,G,B, float[n][3][P] (planar per tile) */
   DFB_BUF_TILE_VARIANCE = 4,  /* per-tile variance of the mean, float[n]; +inf while n < 2 */
-  DFB_BUF_SORT_ORDER = 5      /* debug, needs DFB_KEEP_SORT_ORDER: see below */
+  DFB_BUF_SORT_ORDER = 5,     /* debug, needs DFB_KEEP_SORT_ORDER: see below */
+  DFB_BUF_DENOISED_F32 = 6    /* result of dfb_denoise (dfb_denoise.h), float[n][P][4] */
 } dfb_buffer;
 
 /* dfb_config.flags */

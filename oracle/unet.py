@@ -199,3 +199,36 @@ def adam_step(params, grads, state, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         out[k] = (w.astype(np.float64) - lr * mh / (np.sqrt(vh) + eps)).astype(np.float32)
         state[k] = (m, v)
     return out
+
+
+# ---------------------------------------------------------------- frame glue
+def frame_input(mu_tiles, tile_var, n, width, height, tile_w, tile_h):
+    """Network input of a compositor accumulation: per image pixel
+    [mean R, G, B, A, log(v_t), 1/n], log(v_t) with v_t floored at 1e-12 and
+    0 while n < 2 (no variance measured yet).  mu_tiles [T, P, 4]."""
+    tiles_x = -(-width // tile_w)
+    out = np.zeros((height, width, 6))
+    for y in range(height):
+        for x in range(width):
+            t = (y // tile_h) * tiles_x + x // tile_w
+            q = (y % tile_h) * tile_w + x % tile_w
+            out[y, x, :4] = mu_tiles[t, q]
+            out[y, x, 4] = np.log(max(tile_var[t], 1e-12)) if n >= 2 else 0.0
+            out[y, x, 5] = 1.0 / n
+    return out
+
+
+def select(mu_tiles, tile_var, out_rgb, n, tau, width, height, tile_w, tile_h):
+    """Per tile: the plain mean where the measured variance exceeds tau
+    (n >= 2 and v_t > tau), else the network's RGB with the mean's alpha."""
+    tiles_x = -(-width // tile_w)
+    res = np.array(mu_tiles, dtype=np.float64, copy=True)
+    for t in range(res.shape[0]):
+        if n >= 2 and tile_var[t] > tau:
+            continue
+        for q in range(res.shape[1]):
+            y = (t // tiles_x) * tile_h + q // tile_w
+            x = (t % tiles_x) * tile_w + q % tile_w
+            if x < width and y < height:
+                res[t, q, :3] = out_rgb[y, x]
+    return res

@@ -29,7 +29,7 @@ DFB_ERR_UNSUPPORTED = -8
 DFB_F32, DFB_F16 = 0, 1
 DFB_FMT_RGBA8, DFB_FMT_RGBAF32, DFB_FMT_NONE = 0, 1, 2
 (DFB_BUF_FINAL, DFB_BUF_FINISHED_F32, DFB_BUF_ACCUM_F32, DFB_BUF_M2_F32,
- DFB_BUF_TILE_VARIANCE, DFB_BUF_SORT_ORDER) = range(6)
+ DFB_BUF_TILE_VARIANCE, DFB_BUF_SORT_ORDER, DFB_BUF_DENOISED_F32) = range(7)
 DFB_VALIDATE, DFB_KEEP_SORT_ORDER, DFB_KEEP_FINISHED = 0x1, 0x2, 0x4
 DFB_ACCUMULATE = 0x1
 
@@ -39,6 +39,10 @@ EXPORTED = (
     "dfb_reset_accumulation", "dfb_read_tiles", "dfb_buffer_bytes", "dfb_synchronize",
     "dfb_get_info", "dfb_set_timing", "dfb_kernel_ms", "dfb_validate_layers", "dfb_last_error",
     "dfb_status_string",
+    # dfb_denoise.h
+    "dfb_denoiser_param_count", "dfb_denoiser_create", "dfb_denoiser_destroy", "dfb_denoiser_set_params",
+    "dfb_denoiser_get_params", "dfb_denoiser_forward", "dfb_denoiser_train_step",
+    "dfb_denoiser_read_activation", "dfb_denoiser_frame_input", "dfb_denoise", "dfb_denoiser_last_error",
 )
 
 
@@ -65,6 +69,11 @@ class Info(ctypes.Structure):
                 ("work_w", ctypes.c_int32), ("work_h", ctypes.c_int32),
                 ("waves_per_tile", ctypes.c_int32), ("accumulation_id", ctypes.c_int32),
                 ("grid_size", ctypes.c_int32), ("n_fragments", ctypes.c_int64)]
+
+
+class UnetConfig(ctypes.Structure):
+    _fields_ = [("max_pixels", ctypes.c_int64), ("seed", ctypes.c_uint32), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 class DfbError(RuntimeError):
@@ -101,6 +110,17 @@ def load():
         "dfb_validate_layers": ([ctypes.POINTER(Config), I64, P, I32, P, P], I32),
         "dfb_last_error": ([P], ctypes.c_char_p),
         "dfb_status_string": ([I32], ctypes.c_char_p),
+        "dfb_denoiser_param_count": ([], I64),
+        "dfb_denoiser_create": ([ctypes.POINTER(UnetConfig), P, ctypes.POINTER(P)], I32),
+        "dfb_denoiser_destroy": ([P], I32),
+        "dfb_denoiser_set_params": ([P, P, I64], I32),
+        "dfb_denoiser_get_params": ([P, I32, P, I64], I32),
+        "dfb_denoiser_forward": ([P, P, P, I32, I32, I32], I32),
+        "dfb_denoiser_train_step": ([P, P, P, I32, I32, I32, ctypes.c_float, I32, P], I32),
+        "dfb_denoiser_read_activation": ([P, I32, P, I64], I32),
+        "dfb_denoiser_frame_input": ([P, P], I32),
+        "dfb_denoise": ([P, P, ctypes.c_float], I32),
+        "dfb_denoiser_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -110,10 +130,13 @@ def load():
     return lib
 
 
-def _check(status, handle=None):
+def _check(status, handle=None, net=None):
     if status != DFB_OK:
         lib = load()
-        msg = lib.dfb_last_error(handle).decode(errors="replace")
+        if net is not None:
+            msg = lib.dfb_denoiser_last_error(net).decode(errors="replace")
+        else:
+            msg = lib.dfb_last_error(handle).decode(errors="replace")
         raise DfbError(status, msg or lib.dfb_status_string(status).decode())
 
 
@@ -269,4 +292,105 @@ class Compositor:
             return buf.view(np.float32)
         if which == DFB_BUF_SORT_ORDER:
             return buf.view(np.uint16)
+        if which == DFB_BUF_DENOISED_F32:
+            return buf.view(np.float32).reshape(n_tiles, P, 4)
         raise ValueError(which)
+
+
+# ---------------------------------------------------------- denoiser (dfb_denoise.h)
+UNET_CONV3 = [("enc1a", 6, 32, 0), ("enc1b", 32, 32, 0), ("enc2a", 32, 64, 1), ("enc2b", 64, 64, 1),
+              ("enc3a", 64, 128, 2), ("enc3b", 128, 128, 2), ("up2", 128, 64, 1), ("dec2a", 128, 64, 1),
+              ("dec2b", 64, 64, 1), ("up1", 64, 32, 0), ("dec1a", 64, 32, 0), ("dec1b", 32, 32, 0)]
+
+
+def dfb_denoiser_param_count():
+    return int(load().dfb_denoiser_param_count())
+
+
+def dfb_denoiser_create(cfg: UnetConfig, stream=0):
+    h = ctypes.c_void_p()
+    _check(load().dfb_denoiser_create(ctypes.byref(cfg), ctypes.c_void_p(int(stream)), ctypes.byref(h)), net=None)
+    return h
+
+
+def dfb_denoiser_destroy(net):
+    _check(load().dfb_denoiser_destroy(net), net=net)
+
+
+def dfb_denoiser_set_params(net, flat):
+    flat = np.ascontiguousarray(flat, dtype=np.float32)
+    _check(load().dfb_denoiser_set_params(net, _ptr(flat), flat.size), net=net)
+
+
+def dfb_denoiser_get_params(net, what=0):
+    out = np.empty(dfb_denoiser_param_count(), dtype=np.float32)
+    _check(load().dfb_denoiser_get_params(net, what, _ptr(out), out.size), net=net)
+    return out
+
+
+def dfb_denoiser_forward(net, in_dev, out_dev, n, h, w):
+    _check(load().dfb_denoiser_forward(net, _ptr(in_dev), _ptr(out_dev), n, h, w), net=net)
+
+
+def dfb_denoiser_train_step(net, in_dev, target_dev, n, h, w, lr, apply_update=True, want_loss=True):
+    loss = ctypes.c_float(0.0)
+    _check(load().dfb_denoiser_train_step(net, _ptr(in_dev), _ptr(target_dev), n, h, w, float(lr),
+                                          int(bool(apply_update)),
+                                          ctypes.byref(loss) if want_loss else None), net=net)
+    return float(loss.value) if want_loss else None
+
+
+def dfb_denoiser_read_activation(net, layer, n, h, w):
+    lvl = UNET_CONV3[layer][3]
+    co = UNET_CONV3[layer][2]
+    hh, ww = h >> lvl, w >> lvl
+    out = np.empty((n, hh, ww, co), dtype=np.uint16)
+    _check(load().dfb_denoiser_read_activation(net, layer, _ptr(out), out.nbytes), net=net)
+    return out
+
+
+def dfb_denoiser_frame_input(h, in_dev):
+    _check(load().dfb_denoiser_frame_input(h, _ptr(in_dev)), h)
+
+
+def dfb_denoise(h, net, var_threshold):
+    _check(load().dfb_denoise(h, net, float(var_threshold)), net=net)
+
+
+def unet_params_to_flat(params):
+    """Dict of per-layer arrays (names as UNET_CONV3 + 'out') -> flat ABI order."""
+    parts = []
+    for name, _, _, _ in UNET_CONV3:
+        parts += [np.asarray(params[name + ".w"], np.float32).ravel(), np.asarray(params[name + ".b"], np.float32).ravel()]
+    parts += [np.asarray(params["out.w"], np.float32).ravel(), np.asarray(params["out.b"], np.float32).ravel()]
+    return np.concatenate(parts)
+
+
+def unet_flat_to_params(flat):
+    out, o = {}, 0
+    for name, ci, co, _ in UNET_CONV3:
+        out[name + ".w"] = flat[o:o + 9 * ci * co].reshape(3, 3, ci, co)
+        o += 9 * ci * co
+        out[name + ".b"] = flat[o:o + co]
+        o += co
+    out["out.w"] = flat[o:o + 96].reshape(32, 3)
+    out["out.b"] = flat[o + 96:o + 99]
+    return out
+
+
+class Denoiser:
+    """Owns a denoiser handle."""
+
+    def __init__(self, max_pixels, seed=0, stream=0):
+        self.net = dfb_denoiser_create(UnetConfig(int(max_pixels), seed, 0.0, 0.0, 0.0), stream)
+
+    def close(self):
+        if self.net:
+            dfb_denoiser_destroy(self.net)
+            self.net = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

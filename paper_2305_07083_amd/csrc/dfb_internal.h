@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/dfb.h"
+
 namespace dfb {
 
 // Layers per tile handled by the register sort; above it, the workgroup-wide
@@ -80,6 +82,23 @@ struct ValidateArgs {
   int32_t n_layers, P;
   uint32_t* bad;   // set to 1 if a NaN depth is seen
 };
+
+// What the denoiser needs from a compositor handle: its accumulation.
+struct FrameGlue {
+  const float* accum;      // [T][P][4] running mean
+  const float* tile_var;   // [T]
+  int width, height, tiles_x, tile_w, tile_h, P, n_acc;
+};
+struct FrameView {
+  FrameGlue glue;
+  void* final_out;         // display buffer (or null for NONE)
+  float* denoised;         // [T][P][4] (allocated on request)
+  uint32_t display_mode;   // kModeFmt* | kModeGamma
+  float inv_gamma;
+  hipStream_t stream;
+};
+// Fails with DFB_ERR_STATE unless at least one frame has been accumulated.
+dfb_status frame_view(dfb_ctx* h, FrameView* out, bool want_denoised);
 
 // Kernel entry points for a given fragment type and register-sort cap.
 // dtype: 0 f32, 1 f16.  kcap: 8, 16 or 32 (layers handled in registers).

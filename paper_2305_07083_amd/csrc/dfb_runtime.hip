@@ -57,6 +57,7 @@ struct dfb_ctx {
   void* final_out = nullptr;
   uint16_t* order = nullptr;
   size_t order_cap = 0;
+  float* denoised = nullptr;  // dfb_denoise result
   int acc_n = 0;          // frames folded in
   bool have_finished = false;
 
@@ -531,6 +532,34 @@ dfb_status scan_nan(dfb_ctx* h, const void* frag_dev, int n_layers) {
 
 }  // namespace
 
+namespace dfb {
+dfb_status frame_view(dfb_ctx* h, FrameView* v, bool want_denoised) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (!v) return DFB_ERR_INVALID_ARG;
+  if (!h->accum || h->acc_n < 1) return fail(h, DFB_ERR_STATE, "no accumulated frame");
+  if (want_denoised && !h->denoised) {
+    s = alloc_plain(h, reinterpret_cast<void**>(&h->denoised), static_cast<size_t>(h->n_tiles) * h->P * 16);
+    if (s != DFB_OK) return s;
+  }
+  v->glue.accum = h->accum;
+  v->glue.tile_var = h->tile_var;
+  v->glue.width = h->cfg.width;
+  v->glue.height = h->cfg.height;
+  v->glue.tiles_x = h->tiles_x;
+  v->glue.tile_w = h->cfg.tile_w;
+  v->glue.tile_h = h->cfg.tile_h;
+  v->glue.P = h->P;
+  v->glue.n_acc = h->acc_n;
+  v->final_out = h->final_out;
+  v->denoised = h->denoised;
+  v->display_mode = display_mode(h->cfg);
+  v->inv_gamma = 1.f / h->cfg.tonemap_gamma;
+  v->stream = h->stream;
+  return DFB_OK;
+}
+}  // namespace dfb
+
 extern "C" {
 
 const char* dfb_status_string(dfb_status s) {
@@ -630,7 +659,7 @@ dfb_status dfb_destroy(dfb_handle h) {
   }
   if (h->idle0) (void)hipEventDestroy(h->idle0);
   if (h->idle1) (void)hipEventDestroy(h->idle1);
-  void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->d_off,
+  void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->denoised, h->d_off,
                   h->d_block, h->d_work, h->d_var_partial, h->d_queue, h->d_flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -826,6 +855,7 @@ int64_t dfb_buffer_bytes(dfb_handle h, dfb_buffer which, int32_t first, int32_t 
     case DFB_BUF_SORT_ORDER:
       if (!h->order || h->h_off.empty()) return 0;
       return (static_cast<int64_t>(h->h_off[first + n]) - h->h_off[first]) * P * 2;
+    case DFB_BUF_DENOISED_F32: return h->denoised ? n * P * 16 : 0;
   }
   return 0;
 }
@@ -846,6 +876,7 @@ dfb_status dfb_read_tiles(dfb_handle h, dfb_buffer which, int32_t first, int32_t
     case DFB_BUF_M2_F32: src = reinterpret_cast<const char*>(h->m2) + first * P * 12; break;
     case DFB_BUF_TILE_VARIANCE: src = reinterpret_cast<const char*>(h->tile_var) + first * 4; break;
     case DFB_BUF_SORT_ORDER: src = reinterpret_cast<const char*>(h->order) + static_cast<int64_t>(h->h_off[first]) * P * 2; break;
+    case DFB_BUF_DENOISED_F32: src = reinterpret_cast<const char*>(h->denoised) + first * P * 16; break;
     default: return fail(h, DFB_ERR_INVALID_ARG, "unknown buffer");
   }
   if (bytes > 0)

@@ -1,0 +1,76 @@
+// Internal interface between the denoiser runtime (unet_runtime.hip) and its
+// gfx950 kernels (unet_kernels.hip).  Not part of the C ABI.
+//
+// Layouts: activations NHWC; bf16 maps are stored as uint16 bit patterns;
+// a map may be a channel slice of a wider buffer (row stride `ld`, first
+// channel `off`).  conv3x3 weights (f32 master) are [3][3][ci][co]; the
+// kernels read two bf16 copies: fwd [9][co][ci] and dgrad [9][ci][co].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dfb_internal.h"
+
+namespace dfb {
+namespace unet {
+
+struct Map {          // bf16 NHWC map (or a channel slice of one)
+  uint16_t* p;
+  int ld, off, c;     // row stride (channels), first channel, channels
+};
+struct MapF {         // f32 NHWC map
+  float* p;
+  int ld, off, c;
+};
+struct Shape {
+  int n, h, w;        // batch, height, width
+  __host__ __device__ long long pixels() const { return static_cast<long long>(n) * h * w; }
+};
+
+// y = bf16(relu(conv3x3(x) + b)); x channels must be a multiple of 8.
+hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y,
+                       const Shape& s, hipStream_t st);
+// dx = conv3x3^T(bf16(dy * (y > 0))) (overwrites dx).
+hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, const MapF& dx,
+                         const Shape& s, hipStream_t st);
+// dw[9][ci][co] = sum_p x[p + tap] * bf16(dy[p] * (y[p] > 0)) for ci < ci_out
+// (ci_out < x.c when x carries zero padding channels); db[co] = sum_p dy*(y>0).
+// `partial` needs conv3x3_wgrad_scratch floats.
+hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, float* db,
+                         float* partial, const Shape& s, hipStream_t st, int ci_out);
+size_t conv3x3_wgrad_scratch(int ci, int co, const Shape& s);
+
+hipError_t avgpool2(const Map& x, const Map& y, const Shape& s_in, hipStream_t st);
+hipError_t avgpool2_backward_add(const MapF& dy, const MapF& dx, const Shape& s_in, hipStream_t st);
+hipError_t upsample2(const Map& x, const Map& y, const Shape& s_in, hipStream_t st);
+hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in, hipStream_t st);
+hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st);
+
+// out[p][c] = base[p][c] + b[c] + sum_i x[p][i] w[i][c]   (c < 3, f32)
+hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base,
+                        int base_ld, float* out, const Shape& s, hipStream_t st);
+// dout = 2 (out - target) / count; loss partial sums; dx = dout w^T; dw, db.
+hipError_t out_conv_backward(const Map& x, const float* out, const float* target, const float* w,
+                             const MapF& dx, float* dw, float* db, float* loss, float* partial,
+                             const Shape& s, hipStream_t st);
+size_t out_conv_scratch(const Shape& s);
+
+// bf16 input [p][8] from f32 [p][in_ld] (first 6 channels), channels 6,7 zero.
+hipError_t pack_input(const float* in, int in_ld, uint16_t* x, const Shape& s, hipStream_t st);
+
+// Adam over a flat f32 parameter vector, then refresh the bf16 weight copies.
+hipError_t adam_update(float* w, const float* g, float* m, float* v, long long n, float lr,
+                       float beta1, float beta2, float eps, float c1, float c2, hipStream_t st);
+hipError_t refresh_bf16(const float* w_master, uint16_t* w_fwd, uint16_t* w_dgrad, int ci, int co,
+                        hipStream_t st);
+
+// Compositor glue: NHWC denoiser input from tile-major mean / tile variance,
+// and the per-tile choice between denoised and plain mean + tonemap.
+using dfb::FrameGlue;
+hipError_t frame_to_input(const FrameGlue& g, float* in6, hipStream_t st);
+hipError_t frame_from_output(const FrameGlue& g, const float* out3, float var_threshold,
+                             float* denoised, void* final_out, uint32_t mode, float inv_gamma,
+                             hipStream_t st);
+
+}  // namespace unet
+}  // namespace dfb

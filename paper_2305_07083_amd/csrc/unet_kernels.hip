@@ -1,0 +1,646 @@
+// gfx950 kernels of the denoiser: BF16 MFMA implicit-GEMM conv3x3 forward,
+// data gradient and weight gradient (FP32 accumulation), and the small
+// elementwise / reduction kernels around them.  Every reduction has a fixed
+// order (partials per chunk, then a sequential sum), so results are
+// deterministic.
+//
+// The three convolutions are one GEMM shape, D[M][N] += A[M][K] B[K][N],
+// staged through LDS in 32-wide K slices:
+//   forward  M = pixels, N = c_out, K = (tap, c_in)   A = x[p + tap], B = W
+//   dgrad    M = pixels, N = c_in,  K = (tap, c_out)  A = dy[p - tap], B = W^T
+//   wgrad    M = c_in,   N = c_out, K = pixels (per tap, split over chunks)
+// A workgroup is 4 waves; wave w owns rows 16w..16w+15 of a 64-row tile and
+// every 16-column block of N, one v_mfma_f32_16x16x32_bf16 per block per K
+// slice.  Operand layout (checked on the device): lane l holds k =
+// (l/16)*8 .. +7 of row/column l%16; the result element r of lane l is row
+// (l/16)*4 + r, column l%16.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dfb_internal.h"
+#include "unet_internal.h"
+
+namespace dfb {
+namespace unet {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64;    // rows per workgroup tile
+constexpr int LDK = 40;   // LDS row length in bf16 (32 + 8 padding)
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__device__ __forceinline__ bf16x8 lds_frag(const uint16_t* p) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+struct Pix {
+  int n, r, c;
+  bool ok;
+};
+__device__ __forceinline__ Pix pixel_of(long long p, const Shape& s) {
+  Pix q;
+  q.ok = p < s.pixels();
+  const long long hw = static_cast<long long>(s.h) * s.w;
+  q.n = q.ok ? static_cast<int>(p / hw) : 0;
+  const int rem = q.ok ? static_cast<int>(p - q.n * hw) : 0;
+  q.r = rem / s.w;
+  q.c = rem - q.r * s.w;
+  return q;
+}
+__device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const Shape& s, bool& in) {
+  const int rr = q.r + dr, cc = q.c + dc;
+  in = q.ok && rr >= 0 && rr < s.h && cc >= 0 && cc < s.w;
+  return (static_cast<long long>(q.n) * s.h + rr) * s.w + cc;
+}
+
+// ------------------------------------------------------------- forward
+template <int BN>
+__global__ void __launch_bounds__(256) conv_fwd_k(Map x, const uint16_t* __restrict__ w,
+                                                  const float* __restrict__ bias, Map y, Shape s) {
+  __shared__ __align__(16) uint16_t As[BM * LDK];
+  __shared__ __align__(16) uint16_t Bs[BN * LDK];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long m0 = static_cast<long long>(blockIdx.x) * BM;
+  const int ap = tid >> 2, ach = (tid & 3) * 8;
+  const Pix q = pixel_of(m0 + ap, s);
+  f32x4 acc[BN / 16];
+#pragma unroll
+  for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = (x.c + 31) / 32;
+  for (int tap = 0; tap < 9; ++tap) {
+    bool in;
+    const long long src = shifted(q, tap / 3 - 1, tap % 3 - 1, s, in);
+    for (int kc = 0; kc < nk; ++kc) {
+      const int c0 = kc * 32 + ach;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (in && c0 < x.c) v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + c0);
+      *reinterpret_cast<uint4*>(As + ap * LDK + ach) = v;
+      for (int e = tid; e < BN * 4; e += 256) {
+        const int co = e >> 2, ci0 = kc * 32 + (e & 3) * 8;
+        uint4 wv = {0u, 0u, 0u, 0u};
+        if (ci0 < x.c) wv = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + co) * x.c + ci0);
+        *reinterpret_cast<uint4*>(Bs + co * LDK + (e & 3) * 8) = wv;
+      }
+      __syncthreads();
+      const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+#pragma unroll
+      for (int j = 0; j < BN / 16; ++j) {
+        const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  const long long P = s.pixels();
+#pragma unroll
+  for (int j = 0; j < BN / 16; ++j) {
+    const int col = j * 16 + (lane & 15);
+    const float bb = bias[col];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long p = m0 + wave * 16 + (lane >> 4) * 4 + r;
+      if (p < P) {
+        const float v = acc[j][r] + bb;
+        y.p[p * y.ld + y.off + col] = to_bf16(v > 0.f ? v : 0.f);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- dgrad
+// A[p][(tap, co)] = bf16(dy[p - tap][co] * (y[p - tap][co] > 0)); B = W[tap][ci][co].
+template <int BN>
+__global__ void __launch_bounds__(256) conv_dgrad_k(MapF dy, Map y, const uint16_t* __restrict__ w,
+                                                    MapF dx, Shape s) {
+  __shared__ __align__(16) uint16_t As[BM * LDK];
+  __shared__ __align__(16) uint16_t Bs[BN * LDK];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long m0 = static_cast<long long>(blockIdx.x) * BM;
+  const int ap = tid >> 2, ach = (tid & 3) * 8;
+  const Pix q = pixel_of(m0 + ap, s);
+  const int co_n = dy.c;
+  f32x4 acc[BN / 16];
+#pragma unroll
+  for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = (co_n + 31) / 32;
+  for (int tap = 0; tap < 9; ++tap) {
+    bool in;
+    const long long src = shifted(q, 1 - tap / 3, 1 - tap % 3, s, in);
+    for (int kc = 0; kc < nk; ++kc) {
+      const int c0 = kc * 32 + ach;
+      uint16_t hv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) hv[i] = 0;
+      if (in && c0 < co_n) {
+        const float4 g0 = *reinterpret_cast<const float4*>(dy.p + src * dy.ld + dy.off + c0);
+        const float4 g1 = *reinterpret_cast<const float4*>(dy.p + src * dy.ld + dy.off + c0 + 4);
+        const uint4 mk = *reinterpret_cast<const uint4*>(y.p + src * y.ld + y.off + c0);
+        const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+        const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const uint16_t yh = static_cast<uint16_t>(mw[i >> 1] >> ((i & 1) * 16));
+          hv[i] = to_bf16(from_bf16(yh) > 0.f ? gv[i] : 0.f);
+        }
+      }
+      uint4 pk;
+      pk.x = hv[0] | (static_cast<uint32_t>(hv[1]) << 16);
+      pk.y = hv[2] | (static_cast<uint32_t>(hv[3]) << 16);
+      pk.z = hv[4] | (static_cast<uint32_t>(hv[5]) << 16);
+      pk.w = hv[6] | (static_cast<uint32_t>(hv[7]) << 16);
+      *reinterpret_cast<uint4*>(As + ap * LDK + ach) = pk;
+      for (int e = tid; e < BN * 4; e += 256) {
+        const int ci = e >> 2, k0 = kc * 32 + (e & 3) * 8;
+        uint4 wv = {0u, 0u, 0u, 0u};
+        if (k0 < co_n) wv = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + ci) * co_n + k0);
+        *reinterpret_cast<uint4*>(Bs + ci * LDK + (e & 3) * 8) = wv;
+      }
+      __syncthreads();
+      const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+#pragma unroll
+      for (int j = 0; j < BN / 16; ++j) {
+        const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  const long long P = s.pixels();
+#pragma unroll
+  for (int j = 0; j < BN / 16; ++j) {
+    const int col = j * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long p = m0 + wave * 16 + (lane >> 4) * 4 + r;
+      if (p < P) dx.p[p * dx.ld + dx.off + col] = acc[j][r];
+    }
+  }
+}
+
+// ------------------------------------------------------------- wgrad
+// Per tap and 64-wide c_in tile, over one chunk of pixels:
+// partial[chunk][tap][ci][co] = sum_p x[p + tap][ci] * bf16(dy[p][co] * (y > 0)).
+constexpr int kWgradChunk = 2048;
+
+template <int BN>
+__global__ void __launch_bounds__(256) conv_wgrad_k(Map x, MapF dy, Map y, float* __restrict__ partial,
+                                                    Shape s) {
+  __shared__ __align__(16) uint16_t As[BM * LDK];   // [ci][px]
+  __shared__ __align__(16) uint16_t Bs[BN * LDK];   // [co][px]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int chunk = blockIdx.x, tap = blockIdx.y, ci0 = blockIdx.z * BM;
+  const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+  const long long P = s.pixels();
+  const long long p_begin = static_cast<long long>(chunk) * kWgradChunk;
+  f32x4 acc[BN / 16];
+#pragma unroll
+  for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int px = tid >> 3;                 // 0..31: pixel of the K slice this thread stages
+  const int a8 = (tid & 7) * 8;            // 8 c_in values
+  constexpr int BPER = BN / 8;             // c_out values per thread
+  const int b0 = (tid & 7) * BPER;
+  for (int k0 = 0; k0 < kWgradChunk; k0 += 32) {
+    const long long p = p_begin + k0 + px;
+    const Pix q = pixel_of(p, s);
+    bool in;
+    const long long src = shifted(q, dr, dc, s, in);
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (in && ci0 + a8 < x.c) v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + ci0 + a8);
+    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) As[(a8 + i) * LDK + px] = static_cast<uint16_t>(vw[i >> 1] >> ((i & 1) * 16));
+#pragma unroll
+    for (int i = 0; i < BPER; ++i) {
+      float g = 0.f;
+      if (q.ok) {
+        const long long o = p * dy.ld + dy.off + b0 + i;
+        const uint16_t yh = y.p[p * y.ld + y.off + b0 + i];
+        g = from_bf16(yh) > 0.f ? dy.p[o] : 0.f;
+      }
+      Bs[(b0 + i) * LDK + px] = to_bf16(g);
+    }
+    __syncthreads();
+    const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+#pragma unroll
+    for (int j = 0; j < BN / 16; ++j) {
+      const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (p_begin + k0 + 32 >= P) break;
+  }
+  const int ci_n = x.c;
+#pragma unroll
+  for (int j = 0; j < BN / 16; ++j) {
+    const int co = j * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ci = ci0 + wave * 16 + (lane >> 4) * 4 + r;
+      if (ci < ci_n)
+        partial[((static_cast<size_t>(chunk) * 9 + tap) * ci_n + ci) * BN + co] = acc[j][r];
+    }
+  }
+}
+
+// dw[tap][ci][co] (ci < ci_out) = sum over chunks, in chunk order.
+__global__ void __launch_bounds__(256) wgrad_reduce_k(const float* __restrict__ partial, float* __restrict__ dw,
+                                                      int chunks, int ci_n, int ci_out, int co_n) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long total = 9LL * ci_out * co_n;
+  if (e >= total) return;
+  const int co = static_cast<int>(e % co_n);
+  const int ci = static_cast<int>((e / co_n) % ci_out);
+  const int tap = static_cast<int>(e / (static_cast<long long>(co_n) * ci_out));
+  float sum = 0.f;
+  for (int c = 0; c < chunks; ++c) sum += partial[((static_cast<size_t>(c) * 9 + tap) * ci_n + ci) * co_n + co];
+  dw[e] = sum;
+}
+
+// db[co] partials per chunk: sum over the chunk's pixels in order.
+__global__ void __launch_bounds__(128) bias_partial_k(MapF dy, Map y, float* __restrict__ partial, Shape s) {
+  const int co = threadIdx.x, chunk = blockIdx.x;
+  if (co >= dy.c) return;
+  const long long P = s.pixels();
+  const long long p0 = static_cast<long long>(chunk) * kWgradChunk;
+  const long long p1 = p0 + kWgradChunk < P ? p0 + kWgradChunk : P;
+  float sum = 0.f;
+  for (long long p = p0; p < p1; ++p) {
+    const uint16_t yh = y.p[p * y.ld + y.off + co];
+    sum += from_bf16(yh) > 0.f ? dy.p[p * dy.ld + dy.off + co] : 0.f;
+  }
+  partial[static_cast<size_t>(chunk) * dy.c + co] = sum;
+}
+
+__global__ void __launch_bounds__(128) chunk_reduce_k(const float* __restrict__ partial, float* __restrict__ out,
+                                                      int chunks, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float sum = 0.f;
+  for (int c = 0; c < chunks; ++c) sum += partial[static_cast<size_t>(c) * n + i];
+  out[i] = sum;
+}
+
+// ------------------------------------------------------------- glue kernels
+__global__ void avgpool2_k(Map x, Map y, Shape so) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long total = so.pixels() * x.c;
+  if (e >= total) return;
+  const int ch = static_cast<int>(e % x.c);
+  const long long p = e / x.c;
+  const Pix q = pixel_of(p, so);
+  const int wi = so.w * 2, hi = so.h * 2;
+  const long long b = (static_cast<long long>(q.n) * hi + 2 * q.r) * wi + 2 * q.c;
+  const float v = from_bf16(x.p[b * x.ld + x.off + ch]) + from_bf16(x.p[(b + 1) * x.ld + x.off + ch]) +
+                  from_bf16(x.p[(b + wi) * x.ld + x.off + ch]) + from_bf16(x.p[(b + wi + 1) * x.ld + x.off + ch]);
+  y.p[p * y.ld + y.off + ch] = to_bf16(0.25f * v);
+}
+
+__global__ void avgpool2_bwd_add_k(MapF dy, MapF dx, Shape si) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long total = si.pixels() * dx.c;
+  if (e >= total) return;
+  const int ch = static_cast<int>(e % dx.c);
+  const long long p = e / dx.c;
+  const Pix q = pixel_of(p, si);
+  const long long po = (static_cast<long long>(q.n) * (si.h / 2) + q.r / 2) * (si.w / 2) + q.c / 2;
+  dx.p[p * dx.ld + dx.off + ch] += 0.25f * dy.p[po * dy.ld + dy.off + ch];
+}
+
+__global__ void upsample2_k(Map x, Map y, Shape si) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  Shape so{si.n, si.h * 2, si.w * 2};
+  const long long total = so.pixels() * x.c;
+  if (e >= total) return;
+  const int ch = static_cast<int>(e % x.c);
+  const long long p = e / x.c;
+  const Pix q = pixel_of(p, so);
+  const long long pi = (static_cast<long long>(q.n) * si.h + q.r / 2) * si.w + q.c / 2;
+  y.p[p * y.ld + y.off + ch] = x.p[pi * x.ld + x.off + ch];
+}
+
+__global__ void upsample2_bwd_k(MapF dy, MapF dx, Shape si) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long total = si.pixels() * dx.c;
+  if (e >= total) return;
+  const int ch = static_cast<int>(e % dx.c);
+  const long long p = e / dx.c;
+  const Pix q = pixel_of(p, si);
+  const int wo = si.w * 2;
+  const long long b = (static_cast<long long>(q.n) * si.h * 2 + 2 * q.r) * wo + 2 * q.c;
+  float v = dy.p[b * dy.ld + dy.off + ch];
+  v += dy.p[(b + 1) * dy.ld + dy.off + ch];
+  v += dy.p[(b + wo) * dy.ld + dy.off + ch];
+  v += dy.p[(b + wo + 1) * dy.ld + dy.off + ch];
+  dx.p[p * dx.ld + dx.off + ch] = v;
+}
+
+__global__ void add_into_k(MapF src, MapF dst, Shape s) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long total = s.pixels() * dst.c;
+  if (e >= total) return;
+  const int ch = static_cast<int>(e % dst.c);
+  const long long p = e / dst.c;
+  dst.p[p * dst.ld + dst.off + ch] += src.p[p * src.ld + src.off + ch];
+}
+
+__global__ void out_fwd_k(Map x, const float* __restrict__ w, const float* __restrict__ b,
+                          const float* __restrict__ base, int base_ld, float* __restrict__ out, Shape s) {
+  const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= s.pixels()) return;
+  float o0 = base[p * base_ld] + b[0], o1 = base[p * base_ld + 1] + b[1], o2 = base[p * base_ld + 2] + b[2];
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int i = 0; i < x.c; ++i) {
+    const float xi = from_bf16(x.p[p * x.ld + x.off + i]);
+    a0 = fmaf(xi, w[i * 3 + 0], a0);
+    a1 = fmaf(xi, w[i * 3 + 1], a1);
+    a2 = fmaf(xi, w[i * 3 + 2], a2);
+  }
+  out[p * 3 + 0] = o0 + a0;
+  out[p * 3 + 1] = o1 + a1;
+  out[p * 3 + 2] = o2 + a2;
+}
+
+// Per pixel: dout = 2 (out - t) / count; dx = dout w^T.  Per chunk of pixels
+// (in order): partial[chunk] = {dw[ci][3], db[3], sum (out - t)^2}.
+constexpr int kOutChunk = 1024;
+__global__ void __launch_bounds__(64) out_bwd_k(Map x, const float* __restrict__ out, const float* __restrict__ tgt,
+                                                const float* __restrict__ w, MapF dx, float* __restrict__ partial,
+                                                Shape s, float scale) {
+  // one workgroup (one wave) per chunk; lane i < ci accumulates dw[i][*]
+  const int chunk = blockIdx.x, lane = threadIdx.x;
+  const long long P = s.pixels();
+  const long long p0 = static_cast<long long>(chunk) * kOutChunk;
+  const long long p1 = p0 + kOutChunk < P ? p0 + kOutChunk : P;
+  const int ci = x.c;
+  float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, ls = 0.f;
+  for (long long p = p0; p < p1; ++p) {
+    const float e0 = out[p * 3] - tgt[p * 3], e1 = out[p * 3 + 1] - tgt[p * 3 + 1], e2 = out[p * 3 + 2] - tgt[p * 3 + 2];
+    const float g0 = scale * e0, g1 = scale * e1, g2 = scale * e2;
+    if (lane < ci) {
+      const float xi = from_bf16(x.p[p * x.ld + x.off + lane]);
+      dw0 = fmaf(xi, g0, dw0);
+      dw1 = fmaf(xi, g1, dw1);
+      dw2 = fmaf(xi, g2, dw2);
+      dx.p[p * dx.ld + dx.off + lane] = g0 * w[lane * 3] + g1 * w[lane * 3 + 1] + g2 * w[lane * 3 + 2];
+    }
+    db0 += g0;
+    db1 += g1;
+    db2 += g2;
+    ls = fmaf(e0, e0, ls);
+    ls = fmaf(e1, e1, ls);
+    ls = fmaf(e2, e2, ls);
+  }
+  const int n = ci * 3 + 4;
+  float* q = partial + static_cast<size_t>(chunk) * n;
+  if (lane < ci) {
+    q[lane * 3] = dw0;
+    q[lane * 3 + 1] = dw1;
+    q[lane * 3 + 2] = dw2;
+  }
+  if (lane == 0) {
+    q[ci * 3] = db0;
+    q[ci * 3 + 1] = db1;
+    q[ci * 3 + 2] = db2;
+    q[ci * 3 + 3] = ls;
+  }
+}
+
+__global__ void pack_input_k(const float* __restrict__ in, int in_ld, uint16_t* __restrict__ x, long long P) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= P * 8) return;
+  const long long p = e >> 3;
+  const int ch = static_cast<int>(e & 7);
+  x[e] = ch < 6 ? to_bf16(in[p * in_ld + ch]) : static_cast<uint16_t>(0);
+}
+
+__global__ void adam_k(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// master [9][ci][co] -> fwd [9][co][ci_pad] and dgrad [9][ci_pad][co] (bf16,
+// channels ci..ci_pad-1 zero)
+__global__ void refresh_k(const float* __restrict__ wm, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd,
+                          int ci, int ci_pad, int co) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 9 * ci_pad * co) return;
+  const int o = e % co, i = (e / co) % ci_pad, t = e / (co * ci_pad);
+  const uint16_t h = i < ci ? to_bf16(wm[(static_cast<size_t>(t) * ci + i) * co + o]) : static_cast<uint16_t>(0);
+  wd[(static_cast<size_t>(t) * ci_pad + i) * co + o] = h;
+  wf[(static_cast<size_t>(t) * co + o) * ci_pad + i] = h;
+}
+
+// ------------------------------------------------------------- frame glue
+__global__ void frame_to_input_k(FrameGlue g, float* __restrict__ in6) {
+  const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long P = static_cast<long long>(g.width) * g.height;
+  if (p >= P) return;
+  const int y = static_cast<int>(p / g.width), x = static_cast<int>(p - static_cast<long long>(y) * g.width);
+  const int t = (y / g.tile_h) * g.tiles_x + x / g.tile_w;
+  const int q = (y % g.tile_h) * g.tile_w + x % g.tile_w;
+  const float4 mu = reinterpret_cast<const float4*>(g.accum)[static_cast<size_t>(t) * g.P + q];
+  const float v = g.tile_var[t];
+  float* o = in6 + p * 6;
+  o[0] = mu.x;
+  o[1] = mu.y;
+  o[2] = mu.z;
+  o[3] = mu.w;
+  o[4] = g.n_acc >= 2 ? logf(v > 1e-12f ? v : 1e-12f) : 0.f;
+  o[5] = 1.f / static_cast<float>(g.n_acc);
+}
+
+__device__ __forceinline__ uint32_t q8(float x, bool gamma, float inv_gamma) {
+  float y = x > 0.f ? x : 0.f;
+  y = y < 1.f ? y : 1.f;
+  if (gamma) y = powf(y, inv_gamma);
+  return static_cast<uint32_t>(floorf(fmaf(255.f, y, 0.5f)));
+}
+
+__global__ void frame_from_output_k(FrameGlue g, const float* __restrict__ out3, float tau,
+                                    float* __restrict__ den, void* final_out, uint32_t mode, float inv_gamma) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int T = g.tiles_x * ((g.height + g.tile_h - 1) / g.tile_h);
+  if (e >= static_cast<long long>(T) * g.P) return;
+  const int t = static_cast<int>(e / g.P), q = static_cast<int>(e - static_cast<long long>(t) * g.P);
+  const int x = (t % g.tiles_x) * g.tile_w + q % g.tile_w;
+  const int y = (t / g.tiles_x) * g.tile_h + q / g.tile_w;
+  float4 v = reinterpret_cast<const float4*>(g.accum)[e];
+  const float var = g.tile_var[t];
+  const bool fallback = g.n_acc >= 2 && var > tau;   // measured and too noisy: plain mean
+  if (!fallback && x < g.width && y < g.height) {
+    const long long p = static_cast<long long>(y) * g.width + x;
+    v.x = out3[p * 3];
+    v.y = out3[p * 3 + 1];
+    v.z = out3[p * 3 + 2];
+  }
+  if (den) reinterpret_cast<float4*>(den)[e] = v;
+  if (mode & kModeFmtRGBA8) {
+    const bool gm = (mode & kModeGamma) != 0;
+    static_cast<uint32_t*>(final_out)[e] = q8(v.x, gm, inv_gamma) | (q8(v.y, gm, inv_gamma) << 8) |
+                                           (q8(v.z, gm, inv_gamma) << 16) | (q8(v.w, false, 1.f) << 24);
+  } else if (mode & kModeFmtF32) {
+    static_cast<float4*>(final_out)[e] = v;
+  }
+}
+
+inline unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y, const Shape& s,
+                       hipStream_t st) {
+  const unsigned g = blocks(s.pixels(), BM);
+  if (x.c % 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
+  switch (y.c) {
+    case 32: conv_fwd_k<32><<<g, 256, 0, st>>>(x, w_fwd, bias, y, s); break;
+    case 64: conv_fwd_k<64><<<g, 256, 0, st>>>(x, w_fwd, bias, y, s); break;
+    case 128: conv_fwd_k<128><<<g, 256, 0, st>>>(x, w_fwd, bias, y, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, const MapF& dx, const Shape& s,
+                         hipStream_t st) {
+  const unsigned g = blocks(s.pixels(), BM);
+  if (dy.c % 8 || dy.ld % 4 || dy.off % 4 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
+  switch (dx.c) {
+    case 32: conv_dgrad_k<32><<<g, 256, 0, st>>>(dy, y, w_dgrad, dx, s); break;
+    case 64: conv_dgrad_k<64><<<g, 256, 0, st>>>(dy, y, w_dgrad, dx, s); break;
+    case 128: conv_dgrad_k<128><<<g, 256, 0, st>>>(dy, y, w_dgrad, dx, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t conv3x3_wgrad_scratch(int ci, int co, const Shape& s) {
+  const long long chunks = (s.pixels() + kWgradChunk - 1) / kWgradChunk;
+  return static_cast<size_t>(chunks) * 9 * ci * co;
+}
+
+hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, float* db, float* partial,
+                         const Shape& s, hipStream_t st, int ci_out) {
+  const int chunks = static_cast<int>((s.pixels() + kWgradChunk - 1) / kWgradChunk);
+  if (x.c % 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
+  dim3 grid(chunks, 9, (x.c + BM - 1) / BM);
+  switch (dy.c) {
+    case 32: conv_wgrad_k<32><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
+    case 64: conv_wgrad_k<64><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
+    case 128: conv_wgrad_k<128><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  wgrad_reduce_k<<<blocks(9LL * ci_out * dy.c, 256), 256, 0, st>>>(partial, dw, chunks, x.c, ci_out, dy.c);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // bias partials reuse the front of the scratch (the weight sums are done)
+  bias_partial_k<<<chunks, 128, 0, st>>>(dy, y, partial, s);
+  chunk_reduce_k<<<1, 128, 0, st>>>(partial, db, chunks, dy.c);
+  return hipGetLastError();
+}
+
+hipError_t avgpool2(const Map& x, const Map& y, const Shape& s_in, hipStream_t st) {
+  Shape so{s_in.n, s_in.h / 2, s_in.w / 2};
+  avgpool2_k<<<blocks(so.pixels() * x.c, 256), 256, 0, st>>>(x, y, so);
+  return hipGetLastError();
+}
+hipError_t avgpool2_backward_add(const MapF& dy, const MapF& dx, const Shape& s_in, hipStream_t st) {
+  avgpool2_bwd_add_k<<<blocks(s_in.pixels() * dx.c, 256), 256, 0, st>>>(dy, dx, s_in);
+  return hipGetLastError();
+}
+hipError_t upsample2(const Map& x, const Map& y, const Shape& s_in, hipStream_t st) {
+  upsample2_k<<<blocks(s_in.pixels() * 4 * x.c, 256), 256, 0, st>>>(x, y, s_in);
+  return hipGetLastError();
+}
+hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in, hipStream_t st) {
+  upsample2_bwd_k<<<blocks(s_in.pixels() * dx.c, 256), 256, 0, st>>>(dy, dx, s_in);
+  return hipGetLastError();
+}
+hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st) {
+  add_into_k<<<blocks(s.pixels() * dst.c, 256), 256, 0, st>>>(src, dst, s);
+  return hipGetLastError();
+}
+
+hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base, int base_ld, float* out,
+                        const Shape& s, hipStream_t st) {
+  out_fwd_k<<<blocks(s.pixels(), 256), 256, 0, st>>>(x, w, b, base, base_ld, out, s);
+  return hipGetLastError();
+}
+
+size_t out_conv_scratch(const Shape& s) {  // per-chunk partials + their sum
+  const long long chunks = (s.pixels() + kOutChunk - 1) / kOutChunk;
+  return static_cast<size_t>(chunks + 1) * (32 * 3 + 4);
+}
+
+hipError_t out_conv_backward(const Map& x, const float* out, const float* target, const float* w, const MapF& dx,
+                             float* dw, float* db, float* loss, float* partial, const Shape& s, hipStream_t st) {
+  if (x.c > 64) return hipErrorInvalidValue;
+  const int chunks = static_cast<int>((s.pixels() + kOutChunk - 1) / kOutChunk);
+  const float scale = 2.f / static_cast<float>(s.pixels() * 3);
+  out_bwd_k<<<chunks, 64, 0, st>>>(x, out, target, w, dx, partial, s, scale);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = x.c * 3 + 4;
+  // dw (ci*3), db (3) and the loss sum are consecutive in each partial row
+  chunk_reduce_k<<<blocks(n, 128), 128, 0, st>>>(partial, partial + static_cast<size_t>(chunks) * n, chunks, n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const float* red = partial + static_cast<size_t>(chunks) * n;
+  e = hipMemcpyAsync(dw, red, sizeof(float) * x.c * 3, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(db, red + x.c * 3, sizeof(float) * 3, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(loss, red + x.c * 3 + 3, sizeof(float), hipMemcpyDeviceToDevice, st);
+}
+
+hipError_t pack_input(const float* in, int in_ld, uint16_t* x, const Shape& s, hipStream_t st) {
+  pack_input_k<<<blocks(s.pixels() * 8, 256), 256, 0, st>>>(in, in_ld, x, s.pixels());
+  return hipGetLastError();
+}
+
+hipError_t adam_update(float* w, const float* g, float* m, float* v, long long n, float lr, float beta1, float beta2,
+                       float eps, float c1, float c2, hipStream_t st) {
+  adam_k<<<blocks(n, 256), 256, 0, st>>>(w, g, m, v, n, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t refresh_bf16(const float* w_master, uint16_t* w_fwd, uint16_t* w_dgrad, int ci, int co, hipStream_t st) {
+  const int ci_pad = (ci + 7) / 8 * 8;
+  refresh_k<<<blocks(9LL * ci_pad * co, 256), 256, 0, st>>>(w_master, w_fwd, w_dgrad, ci, ci_pad, co);
+  return hipGetLastError();
+}
+
+hipError_t frame_to_input(const FrameGlue& g, float* in6, hipStream_t st) {
+  frame_to_input_k<<<blocks(static_cast<long long>(g.width) * g.height, 256), 256, 0, st>>>(g, in6);
+  return hipGetLastError();
+}
+
+hipError_t frame_from_output(const FrameGlue& g, const float* out3, float var_threshold, float* denoised,
+                             void* final_out, uint32_t mode, float inv_gamma, hipStream_t st) {
+  const long long T = static_cast<long long>(g.tiles_x) * ((g.height + g.tile_h - 1) / g.tile_h);
+  frame_from_output_k<<<blocks(T * g.P, 256), 256, 0, st>>>(g, out3, var_threshold, denoised, final_out, mode,
+                                                            inv_gamma);
+  return hipGetLastError();
+}
+
+}  // namespace unet
+}  // namespace dfb
