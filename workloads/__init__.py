@@ -233,10 +233,29 @@ def brick_frame(width, height, bricks=(4, 4, 4), tile=64, seed=0, azimuth=30.0, 
     return Frame(width, height, tile, tile, frag, layers, expected, covered, name)
 
 
+_BETA25_U = None
+_BETA25_Q = None
+
+
+def _beta25_ppf(u):
+    """Beta(2,5) quantile by interpolation in a dense table of its CDF
+    (F(x) = 1 - (1-x)^5 (1 + 5x), closed form for integer parameters)."""
+    global _BETA25_U, _BETA25_Q
+    if _BETA25_U is None:
+        x = np.linspace(0.0, 1.0, 1 << 16)
+        _BETA25_U = 1.0 - (1.0 - x) ** 5 * (1.0 + 5.0 * x)
+        _BETA25_Q = x
+    return np.interp(u, _BETA25_U, _BETA25_Q)
+
+
 def _smooth_fields(rng, pairs, n_bricks, tiles_x, tile, Wp, Hp, length_px):
     """Per-brick spatially correlated alpha (Beta(2,5) marginal) and U
-    (uniform marginal): Gaussian copula of a filtered white field."""
-    from scipy import ndimage, special, stats
+    (uniform marginal): a Gaussian copula of white noise filtered with a
+    Gaussian of standard deviation ``length_px`` pixels.  The noise is drawn
+    on a grid 8x coarser than the pixels over the brick's tile bounding box,
+    filtered there and interpolated bilinearly, then rescaled to unit
+    variance.  Draw order: per brick (ascending), 4 coarse normal fields."""
+    from scipy import ndimage, special
     P = tile * tile
     L = len(pairs)
     alpha = np.empty((L, P), dtype=np.float32)
@@ -244,19 +263,27 @@ def _smooth_fields(rng, pairs, n_bricks, tiles_x, tile, Wp, Hp, length_px):
     by_brick = {}
     for i, (t, b) in enumerate(pairs):
         by_brick.setdefault(b, []).append((i, t))
+    f = 8
     for b in range(n_bricks):
+        items = by_brick.get(b)
+        if not items:
+            continue
+        tys = [t // tiles_x for _, t in items]
+        txs = [t % tiles_x for _, t in items]
+        y0, y1 = min(tys) * tile, (max(tys) + 1) * tile
+        x0, x1 = min(txs) * tile, (max(txs) + 1) * tile
+        hc, wc = (y1 - y0) // f + 2, (x1 - x0) // f + 2
         fields = []
         for _ in range(4):
-            w = rng.standard_normal((Hp, Wp))
-            f = ndimage.gaussian_filter(w, length_px, mode="wrap")
-            f /= f.std()
-            fields.append(special.ndtr(f))               # uniform marginal
-        if b not in by_brick:
-            continue
-        a_img = stats.beta.ppf(np.clip(fields[0], 1e-12, 1 - 1e-12), 2.0, 5.0)
-        for i, t in by_brick[b]:
+            w = rng.standard_normal((hc, wc))
+            g = ndimage.gaussian_filter(w, length_px / f, mode="wrap")
+            up = ndimage.zoom(g, f, order=1)[: y1 - y0, : x1 - x0]
+            up = (up - up.mean()) / up.std()
+            fields.append(special.ndtr(up))
+        a_img = _beta25_ppf(fields[0])
+        for i, t in items:
             ty, tx = divmod(t, tiles_x)
-            win = (slice(ty * tile, (ty + 1) * tile), slice(tx * tile, (tx + 1) * tile))
+            win = (slice(ty * tile - y0, (ty + 1) * tile - y0), slice(tx * tile - x0, (tx + 1) * tile - x0))
             alpha[i] = a_img[win].reshape(P)
             for c in range(3):
                 U[i, c] = fields[1 + c][win].reshape(P)
@@ -276,6 +303,13 @@ def c2(seed=0, width=2048, height=2048):
 def c3(seed=0, width=4096, height=1024):
     """4096x1024 frame, 8x8x4 bricks (256 ranks)."""
     return brick_frame(width, height, (8, 8, 4), 64, seed, name="%dx%d 8x8x4 bricks" % (width, height))
+
+
+def c5(seed=0, width=2048, height=2048, azimuth=30.0, elevation=25.0):
+    """Denoiser scenes: the 4x4x4-brick geometry with spatially correlated
+    alpha and colour fields (correlation length 16 px)."""
+    return brick_frame(width, height, (4, 4, 4), 64, seed, azimuth, elevation,
+                       name="%dx%d 4x4x4 bricks, smooth fields" % (width, height), smooth_px=16.0)
 
 
 # --------------------------------------------------------------------------
@@ -350,3 +384,27 @@ def uniform_values_torch(n_blocks, P, seed, device, dtype=None, chunk_blocks=409
         out[b0:b1, 3] = a.to(dtype)
         out[b0:b1, 4] = dpt.to(dtype)
     return out
+
+
+class DeviceNoise:
+    """Progressive frames drawn on the device: colour = base + N(0, sigma) per
+    covered fragment and RGB channel, i.i.d. per frame, from a seeded
+    ``torch.Generator`` (one normal draw of shape [L, 3, P] per frame, in
+    frame order)."""
+
+    def __init__(self, frame: Frame, sigma, seed, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.base = torch.from_numpy(frame.frag.astype(np.float32)).to(device)
+        self.mask = torch.from_numpy(frame.covered).to(device).unsqueeze(1).to(torch.float32) * float(sigma)
+        self.gen = torch.Generator(device=device)
+        self.gen.manual_seed(seed)
+        self.out = torch.empty_like(self.base)
+
+    def next(self):
+        torch = self.torch
+        self.out.copy_(self.base)
+        noise = torch.randn(self.base[:, 0:3, :].shape, generator=self.gen, device=self.base.device,
+                            dtype=torch.float32)
+        self.out[:, 0:3, :] += noise * self.mask
+        return self.out
