@@ -7,7 +7,11 @@ per-tile variance and RGBA8 tonemapping.  Inputs are resident in HBM before
 the timed region; four copies rotate so the 555 MB working set cannot stay in
 the 256 MB last-level cache.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3f16|c1] [--no-cpu]
+The line also carries the learned part of the metric ("denoise"): frames to
+reach the 64-frame plain PSNR with the denoiser, trained on the GPU by the
+library's own kernels on compositor-generated pairs.
+
+  python bench.py [--steps K] [--warmup W] [--workload c2|c3|c3f16|c1] [--no-cpu] [--no-denoise]
 """
 import argparse
 import json
@@ -31,6 +35,10 @@ def parse():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain", action="store_true", help="composite only (no accumulation)")
+    ap.add_argument("--no-denoise", action="store_true",
+                    help="skip training / evaluating the denoiser (frames-to-PSNR part of the metric)")
+    ap.add_argument("--denoise-scenes", type=int, default=8)
+    ap.add_argument("--denoise-steps", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device to device (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -66,6 +74,45 @@ def measured_traffic(workload, accumulate):
     fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
     write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
     return (fetch + write) * 1024.0
+
+
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def denoiser_flops_per_pixel():
+    """Multiply-adds x 2 of one forward pass per full-resolution pixel."""
+    import paper_2305_07083_amd as dfb
+    f = sum(2 * 9 * ci * co / 4 ** lvl for _, ci, co, lvl in dfb.UNET_CONV3)
+    return f + 2 * 32 * 3
+
+
+def denoise_leg(scenes, steps):
+    """Frames-to-PSNR of the learned denoiser vs plain accumulation on the
+    2048x2048 smooth-field brick scene (sigma 0.2): train on compositor pairs
+    from ``scenes`` other views, evaluate on the 30/25 view.  PSNR reference:
+    the noise-free composite from the GPU compositor (the limit of the
+    accumulation; the tests pin it to the FP64 oracle)."""
+    from paper_2305_07083_amd import denoise_train as dt
+    res, net, test = dt.run(scenes=scenes, steps=steps, log=lambda m: print(m, file=sys.stderr, flush=True))
+    net.close()
+    flops = denoiser_flops_per_pixel() * test.width * test.height
+    tflops = flops / (res["ms_denoise_only"] * 1e-3) / 1e12
+    return {
+        "workload": "2048x2048 frame, 4x4x4 bricks, spatially correlated alpha/colour (16 px), colour noise "
+                    "sigma 0.2; 3-level U-Net, 32 base channels, BF16 MFMA, FP32 accumulate",
+        "plain_psnr_db": {int(k): v for k, v in res["plain"].items()},
+        "denoised_psnr_db": {int(k): v for k, v in res["denoised"].items()},
+        "frames_to_psnr": res["frames_to_psnr"],
+        "target": "denoised PSNR >= plain PSNR after 64 frames",
+        "ms_64_plain_frames": res["ms_plain"],
+        "ms_n_frames_plus_denoise": {int(k): v for k, v in res["ms_denoised"].items()},
+        "ms_denoise_forward": res["ms_denoise_only"],
+        "denoise_roofline": {"bound": "mfma", "achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tflops / BF16_PEAK_TFLOPS, "flops_per_launch": flops},
+        "fallback_tiles": {int(k): v for k, v in res["fallback_tiles"].items()},
+        "train": {"scenes": scenes, "steps": steps, "batch": res["batch"], "crop": res["crop"],
+                  "seconds": res["train_seconds"], "final_loss": res["loss_curve"][-1][1]},
+    }
 
 
 def make_frame(name):
@@ -196,6 +243,8 @@ def main():
         torch.cuda.synchronize()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(f, accumulate)
+    if not args.no_denoise and args.workload == "c2":
+        out["denoise"] = denoise_leg(args.denoise_scenes, args.denoise_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -44,8 +44,11 @@ def make_scenes(seeds, size=2048, rng_seed=1000, processes=8, test_view=False):
         az, el = float(rng.uniform(0, 360)), float(rng.uniform(10, 60))
         jobs.append((s, 30.0, 25.0, size) if test_view else (s, az, el, size))
     if processes > 1 and len(jobs) > 1:
+        # fresh interpreters (spawn): the caller may already hold a GPU context
+        import multiprocessing
         from concurrent.futures import ProcessPoolExecutor
-        with ProcessPoolExecutor(min(processes, len(jobs))) as ex:
+        ctx = multiprocessing.get_context("spawn")
+        with ProcessPoolExecutor(min(processes, len(jobs)), mp_context=ctx) as ex:
             return list(ex.map(_scene, jobs))
     return [_scene(j) for j in jobs]
 
