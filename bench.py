@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3f16"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3f16", "c4"])
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain", action="store_true", help="composite only (no accumulation)")
@@ -115,9 +115,37 @@ def denoise_leg(scenes, steps):
     }
 
 
+class DeviceFrame:
+    """The 8192x8192 heavy-tailed frame: layer list on the host, fragment
+    values drawn on the device (57.6 GB fp32 does not fit host memory)."""
+
+    def __init__(self):
+        import workloads
+        self.width = self.height = 8192
+        self.tile_w = self.tile_h = 128
+        self.layers, K = workloads.zipf_layout(8192, 8192, 128, 512, 1.2, 512, seed=0)
+        self.expected = K.astype("int32")
+        self.frag = None
+
+    @property
+    def n_tiles(self):
+        return 64 * 64
+
+    @property
+    def P(self):
+        return 128 * 128
+
+    @property
+    def n_fragments(self):
+        return len(self.layers) * self.P
+
+
 def make_frame(name):
     import numpy as np
     import workloads
+    if name == "c4":
+        return DeviceFrame(), ("8192x8192 frame, 128x128 tiles, 512 ranks, truncated Zipf(1.2) layers per tile "
+                               "(1..512), fp32, work unit and waves autotuned")
     if name == "c1":
         f = workloads.c1()
         desc = "256x256 frame, 64x64 tiles, 4 ranks on every tile, fp32"
@@ -177,14 +205,19 @@ def main():
     dfb.load()
     f, desc = make_frame(args.workload)
     dev = torch.device("cuda:0")
-    copies = [torch.from_numpy(f.frag).to(dev) for _ in range(max(1, args.copies))]
+    if args.workload == "c4":
+        import workloads
+        copies = [workloads.uniform_values_torch(len(f.layers), f.P, seed=0, device=dev)]
+        f16 = False
+    else:
+        copies = [torch.from_numpy(f.frag).to(dev) for _ in range(max(1, args.copies))]
+        f16 = f.frag.dtype == np.float16
     torch.cuda.synchronize()
-    f16 = f.frag.dtype == np.float16
     cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=0, waves=0,
                           dtype=dfb.DFB_F16 if f16 else dfb.DFB_F32, fmt=dfb.DFB_FMT_RGBA8)
     stream = torch.cuda.current_stream().cuda_stream
     accumulate = not args.plain
-    n_blocks = f.frag.shape[0]
+    n_blocks = copies[0].shape[0]
     with dfb.Compositor(cfg, stream) as c:
         c.set_fragments(copies[0], n_blocks, f.layers, f.expected)
         c.composite(accumulate=False)     # first frame of a new layout: autotunes the launch shape
@@ -241,7 +274,7 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "c4":
         out["cpu_baseline"] = cpu_baseline(f, accumulate)
     if not args.no_denoise and args.workload == "c2":
         out["denoise"] = denoise_leg(args.denoise_scenes, args.denoise_steps)

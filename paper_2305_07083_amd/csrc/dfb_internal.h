@@ -14,8 +14,9 @@ constexpr int kRegMax = 32;
 // Largest layer count per tile the LDS sort supports (keys + weights of one
 // pixel must fit the LDS budget below).
 constexpr int kMaxLayers = 4096;
-// LDS bytes the large-K path uses for keys (u64) and weights (f32).
-constexpr int kBigLdsBytes = 64 * 1024;
+// Largest LDS budget of the large-K path for keys (u64) and weights (f32);
+// the host passes 64, 96 or 112 KB depending on the frame's largest tile.
+constexpr int kBigLdsBytes = 112 * 1024;
 
 enum ModeBits : uint32_t {
   kModeAccumulate = 1u,     // fold into the running mean + per-tile variance
@@ -43,6 +44,7 @@ struct FrameArgs {
   int32_t tile_w, tile_h, P;
   int32_t work_w, work_h, subs_x, subs_per_tile, work_px;
   int32_t work_shift;          // log2(work_w) if a power of two, else -1
+  int32_t big_lds;             // LDS bytes for keys + weights of the K > 32 path
   float bg[4];
   float inv_gamma;
   uint32_t mode;
@@ -107,7 +109,9 @@ const void* accumulate_kernel();
 const void* tile_variance_kernel();
 const void* validate_kernel(int dtype);
 
-// Dynamic LDS bytes a frame launch needs.
+// LDS budget of the K > 32 path for a frame whose largest tile has
+// max_layers layers, and the dynamic LDS bytes a frame launch needs.
+int big_lds_bytes(int max_layers);
 size_t frame_lds_bytes(int kcap, int threads, int max_layers);
 
 }  // namespace dfb

@@ -305,36 +305,81 @@ __device__ float unit_background(const FrameArgs& a, const Unit& u) {
 }
 
 // ---------------------------------------------------------------- K > 32
-// The workgroup handles G pixels at a time.  LDS rows (one per pixel) hold Kp
-// keys (u64) and Kp floats (alpha, later T); columns are XOR-swizzled by the
-// row so that both the coalesced fill (threads across pixels) and the sort
-// (threads along a row) are free of bank conflicts.  S = NT / G lanes share a
-// pixel for the front-to-back walk (a product scan over S chunks) and for the
-// colour sums (a fixed-order reduction).
+// The workgroup handles G pixels at a time.  LDS holds one row per pixel:
+// Kp keys (u64) and, in a second array of the same shape, Kp floats (alpha,
+// later the transmittance T).  Position i of a row is stored at
+// i + i/16 (one pad slot per 16) and rows are RS = Kp*17/16 + 1 slots apart,
+// so the coalesced fill (lanes across rows), the LDS sort stages (lanes along
+// a row) and the register blocks (a lane per 16 consecutive keys) all hit
+// distinct banks.
+//
+// Sort: bitonic, every comparator min-to-lower.  Comparators closer than 16
+// positions never leave a 16-key block, so each block is sorted (sizes
+// 2..16) or half-cleaned (strides 8..1 of every later merge) by one lane in
+// registers; only strides >= 16 go through LDS with a barrier each.  For
+// Kp = 512 that is 21 barriers instead of 45.
+//
+// S = NT / G lanes share a pixel for the front-to-back walk (a product scan
+// over S chunks) and for the colour sums (a fixed-order reduction).
+constexpr int kBlk = 16;
+
+__device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
+
+__device__ __forceinline__ void block_load(const uint64_t* r, int base, uint64_t (&k)[kBlk]) {
+  const uint64_t* q = r + kslot(base);  // a block never straddles a pad slot
+#pragma unroll
+  for (int i = 0; i < kBlk; ++i) k[i] = q[i];
+}
+__device__ __forceinline__ void block_store(uint64_t* r, int base, const uint64_t (&k)[kBlk]) {
+  uint64_t* q = r + kslot(base);
+#pragma unroll
+  for (int i = 0; i < kBlk; ++i) q[i] = k[i];
+}
+// strides 8, 4, 2, 1 of a merge larger than the block (half-cleaners)
+__device__ __forceinline__ void block_half_clean(uint64_t (&k)[kBlk]) {
+#pragma unroll
+  for (int str = kBlk / 2; str > 0; str >>= 1)
+#pragma unroll
+    for (int i = 0; i < kBlk; ++i)
+      if ((i & str) == 0) compare_exchange(k[i], k[i + str]);
+}
+
+// G (pixels per group) for a padded layer count 2^lk and an LDS budget.
+__device__ __forceinline__ int bigk_group(int lk, int budget, int NT) {
+  const int RS = (1 << lk) + (1 << (lk - 4)) + 1;
+  int G = budget / (RS * 12);
+  G = G > NT ? NT : G;
+  G = G > 64 ? 64 : G;
+  while (G & (G - 1)) G &= G - 1;  // power of two
+  return G;
+}
+
 template <typename FT>
 __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff,
                            int K, int off, char* lds) {
   const int NT = blockDim.x, tid = threadIdx.x;
   const uint32_t P = static_cast<uint32_t>(a.P);
   const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
-  int Kp = 64;
-  while (Kp < K) Kp <<= 1;
-  int G = kBigLdsBytes / (Kp * 12);
-  G = G > NT ? NT : G;
-  G = G > 64 ? 64 : G;
-  while (G & (G - 1)) G &= G - 1;  // power of two
-  const int S = NT / G;            // lanes per pixel
+  int lk = 6;                       // log2(Kp), Kp >= 64
+  while ((1 << lk) < K) ++lk;
+  const int Kp = 1 << lk;
+  const int RS = Kp + (Kp >> 4) + 1;
+  const int G = bigk_group(lk, a.big_lds, NT);
+  int lg = 0;
+  while ((1 << lg) < G) ++lg;
+  const int S = NT / G;                   // lanes per pixel
   const int C = Kp / S > 0 ? Kp / S : 1;  // sorted positions per lane
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-  float* wv = reinterpret_cast<float*>(keys + static_cast<size_t>(G) * Kp);
-  float4* red = reinterpret_cast<float4*>(lds + kBigLdsBytes);  // [NT]
-  float* tend = reinterpret_cast<float*>(red + NT);               // [G]
-  const int gm = tid % G, sm = tid / G;
+  float* wv = reinterpret_cast<float*>(keys + static_cast<size_t>(G) * RS);
+  float4* red = reinterpret_cast<float4*>(lds + a.big_lds);  // [NT]
+  float* tend = reinterpret_cast<float*>(red + NT);           // [G]
+  const int gm = tid & (G - 1), sm = tid >> lg;
+  const int nblk = G << (lk - 4);  // 16-key blocks over all rows
   float vs = 0.f;
   for (int q0 = 0; q0 < a.work_px; q0 += G) {
     // 1. keys and alpha (coalesced over the G pixels)
-    for (int e = tid; e < G * Kp; e += NT) {
-      const int g = e % G, l = e / G, q = q0 + g;
+    for (int e = tid; e < (G << lk); e += NT) {
+      const int g = e & (G - 1), l = e >> lg, q = q0 + g;
       uint64_t key = ~0ull;
       float al = 0.f;
       if (l < K && q < a.work_px) {
@@ -345,41 +390,57 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
               static_cast<uint32_t>(l);
         al = ldf<FT>(b, 3 * P + p);
       }
-      const int col = l ^ (g & 15);
-      keys[g * Kp + col] = key;
-      wv[g * Kp + col] = al;
+      keys[g * RS + kslot(l)] = key;
+      wv[g * RS + kslot(l)] = al;
     }
     __syncthreads();
-    // 2. sort every row
-    for (int size = 2; size <= Kp; size <<= 1) {
-      for (int str = size >> 1; str > 0; str >>= 1) {
-        for (int e = tid; e < G * (Kp / 2); e += NT) {
-          const int g = e / (Kp / 2), c = e - g * (Kp / 2);
-          const int lo = (c / str) * (2 * str) + (c % str);
-          const int hi = (str == (size >> 1)) ? (lo ^ (size - 1)) : (lo + str);
-          uint64_t* r = keys + g * Kp;
-          const int sw = g & 15;
-          const uint64_t x = r[lo ^ sw], y = r[hi ^ sw];
+    // 2. sort every row: blocks of 16 in registers first
+    for (int b = tid; b < nblk; b += NT) {
+      uint64_t k[kBlk];
+      uint64_t* r = keys + (b >> (lk - 4)) * RS;
+      const int base = (b & ((1 << (lk - 4)) - 1)) * kBlk;
+      block_load(r, base, k);
+      sort_network<kBlk>(k);
+      block_store(r, base, k);
+    }
+    __syncthreads();
+    for (int ls = 5; ls <= lk; ++ls) {          // merge size 2^ls
+      for (int lt = ls - 1; lt >= 4; --lt) {     // strides >= 16 through LDS
+        const int str = 1 << lt;
+        for (int e = tid; e < (G << (lk - 1)); e += NT) {
+          const int g = e >> (lk - 1), c = e & ((1 << (lk - 1)) - 1);
+          const int lo = ((c >> lt) << (lt + 1)) | (c & (str - 1));
+          const int hi = (lt == ls - 1) ? (lo ^ ((1 << ls) - 1)) : (lo + str);
+          uint64_t* r = keys + g * RS;
+          const uint64_t x = r[kslot(lo)], y = r[kslot(hi)];
           if (y < x) {
-            r[lo ^ sw] = y;
-            r[hi ^ sw] = x;
+            r[kslot(lo)] = y;
+            r[kslot(hi)] = x;
           }
         }
         __syncthreads();
       }
+      for (int b = tid; b < nblk; b += NT) {     // strides 8..1 in registers
+        uint64_t k[kBlk];
+        uint64_t* r = keys + (b >> (lk - 4)) * RS;
+        const int base = (b & ((1 << (lk - 4)) - 1)) * kBlk;
+        block_load(r, base, k);
+        block_half_clean(k);
+        block_store(r, base, k);
+      }
+      __syncthreads();
     }
     // 3. front-to-back walk: chunk products, exclusive scan over the S chunks.
     //    Rows past the unit's last pixel hold only padding keys: skipped.
-    const int sw = gm & 15;
-    const uint64_t* row = keys + gm * Kp;
-    float* wrow = wv + gm * Kp;
+    const uint64_t* row = keys + gm * RS;
+    float* wrow = wv + gm * RS;
     const int qme = q0 + gm;
     const bool live = qme < a.work_px;
     const int i0 = sm * C, i1 = live ? ((i0 + C < K) ? i0 + C : K) : 0;
     float prod = 1.f;
     for (int i = i0; i < i1; ++i) {
-      const int l = static_cast<int>(static_cast<uint32_t>(row[i ^ sw]));
-      prod = prod * (1.f - wrow[l ^ sw]);
+      const int l = static_cast<int>(static_cast<uint32_t>(row[kslot(i)]));
+      prod = prod * (1.f - wrow[kslot(l)]);
     }
     red[tid].x = prod;
     __syncthreads();
@@ -390,21 +451,39 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     bool in_me = false;
     const int p_me = live ? unit_pixel(a, u, qme, in_me) : 0;
     for (int i = i0; i < i1; ++i) {
-      const int l = static_cast<int>(static_cast<uint32_t>(row[i ^ sw]));
-      const float al = wrow[l ^ sw];
-      wrow[l ^ sw] = T;
+      const int l = static_cast<int>(static_cast<uint32_t>(row[kslot(i)]));
+      const float al = wrow[kslot(l)];
+      wrow[kslot(l)] = T;
       Ap = fmaf(T, al, Ap);
       T = T * (1.f - al);
       if (a.mode & kModeKeepOrder)
         a.order[static_cast<size_t>(off + i) * P + p_me] = static_cast<uint16_t>(l);
     }
     __syncthreads();
-    // 4. colour in layer order (coalesced over the G pixels)
+    // 4. colour in layer order (coalesced over the G pixels), 4 layers per step
     float R = 0.f, Gc = 0.f, B = 0.f;
     if (live) {
-      for (int l = sm; l < K; l += S) {
+      int l = sm;
+      for (; l + 3 * S < K; l += 4 * S) {
+        float w[4], cr[4], cg[4], cb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const FT* __restrict__ b = frag + loff[l + j * S];
+          w[j] = wrow[kslot(l + j * S)];
+          cr[j] = ldf<FT>(b, p_me);
+          cg[j] = ldf<FT>(b, P + p_me);
+          cb[j] = ldf<FT>(b, 2 * P + p_me);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          R = fmaf(w[j], cr[j], R);
+          Gc = fmaf(w[j], cg[j], Gc);
+          B = fmaf(w[j], cb[j], B);
+        }
+      }
+      for (; l < K; l += S) {
         const FT* __restrict__ b = frag + loff[l];
-        const float w = wrow[l ^ sw];
+        const float w = wrow[kslot(l)];
         R = fmaf(w, ldf<FT>(b, p_me), R);
         Gc = fmaf(w, ldf<FT>(b, P + p_me), Gc);
         B = fmaf(w, ldf<FT>(b, 2 * P + p_me), B);
@@ -620,10 +699,15 @@ const void* validate_kernel(int dtype) {
                     : reinterpret_cast<const void*>(&validate_kernel_t<_Float16>);
 }
 
+int big_lds_bytes(int max_layers) {
+  // 16 pixels per group at 512 padded layers needs 16 * 545 * 12 bytes
+  return max_layers > 256 ? kBigLdsBytes : (max_layers > 128 ? 96 * 1024 : 64 * 1024);
+}
+
 size_t frame_lds_bytes(int kcap, int threads, int max_layers) {
   size_t small = static_cast<size_t>(kcap) * threads * sizeof(float);
   size_t big = 0;
-  if (max_layers > kcap) big = kBigLdsBytes + static_cast<size_t>(threads) * 16 + 64 * 4;
+  if (max_layers > kcap) big = big_lds_bytes(max_layers) + static_cast<size_t>(threads) * 16 + 64 * 4;
   return small > big ? small : big;
 }
 

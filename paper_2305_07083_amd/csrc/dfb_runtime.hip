@@ -328,6 +328,7 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   a.subs_x = h->subs_x;
   a.subs_per_tile = h->subs_per_tile;
   a.work_px = h->shape.work_w * h->shape.work_h;
+  a.big_lds = dfb::big_lds_bytes(h->max_k);
   a.work_shift = -1;
   for (int k = 0; k < 16; ++k)
     if ((1 << k) == h->shape.work_w) a.work_shift = k;
