@@ -112,6 +112,6 @@ const void* validate_kernel(int dtype);
 // LDS budget of the K > 32 path for a frame whose largest tile has
 // max_layers layers, and the dynamic LDS bytes a frame launch needs.
 int big_lds_bytes(int max_layers);
-size_t frame_lds_bytes(int kcap, int threads, int max_layers);
+size_t frame_lds_bytes(int kcap, int threads, int max_layers, int big_lds);
 
 }  // namespace dfb

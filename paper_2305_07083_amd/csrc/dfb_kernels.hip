@@ -377,21 +377,35 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
   const int nblk = G << (lk - 4);  // 16-key blocks over all rows
   float vs = 0.f;
   for (int q0 = 0; q0 < a.work_px; q0 += G) {
-    // 1. keys and alpha (coalesced over the G pixels)
-    for (int e = tid; e < (G << lk); e += NT) {
-      const int g = e & (G - 1), l = e >> lg, q = q0 + g;
-      uint64_t key = ~0ull;
-      float al = 0.f;
-      if (l < K && q < a.work_px) {
-        bool in;
-        const int p = unit_pixel(a, u, q, in);
-        const FT* __restrict__ b = frag + loff[l];
-        key = (static_cast<uint64_t>(depth_bits(ldf<FT>(b, 4 * P + p))) << 32) |
-              static_cast<uint32_t>(l);
-        al = ldf<FT>(b, 3 * P + p);
+    // 1. keys and alpha (coalesced over the G pixels); 8 elements per lane
+    //    per step so that their loads are in flight together
+    for (int e0 = tid; e0 < (G << lk); e0 += 8 * NT) {
+      float dv[8], av[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = e0 + j * NT;
+        const int g = e & (G - 1), l = e >> lg, q = q0 + g;
+        dv[j] = 0.f;
+        av[j] = 0.f;
+        if (e < (G << lk) && l < K && q < a.work_px) {
+          bool in;
+          const int p = unit_pixel(a, u, q, in);
+          const FT* __restrict__ b = frag + loff[l];
+          dv[j] = ldf<FT>(b, 4 * P + p);
+          av[j] = ldf<FT>(b, 3 * P + p);
+        }
       }
-      keys[g * RS + kslot(l)] = key;
-      wv[g * RS + kslot(l)] = al;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = e0 + j * NT;
+        const int g = e & (G - 1), l = e >> lg, q = q0 + g;
+        if (e < (G << lk)) {
+          const bool real = l < K && q < a.work_px;
+          keys[g * RS + kslot(l)] =
+              real ? ((static_cast<uint64_t>(depth_bits(dv[j])) << 32) | static_cast<uint32_t>(l)) : ~0ull;
+          wv[g * RS + kslot(l)] = av[j];
+        }
+      }
     }
     __syncthreads();
     // 2. sort every row: blocks of 16 in registers first
@@ -407,15 +421,29 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     for (int ls = 5; ls <= lk; ++ls) {          // merge size 2^ls
       for (int lt = ls - 1; lt >= 4; --lt) {     // strides >= 16 through LDS
         const int str = 1 << lt;
-        for (int e = tid; e < (G << (lk - 1)); e += NT) {
-          const int g = e >> (lk - 1), c = e & ((1 << (lk - 1)) - 1);
-          const int lo = ((c >> lt) << (lt + 1)) | (c & (str - 1));
-          const int hi = (lt == ls - 1) ? (lo ^ ((1 << ls) - 1)) : (lo + str);
-          uint64_t* r = keys + g * RS;
-          const uint64_t x = r[kslot(lo)], y = r[kslot(hi)];
-          if (y < x) {
-            r[kslot(lo)] = y;
-            r[kslot(hi)] = x;
+        const int pairs = G << (lk - 1);
+        for (int e0 = tid; e0 < pairs; e0 += 4 * NT) {  // 4 pairs per lane in flight
+          int ia[4], ib[4];
+          uint64_t x[4], y[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int e = e0 + j * NT;
+            const int g = e >> (lk - 1), c = e & ((1 << (lk - 1)) - 1);
+            const int lo = ((c >> lt) << (lt + 1)) | (c & (str - 1));
+            const int hi = (lt == ls - 1) ? (lo ^ ((1 << ls) - 1)) : (lo + str);
+            ia[j] = g * RS + kslot(lo);
+            ib[j] = g * RS + kslot(hi);
+            if (e < pairs) {
+              x[j] = keys[ia[j]];
+              y[j] = keys[ib[j]];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (e0 + j * NT < pairs && y[j] < x[j]) {
+              keys[ia[j]] = y[j];
+              keys[ib[j]] = x[j];
+            }
           }
         }
         __syncthreads();
@@ -438,6 +466,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     const bool live = qme < a.work_px;
     const int i0 = sm * C, i1 = live ? ((i0 + C < K) ? i0 + C : K) : 0;
     float prod = 1.f;
+#pragma unroll 8
     for (int i = i0; i < i1; ++i) {
       const int l = static_cast<int>(static_cast<uint32_t>(row[kslot(i)]));
       prod = prod * (1.f - wrow[kslot(l)]);
@@ -450,6 +479,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     float Ap = 0.f;
     bool in_me = false;
     const int p_me = live ? unit_pixel(a, u, qme, in_me) : 0;
+#pragma unroll 4
     for (int i = i0; i < i1; ++i) {
       const int l = static_cast<int>(static_cast<uint32_t>(row[kslot(i)]));
       const float al = wrow[kslot(l)];
@@ -704,10 +734,10 @@ int big_lds_bytes(int max_layers) {
   return max_layers > 256 ? kBigLdsBytes : (max_layers > 128 ? 96 * 1024 : 64 * 1024);
 }
 
-size_t frame_lds_bytes(int kcap, int threads, int max_layers) {
+size_t frame_lds_bytes(int kcap, int threads, int max_layers, int big_lds) {
   size_t small = static_cast<size_t>(kcap) * threads * sizeof(float);
   size_t big = 0;
-  if (max_layers > kcap) big = big_lds_bytes(max_layers) + static_cast<size_t>(threads) * 16 + 64 * 4;
+  if (max_layers > kcap) big = big_lds + static_cast<size_t>(threads) * 16 + 64 * 4;
   return small > big ? small : big;
 }
 

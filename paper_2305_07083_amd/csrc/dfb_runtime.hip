@@ -34,6 +34,7 @@ struct AutotuneKey {
 };
 struct Shape {
   int work_w, work_h, waves;
+  int big_lds;  // LDS budget of the K > 32 path
 };
 std::map<AutotuneKey, Shape> g_autotune_cache;
 
@@ -83,7 +84,7 @@ struct dfb_ctx {
   unsigned long long q_base = 0;
 
   // launch shape
-  Shape shape{0, 0, 0};
+  Shape shape{0, 0, 0, 64 * 1024};
   bool shape_valid = false;
   int kcap = 8;
   int grid = 0;
@@ -254,9 +255,11 @@ dfb_status check_usable(dfb_ctx* h) {
 
 int kcap_for(int max_k) { return max_k <= 8 ? 8 : (max_k <= 16 ? 16 : 32); }
 
-// Candidate launch shapes: square work units of 32/64/128 that divide the
-// tile (else the whole tile), times 1/2/4 waves.
-std::vector<Shape> candidates(const dfb_config& c) {
+// Candidate launch shapes: square work units of 16/32/64/128 that divide the
+// tile (else the whole tile), times 1/2/4 waves, times (frames with tiles of
+// more than 128 layers) a small or a large LDS budget for the K > 32 path --
+// two workgroups per CU, or one with twice the pixels per sorting group.
+std::vector<Shape> candidates(const dfb_config& c, int max_k) {
   std::vector<std::pair<int, int>> sizes;
   if (c.work_w) {
     sizes.push_back({c.work_w, c.work_h});
@@ -268,9 +271,12 @@ std::vector<Shape> candidates(const dfb_config& c) {
   std::vector<int> waves;
   if (c.waves_per_tile) waves.push_back(c.waves_per_tile);
   else waves = {1, 2, 4};
+  std::vector<int> ldss{dfb::big_lds_bytes(max_k)};
+  if (max_k > 128) ldss.push_back(64 * 1024);
   std::vector<Shape> out;
   for (auto& s : sizes)
-    for (int w : waves) out.push_back({s.first, s.second, w});
+    for (int w : waves)
+      for (int l : ldss) out.push_back({s.first, s.second, w, l});
   return out;
 }
 
@@ -328,7 +334,7 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   a.subs_x = h->subs_x;
   a.subs_per_tile = h->subs_per_tile;
   a.work_px = h->shape.work_w * h->shape.work_h;
-  a.big_lds = dfb::big_lds_bytes(h->max_k);
+  a.big_lds = h->shape.big_lds;
   a.work_shift = -1;
   for (int k = 0; k < 16; ++k)
     if ((1 << k) == h->shape.work_w) a.work_shift = k;
@@ -387,7 +393,7 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0
                         hipEvent_t t1 = nullptr) {
   const int threads = 64 * h->shape.waves;
   const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap);
-  const size_t lds = dfb::frame_lds_bytes(h->kcap, threads, h->max_k);
+  const size_t lds = dfb::frame_lds_bytes(h->kcap, threads, h->max_k, h->shape.big_lds);
   const bool acc = (mode & dfb::kModeAccumulate) != 0;
   int grid = 0;
   dfb_status st = grid_for(h, func, threads, lds, grid);
@@ -455,7 +461,7 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0
 dfb_status autotune(dfb_ctx* h) {
   AutotuneKey key{h->device, h->cfg.width, h->cfg.height, h->cfg.tile_w, h->cfg.tile_h,
                   h->cfg.frag_dtype, h->max_k, h->digest};
-  auto cands = candidates(h->cfg);
+  auto cands = candidates(h->cfg, h->max_k);
   if (cands.size() == 1) {
     h->shape = cands[0];
     h->shape_valid = true;
@@ -478,7 +484,8 @@ dfb_status autotune(dfb_ctx* h) {
     dfb_status st = build_work(h, s);
     if (st != DFB_OK) return st;
     std::vector<float> times;
-    for (int r = 0; r < 10; ++r) {
+    int warm = 5, timed = 5;  // frames longer than 5 ms: 1 warm-up, 3 timed
+    for (int r = 0; r < warm + timed; ++r) {
       DFB_HIP(h, hipEventRecord(e0, h->stream));
       st = launch_frame(h, mode, false);
       if (st != DFB_OK) return st;
@@ -486,7 +493,11 @@ dfb_status autotune(dfb_ctx* h) {
       DFB_HIP(h, hipEventSynchronize(e1));
       float ms = 0.f;
       DFB_HIP(h, hipEventElapsedTime(&ms, e0, e1));
-      if (r >= 5) times.push_back(ms);  // 5 warm-up, 5 timed
+      if (r == 0 && ms > 5.f) {
+        warm = 1;
+        timed = 3;
+      }
+      if (r >= warm) times.push_back(ms);
     }
     std::sort(times.begin(), times.end());
     const double med = times[times.size() / 2];
@@ -751,7 +762,7 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
   h->work_valid = false;
   if (!h->shape_valid) {
     // fixed shapes skip the autotuner
-    auto c = candidates(h->cfg);
+    auto c = candidates(h->cfg, max_k);
     if (c.size() == 1) { h->shape = c[0]; h->shape_valid = true; }
   }
   if (h->shape_valid) {
