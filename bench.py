@@ -39,6 +39,8 @@ def parse():
                     help="skip training / evaluating the denoiser (frames-to-PSNR part of the metric)")
     ap.add_argument("--denoise-scenes", type=int, default=8)
     ap.add_argument("--denoise-steps", type=int, default=1000)
+    ap.add_argument("--no-ops", action="store_true",
+                    help="skip the list / average tile-operation legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device to device (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -161,6 +163,62 @@ def make_frame(name):
     return f, desc
 
 
+def time_frames(dfb, torch, f, op, copies, steps, warmup):
+    """Plain frames (composite + RGBA8) of ``f`` with tile operation ``op``,
+    autotuned; returns (kernel ms from the graph's events, wall ms per frame,
+    launch info)."""
+    cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=0, waves=0, op=op)
+    n_blocks = copies[0].shape[0]
+    with dfb.Compositor(cfg, torch.cuda.current_stream().cuda_stream) as c:
+        c.set_fragments(copies[0], n_blocks, f.layers, f.expected)
+        c.composite()
+        for i in range(warmup):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite()
+        torch.cuda.synchronize()
+        dfb.dfb_set_timing(c.h, True)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps * 1e3
+        return dfb.dfb_kernel_ms(c.h), wall, c.info()
+
+
+def tile_ops_leg(dfb, torch, steps=30, warmup=5, copies=4):
+    """The other tile operations on full-size frames, plain frames with RGBA8
+    output: the 2048x2048 brick frame as a generation list (list operation)
+    next to the same frame through the per-pixel sort, and redundant renders
+    of a 2048x2048 frame (U{1..8} per tile) through the averaging operation.
+    Algorithmic bytes per launch: RGBA of every fragment (the list and
+    average read no depth; the sort reads RGBA + depth), 4 B per output
+    pixel, the layer table."""
+    import workloads
+    out = {}
+    legs = [("list", workloads.bricks_2048_list(), dfb.DFB_OP_LIST, 16,
+             "2048x2048, 64x64 tiles, 4x4x4 bricks as a back-to-front generation list, fp32"),
+            ("alpha_blend_same_frame", workloads.c2(), dfb.DFB_OP_ALPHA_BLEND, 20,
+             "2048x2048, 64x64 tiles, 4x4x4 bricks, per-pixel sort, fp32"),
+            ("average", workloads.redundant_2048(), dfb.DFB_OP_AVERAGE, 16,
+             "2048x2048, 64x64 tiles, U{1..8} redundant renders per tile, fp32")]
+    for name, f, op, frag_bytes, desc in legs:
+        bufs = [torch.from_numpy(f.frag).to("cuda:0") for _ in range(copies)]
+        torch.cuda.synchronize()
+        kms, wall, info = time_frames(dfb, torch, f, op, bufs, steps, warmup)
+        del bufs
+        torch.cuda.empty_cache()
+        px = f.n_tiles * f.P
+        alg = f.n_fragments * frag_bytes + px * 4 + f.n_tiles * 4 + len(f.layers) * 8
+        gbps = alg / (kms * 1e-3) / 1e9
+        out[name] = {"workload": desc, "fragments_per_frame": f.n_fragments, "kernel_ms": kms,
+                     "wall_ms_per_frame": wall, "fragments_per_s": f.n_fragments / (kms * 1e-3),
+                     "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
+                     "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                  "frac": gbps / HBM_PEAK_GBPS, "algorithmic_bytes_per_launch": alg}}
+    return out
+
+
 def cpu_baseline(f, accumulate, budget_s=12.0):
     """The FP64 oracle as it stands, on whole frames, repeated for about
     ``budget_s`` seconds on this host's cores."""
@@ -276,6 +334,8 @@ def main():
         torch.cuda.synchronize()
     if not args.no_cpu and args.workload != "c4":
         out["cpu_baseline"] = cpu_baseline(f, accumulate)
+    if not args.no_ops and args.workload == "c2":
+        out["tile_ops"] = tile_ops_leg(dfb, torch)
     if not args.no_denoise and args.workload == "c2":
         out["denoise"] = denoise_leg(args.denoise_scenes, args.denoise_steps)
     print(json.dumps(out), flush=True)

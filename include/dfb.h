@@ -46,13 +46,30 @@ typedef enum {
   DFB_ERR_BAD_VALUE = -5,    /* DFB_VALIDATE found a NaN depth */
   DFB_ERR_OOM = -6,          /* a device or host allocation failed */
   DFB_ERR_HIP = -7,          /* a HIP call failed (sticky) */
-  DFB_ERR_UNSUPPORTED = -8   /* e.g. more layers in one tile than the kernels handle */
+  DFB_ERR_UNSUPPORTED = -8,  /* e.g. more layers in one tile than the kernels handle */
+  DFB_ERR_TREE = -9          /* a dependency tree received more tiles than its parents declared */
 } dfb_status;
 
 typedef enum { DFB_F32 = 0, DFB_F16 = 1 } dfb_dtype;   /* storage of all five planes */
 
 /* Display formats of the final pixels (Sec. 3.1): NONE stores nothing. */
 typedef enum { DFB_FMT_RGBA8 = 0, DFB_FMT_RGBAF32 = 1, DFB_FMT_NONE = 2 } dfb_format;
+
+/* Tile operations (Sec. 3.1: the tile operation interprets a tile's
+ * dependency tree; Sec. 4.1.1; Sec. 4.2).
+ *  ALPHA_BLEND  per pixel, sort the layers by depth and blend with "over"
+ *               (Sec. 4.2, Listing 4).
+ *  LIST         the tree is a list ordered back to front by generation (the
+ *               end of Sec. 4.2: valid when a rank-order sort is correct):
+ *               a tile's layers are blended in source_id order, the highest
+ *               in front, and no depth is read or sorted.  With
+ *               dfb_set_fragments, pass each layer's generation (>= 1) as its
+ *               source_id; dfb_set_fragments_tree does that itself.
+ *  AVERAGE      the mean RGBA of a tile's layers: redundant renders of one
+ *               tile with different seeds (Sec. 4.1.1, dynamic load
+ *               balancing); the number of layers may differ between tiles;
+ *               a tile with none shows the background.  No depth is read. */
+typedef enum { DFB_OP_ALPHA_BLEND = 0, DFB_OP_LIST = 1, DFB_OP_AVERAGE = 2 } dfb_tile_op;
 
 typedef enum {
   DFB_BUF_FINAL = 0,          /* display pixels: RGBA8 as uint8[n][P][4], RGBAF32 as float[n][P][4] */
@@ -86,6 +103,13 @@ typedef struct {
   float background[4];     /* premultiplied RGBA of the generation-0 background tile (Sec. 4.2) */
   float tonemap_gamma;     /* 1 = clamp only; else colour channels raised to 1/gamma */
   uint32_t flags;          /* DFB_VALIDATE | DFB_KEEP_SORT_ORDER | DFB_KEEP_FINISHED */
+  int32_t tile_op;         /* dfb_tile_op; DFB_KEEP_SORT_ORDER needs ALPHA_BLEND or LIST */
+  const float* background_image; /* NULL, or a background texture (Sec. 4.2: the background
+                              tile holds the background colour or a texture): device
+                              float[n_tiles][P][4], premultiplied RGBA, tile-major like the
+                              finished tiles, 16-byte aligned.  Borrowed: it must stay valid
+                              while frames that use it run; replace it with
+                              dfb_set_background_image. */
 } dfb_config;
 
 /* One generation-1 tile from one contributor (Listing 1 Tile; Listing 3).
@@ -144,6 +168,83 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
  * floor(255 y + 0.5).  If work_w/waves_per_tile are 0, the first frame of a
  * new layer layout first autotunes them (synchronously). */
 dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags);
+
+/* Replace the background texture (NULL: back to cfg.background) for the
+ * frames composited after this call.  Layout and ownership as
+ * dfb_config.background_image; a pointer that is not 16-byte aligned ->
+ * DFB_ERR_INVALID_ARG. */
+dfb_status dfb_set_background_image(dfb_handle h, const float* image_dev);
+
+/* One layer's place in its tile's dependency tree (Sec. 3.1.1; Listing 1
+ * Tile.generation / Tile.children). */
+typedef struct {
+  int32_t generation;  /* >= 1; generation 0 is the background tile */
+  int32_t children;    /* >= 0: tiles this one adds to generation + 1 */
+} dfb_tree_node;
+
+/* dfb_set_fragments with general per-tile dependency trees (Sec. 3.1.1):
+ * tree[i] places layers[i]; bg_children[t] (host int32[n_tiles]) is what the
+ * background tile of tile t declares for generation 1.  Every tile's tree is
+ * checked with the same bookkeeping as dfb_tree_add, the layers taken in
+ * array order as arrival order; a tree still waiting for tiles after the
+ * last layer -> DFB_ERR_INCOMPLETE, more tiles in a generation than its
+ * parents declared -> DFB_ERR_TREE.  ALPHA_BLEND and AVERAGE then treat all
+ * generations alike; LIST needs exactly one tile per generation and blends
+ * them by generation, the highest in front. */
+dfb_status dfb_set_fragments_tree(dfb_handle h, const void* frag_dev, int64_t n_blocks,
+                                  const dfb_layer* layers, const dfb_tree_node* tree,
+                                  int32_t n_layers, const int32_t* bg_children);
+
+/* Host-side dependency-tree bookkeeping for tiles that arrive one at a time
+ * (Sec. 3.1.1; Listing 4's process): per tile, generation 0 starts with one
+ * expected tile; a generation is done when as many of its tiles arrived as
+ * its parents declared children, and the next generation then expects the
+ * sum of the children its tiles declared; the tree is complete when a done
+ * generation declared no children.  Tiles may arrive in any generation
+ * order: later generations are counted until their parents are done.
+ * No GPU is involved. */
+typedef struct dfb_tree_s* dfb_tree;
+
+/* n_tiles >= 1 trees, each waiting for its generation-0 tile. */
+dfb_status dfb_tree_create(int32_t n_tiles, dfb_tree* out);
+dfb_status dfb_tree_destroy(dfb_tree t);
+
+/* Forget every arrival: each tile again waits for its generation-0 tile. */
+dfb_status dfb_tree_new_frame(dfb_tree t);
+
+/* One tile arrives.  *completed (nullable) = 1 if this arrival completed the
+ * tile's tree, else 0.  generation outside [0, 65535], children < 0 or tile_id
+ * out of range -> DFB_ERR_INVALID_ARG; a tile that makes some generation hold
+ * more tiles than declared, found as soon as all generations before it are
+ * done (also any tile after completion) -> DFB_ERR_TREE, and the tile's tree
+ * stays in error until dfb_tree_new_frame. */
+dfb_status dfb_tree_add(dfb_tree t, int32_t tile_id, int32_t generation, int32_t children,
+                        int32_t* completed);
+
+/* State of one tile's tree: *state = 1 complete, 0 waiting, -1 error;
+ * *generation = the generation being completed (the last one when complete);
+ * *missing = tiles that generation still waits for (0 when complete).
+ * Each output is nullable. */
+dfb_status dfb_tree_query(dfb_tree t, int32_t tile_id, int32_t* state, int32_t* generation,
+                          int32_t* missing);
+
+/* Variance-driven assignment of extra samples (Sec. 4.1.1: tiles with a
+ * higher variance get more renders).  Distributes `extra` (0 <= extra <
+ * 2^31) additional tile renders over the n_tiles tiles in proportion to each
+ * tile's variance of the mean, by largest remainders:
+ *   w_t = v_t where finite and > 0, else 0;  S = sum of w_t in tile order,
+ *   in double;  q_t = extra * w_t / S (double);  c_t = floor(q_t); the
+ *   extra - sum c_t renders left go one each to the tiles of largest
+ *   q_t - c_t, ties to the smaller tile id.
+ * S == 0 -> uniform: floor(extra / n_tiles) each and one more for the first
+ * extra mod n_tiles tiles.  counts: host int32[n_tiles]. */
+dfb_status dfb_assign_samples_host(const float* variance, int32_t n_tiles, int64_t extra,
+                                   int32_t* counts);
+
+/* The same from the handle's per-tile variance (DFB_BUF_TILE_VARIANCE of the
+ * last accumulated frame; uniform before two frames are accumulated).
+ * Synchronises the handle's stream. */
+dfb_status dfb_assign_samples(dfb_handle h, int64_t extra, int32_t* counts);
 
 /* Unfused accumulation of the last finished frame (needs DFB_KEEP_FINISHED):
  * the same Welford update, variance and display conversion as

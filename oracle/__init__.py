@@ -52,8 +52,8 @@ def _load():
         lib.orc_composite.restype = ctypes.c_int
         lib.orc_composite.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, ctypes.c_int32, P,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                      ctypes.c_int32, P, P, ctypes.c_int32, P, P, P,
-                                      ctypes.c_int32, ctypes.c_int32]
+                                      ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.c_int32,
+                                      P, P, P, ctypes.c_int32, ctypes.c_int32]
         lib.orc_tile_counts.restype = ctypes.c_int
         lib.orc_tile_counts.argtypes = [P, ctypes.c_int32, ctypes.c_int64, P, ctypes.c_int32, P]
         lib.orc_accumulate.restype = None
@@ -86,9 +86,17 @@ def _as_layers(layers):
     return out
 
 
+OPS = {"blend": 0, "list": 1, "average": 2}
+
+
 def composite(frag, layers, width, height, tile_w, tile_h, *, expected=None, background=(0, 0, 0, 0),
-              tiles=None, want_mag=False, want_order=False, threads=None):
+              tiles=None, want_mag=False, want_order=False, threads=None, op="blend",
+              background_image=None):
     """O1-O5: composite the listed tiles (default: all) of one frame in FP64.
+
+    ``op``: "blend" (per-pixel depth sort + over), "list" (back to front by
+    generation = source id >= 1), "average" (mean of the layers).
+    ``background_image``: optional [n_tiles, P, 4] texture behind everything.
 
     ``frag`` is a numpy array of float32 or float16 with ``n_blocks*5*P``
     elements (block, plane R,G,B,A,depth, pixel).  Returns a dict with
@@ -114,6 +122,11 @@ def composite(frag, layers, width, height, tile_w, tile_h, *, expected=None, bac
     tiles = np.arange(n_tiles, dtype=np.int32) if tiles is None else np.ascontiguousarray(tiles, dtype=np.int32)
     exp = None if expected is None else np.ascontiguousarray(expected, dtype=np.int32)
     bg = np.ascontiguousarray(background, dtype=np.float64)
+    bgi = None
+    if background_image is not None:
+        bgi = np.ascontiguousarray(background_image, dtype=np.float64)
+        if bgi.shape != (n_tiles, P, 4):
+            raise ValueError("background_image must be [n_tiles, P, 4]")
     rgba = np.zeros((len(tiles), P, 4), dtype=np.float64)
     mag = np.zeros((len(tiles), P, 4), dtype=np.float64) if want_mag else None
     kmax = 0
@@ -125,7 +138,8 @@ def composite(frag, layers, width, height, tile_w, tile_h, *, expected=None, bac
     if threads is None:
         threads = len(os.sched_getaffinity(0))
     rc = lib.orc_composite(_ptr(frag), dtype, n_blocks, _ptr(lay), len(lay), _ptr(exp), width,
-                           height, tile_w, tile_h, _ptr(bg), _ptr(tiles), len(tiles), _ptr(rgba),
+                           height, tile_w, tile_h, _ptr(bg), OPS[op], _ptr(bgi), _ptr(tiles),
+                           len(tiles), _ptr(rgba),
                            _ptr(mag), _ptr(order), max(kmax, 1), int(threads))
     if rc != OK:
         raise OracleError(rc)

@@ -19,7 +19,14 @@
  *                 nearer, ties broken by the contributor's id).
  *   O4 sort    -- per pixel, not per rank (Sec. 4.2).
  *   O5 blend   -- front-to-back premultiplied "over", then the background
- *                 colour behind everything (Sec. 4.2).
+ *                 colour, or a background texture, behind everything
+ *                 (Sec. 4.2).
+ *   O5L list   -- when a rank-order sort is correct the tree is a list of
+ *                 tiles ordered back to front by generation (end of
+ *                 Sec. 4.2): starting from the background, each generation
+ *                 in increasing order is put "over" what is behind it.
+ *   O5A average -- redundant renders of one tile with different seeds are
+ *                 averaged (Sec. 4.1.1, dynamic load balancing).
  *   O6 accumulate -- progressive refinement as the running mean since the
  *                 last reset, with Welford's M2 (Listing 1 accumulationID,
  *                 accumulation and variance tiles).
@@ -148,6 +155,8 @@ typedef struct {
   const orc_groups* g;
   int32_t tile_w, tile_h;
   double bg[4];
+  const double* bg_image; /* nullable [n_tiles][P][4] */
+  int op;                 /* 0 sort + blend, 1 list, 2 average */
   const int32_t* out_tiles;
   int32_t n_out;
   double* out_rgba;     /* [n_out][P][4] */
@@ -158,7 +167,85 @@ typedef struct {
   pthread_mutex_t lock;
 } orc_job;
 
+/* the background of pixel p of tile t */
+static void background(const orc_job* job, int32_t t, int64_t P, int64_t p, double out[4]) {
+  for (int c = 0; c < 4; ++c) out[c] = job->bg_image ? job->bg_image[((int64_t)t * P + p) * 4 + c] : job->bg[c];
+}
+
+static void store(orc_job* job, int32_t oi, int64_t P, int64_t p, const double v[4], const double m[4]) {
+  double* o = job->out_rgba + (oi * P + p) * 4;
+  for (int c = 0; c < 4; ++c) o[c] = v[c];
+  if (job->out_mag) {
+    double* q = job->out_mag + (oi * P + p) * 4;
+    for (int c = 0; c < 4; ++c) q[c] = m[c];
+  }
+}
+
+/* O5L: back to front, generation by generation, each tile "over" the rest */
+static void list_tile(orc_job* job, int32_t oi) {
+  const int32_t t = job->out_tiles[oi];
+  const int64_t P = (int64_t)job->tile_w * job->tile_h;
+  const orc_groups* g = job->g;
+  const int32_t K = g->count[t];
+  /* the tile's layers by increasing generation (= source id) */
+  int32_t* byg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(K > 0 ? K : 1));
+  for (int32_t i = 0; i < K; ++i) byg[i] = g->members[g->start[t] + i];
+  for (int32_t i = 1; i < K; ++i)
+    for (int32_t j = i; j > 0 && job->layers[byg[j - 1]].source_id > job->layers[byg[j]].source_id; --j) {
+      int32_t x = byg[j]; byg[j] = byg[j - 1]; byg[j - 1] = x;
+    }
+  for (int64_t p = 0; p < P; ++p) {
+    double v[4], m[4];
+    background(job, t, P, p, v);
+    for (int c = 0; c < 4; ++c) m[c] = fabs(v[c]);
+    for (int32_t i = 0; i < K; ++i) {
+      const orc_layer* L = &job->layers[byg[i]];
+      const double a = frag_value(job->frag, job->dtype, P, L->block, 3, p);
+      for (int c = 0; c < 4; ++c) {
+        const double x = frag_value(job->frag, job->dtype, P, L->block, c, p);
+        v[c] = x + (1.0 - a) * v[c];
+        m[c] = fabs(x) + (1.0 - a) * m[c];
+      }
+      /* nearest first: generation K-1-i sits at position i of the order */
+      if (job->out_order) job->out_order[(oi * P + p) * job->kmax + (K - 1 - i)] = L->source_id;
+    }
+    store(job, oi, P, p, v, m);
+  }
+  free(byg);
+}
+
+/* O5A: the mean of the tile's layers; none -> the background */
+static void average_tile(orc_job* job, int32_t oi) {
+  const int32_t t = job->out_tiles[oi];
+  const int64_t P = (int64_t)job->tile_w * job->tile_h;
+  const orc_groups* g = job->g;
+  const int32_t K = g->count[t];
+  for (int64_t p = 0; p < P; ++p) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0}, m[4] = {0.0, 0.0, 0.0, 0.0};
+    if (K == 0) {
+      background(job, t, P, p, v);
+      for (int c = 0; c < 4; ++c) m[c] = fabs(v[c]);
+    } else {
+      for (int32_t i = 0; i < K; ++i) {
+        const orc_layer* L = &job->layers[g->members[g->start[t] + i]];
+        for (int c = 0; c < 4; ++c) {
+          const double x = frag_value(job->frag, job->dtype, P, L->block, c, p);
+          v[c] += x;
+          m[c] += fabs(x);
+        }
+      }
+      for (int c = 0; c < 4; ++c) {
+        v[c] /= (double)K;
+        m[c] /= (double)K;
+      }
+    }
+    store(job, oi, P, p, v, m);
+  }
+}
+
 static void composite_tile(orc_job* job, int32_t oi) {
+  if (job->op == 1) { list_tile(job, oi); return; }
+  if (job->op == 2) { average_tile(job, oi); return; }
   const int32_t t = job->out_tiles[oi];
   const int64_t P = (int64_t)job->tile_w * job->tile_h;
   const orc_groups* g = job->g;
@@ -185,12 +272,14 @@ static void composite_tile(orc_job* job, int32_t oi) {
       T *= (1.0 - a);
       if (job->out_order) job->out_order[(oi * P + p) * job->kmax + i] = keys[i].sid;
     }
+    double bg[4];
+    background(job, t, P, p, bg);
     for (int c = 0; c < 3; ++c) {
-      C[c] += T * job->bg[c];
-      M[c] += T * fabs(job->bg[c]);
+      C[c] += T * bg[c];
+      M[c] += T * fabs(bg[c]);
     }
-    A += T * job->bg[3];
-    M[3] += T * fabs(job->bg[3]);
+    A += T * bg[3];
+    M[3] += T * fabs(bg[3]);
     double* o = job->out_rgba + (oi * P + p) * 4;
     o[0] = C[0]; o[1] = C[1]; o[2] = C[2]; o[3] = A;
     if (job->out_mag) {
@@ -220,17 +309,28 @@ static void* worker(void* arg) {
  *              1 = f16 (IEEE binary16 bits).
  *   layers     generation-1 tiles in any order.
  *   expected   nullable, [n_tiles]: the background tile's children count.
+ *   bg         nullable RGBA background colour (default 0).
+ *   op         0: per-pixel sort + blend; 1: list by generation (source id
+ *              >= 1 is the generation); 2: average.
+ *   bg_image   nullable [n_tiles][P][4]: a background texture, used instead
+ *              of bg.
  *   out_tiles  tile ids to compute; outputs are in this order.
- *   out_order  nullable, [n_out][P][kmax]: source ids, nearest first.
+ *   out_order  nullable, [n_out][P][kmax]: source ids, nearest first (not
+ *              with op 2).
  * Returns 0, or a negative error (bad id / duplicate / incomplete tree).
  */
 int orc_composite(const void* frag, int dtype, int64_t n_blocks, const orc_layer* layers,
                   int32_t n_layers, const int32_t* expected, int32_t width, int32_t height,
-                  int32_t tile_w, int32_t tile_h, const double* bg, const int32_t* out_tiles,
-                  int32_t n_out, double* out_rgba, double* out_mag, uint32_t* out_order,
-                  int32_t kmax, int32_t n_threads) {
+                  int32_t tile_w, int32_t tile_h, const double* bg, int32_t op,
+                  const double* bg_image, const int32_t* out_tiles, int32_t n_out,
+                  double* out_rgba, double* out_mag, uint32_t* out_order, int32_t kmax,
+                  int32_t n_threads) {
   if (width <= 0 || height <= 0 || tile_w <= 0 || tile_h <= 0 || (dtype != 0 && dtype != 1))
     return ORC_ERR_ARG;
+  if (op < 0 || op > 2 || (op == 2 && out_order)) return ORC_ERR_ARG;
+  if (op == 1)
+    for (int32_t i = 0; i < n_layers; ++i)
+      if (layers[i].source_id == 0) return ORC_ERR_ARG; /* generation 0 is the background */
   const int32_t tiles_x = (width + tile_w - 1) / tile_w;
   const int32_t tiles_y = (height + tile_h - 1) / tile_h;
   const int32_t n_tiles = tiles_x * tiles_y;
@@ -245,6 +345,8 @@ int orc_composite(const void* frag, int dtype, int64_t n_blocks, const orc_layer
   job.frag = frag; job.dtype = dtype; job.layers = layers; job.g = &g;
   job.tile_w = tile_w; job.tile_h = tile_h;
   for (int c = 0; c < 4; ++c) job.bg[c] = bg ? bg[c] : 0.0;
+  job.bg_image = bg_image;
+  job.op = op;
   job.out_tiles = out_tiles; job.n_out = n_out;
   job.out_rgba = out_rgba; job.out_mag = out_mag; job.out_order = out_order; job.kmax = kmax;
   job.next = 0;

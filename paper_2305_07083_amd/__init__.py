@@ -25,6 +25,9 @@ DFB_ERR_BAD_VALUE = -5
 DFB_ERR_OOM = -6
 DFB_ERR_HIP = -7
 DFB_ERR_UNSUPPORTED = -8
+DFB_ERR_TREE = -9
+
+DFB_OP_ALPHA_BLEND, DFB_OP_LIST, DFB_OP_AVERAGE = 0, 1, 2
 
 DFB_F32, DFB_F16 = 0, 1
 DFB_FMT_RGBA8, DFB_FMT_RGBAF32, DFB_FMT_NONE = 0, 1, 2
@@ -38,7 +41,9 @@ EXPORTED = (
     "dfb_create", "dfb_destroy", "dfb_set_fragments", "dfb_composite_frame", "dfb_accumulate",
     "dfb_reset_accumulation", "dfb_read_tiles", "dfb_buffer_bytes", "dfb_synchronize",
     "dfb_get_info", "dfb_set_timing", "dfb_kernel_ms", "dfb_validate_layers", "dfb_last_error",
-    "dfb_status_string",
+    "dfb_status_string", "dfb_set_background_image", "dfb_set_fragments_tree", "dfb_tree_create",
+    "dfb_tree_destroy", "dfb_tree_new_frame", "dfb_tree_add", "dfb_tree_query",
+    "dfb_assign_samples_host", "dfb_assign_samples",
     # dfb_denoise.h
     "dfb_denoiser_param_count", "dfb_denoiser_create", "dfb_denoiser_destroy", "dfb_denoiser_set_params",
     "dfb_denoiser_get_params", "dfb_denoiser_forward", "dfb_denoiser_train_step",
@@ -52,7 +57,15 @@ class Config(ctypes.Structure):
                 ("work_w", ctypes.c_int32), ("work_h", ctypes.c_int32),
                 ("waves_per_tile", ctypes.c_int32), ("frag_dtype", ctypes.c_int32),
                 ("format", ctypes.c_int32), ("background", ctypes.c_float * 4),
-                ("tonemap_gamma", ctypes.c_float), ("flags", ctypes.c_uint32)]
+                ("tonemap_gamma", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("tile_op", ctypes.c_int32), ("background_image", ctypes.c_void_p)]
+
+
+class TreeNode(ctypes.Structure):
+    _fields_ = [("generation", ctypes.c_int32), ("children", ctypes.c_int32)]
+
+
+TREE_DTYPE = np.dtype([("generation", "<i4"), ("children", "<i4")])
 
 
 class Layer(ctypes.Structure):
@@ -110,6 +123,15 @@ def load():
         "dfb_validate_layers": ([ctypes.POINTER(Config), I64, P, I32, P, P], I32),
         "dfb_last_error": ([P], ctypes.c_char_p),
         "dfb_status_string": ([I32], ctypes.c_char_p),
+        "dfb_set_background_image": ([P, P], I32),
+        "dfb_set_fragments_tree": ([P, P, I64, P, P, I32, P], I32),
+        "dfb_tree_create": ([I32, ctypes.POINTER(P)], I32),
+        "dfb_tree_destroy": ([P], I32),
+        "dfb_tree_new_frame": ([P], I32),
+        "dfb_tree_add": ([P, I32, I32, I32, P], I32),
+        "dfb_tree_query": ([P, I32, P, P, P], I32),
+        "dfb_assign_samples_host": ([P, I32, I64, P], I32),
+        "dfb_assign_samples": ([P, I64, P], I32),
         "dfb_denoiser_param_count": ([], I64),
         "dfb_denoiser_create": ([ctypes.POINTER(UnetConfig), P, ctypes.POINTER(P)], I32),
         "dfb_denoiser_destroy": ([P], I32),
@@ -151,11 +173,14 @@ def _ptr(a):
 
 
 def make_config(width, height, tile_w=64, tile_h=None, *, work=0, waves=0, dtype=DFB_F32,
-                fmt=DFB_FMT_RGBA8, background=(0.0, 0.0, 0.0, 0.0), gamma=1.0, flags=0):
+                fmt=DFB_FMT_RGBA8, background=(0.0, 0.0, 0.0, 0.0), gamma=1.0, flags=0,
+                op=DFB_OP_ALPHA_BLEND, background_image=None):
+    """``background_image``: a device pointer (int) or a tensor with data_ptr()."""
     tile_h = tile_w if tile_h is None else tile_h
     ww, wh = (work, work) if isinstance(work, int) else work
+    bgi = None if background_image is None else _ptr(background_image).value
     return Config(width, height, tile_w, tile_h, ww, wh, waves, dtype, fmt,
-                  (ctypes.c_float * 4)(*background), gamma, flags)
+                  (ctypes.c_float * 4)(*background), gamma, flags, op, bgi)
 
 
 def as_layers(layers):
@@ -236,6 +261,85 @@ def dfb_validate_layers(cfg: Config, n_blocks, layers, expected=None):
     return counts
 
 
+def dfb_set_background_image(h, image_dev):
+    _check(load().dfb_set_background_image(h, _ptr(image_dev)), h)
+
+
+def as_tree(tree):
+    """numpy record array with fields generation, children -> C layout."""
+    if isinstance(tree, np.ndarray) and tree.dtype == TREE_DTYPE and tree.flags.c_contiguous:
+        return tree
+    out = np.empty(len(tree), dtype=TREE_DTYPE)
+    for f in TREE_DTYPE.names:
+        out[f] = np.asarray(tree[f])
+    return out
+
+
+def dfb_set_fragments_tree(h, frag_dev, n_blocks, layers, tree, bg_children):
+    lay = as_layers(layers)
+    tr = as_tree(tree)
+    if len(tr) != len(lay):
+        raise ValueError("one tree node per layer")
+    bgc = np.ascontiguousarray(bg_children, dtype=np.int32)
+    _check(load().dfb_set_fragments_tree(h, _ptr(frag_dev), int(n_blocks), _ptr(lay), _ptr(tr), len(lay),
+                                         _ptr(bgc)), h)
+
+
+def dfb_assign_samples_host(variance, extra):
+    """Host-only largest-remainder assignment; returns int32[n_tiles]."""
+    v = np.ascontiguousarray(variance, dtype=np.float32)
+    counts = np.zeros(len(v), dtype=np.int32)
+    st = load().dfb_assign_samples_host(_ptr(v), len(v), int(extra), _ptr(counts))
+    if st != DFB_OK:
+        raise DfbError(st, load().dfb_status_string(st).decode())
+    return counts
+
+
+def dfb_assign_samples(h, extra, n_tiles):
+    counts = np.zeros(n_tiles, dtype=np.int32)
+    _check(load().dfb_assign_samples(h, int(extra), _ptr(counts)), h)
+    return counts
+
+
+class Tree:
+    """Dependency-tree bookkeeping for tiles arriving one at a time (host)."""
+
+    def __init__(self, n_tiles):
+        self.lib = load()
+        self.t = ctypes.c_void_p()
+        st = self.lib.dfb_tree_create(int(n_tiles), ctypes.byref(self.t))
+        if st != DFB_OK:
+            raise DfbError(st, "dfb_tree_create")
+
+    def close(self):
+        if self.t:
+            self.lib.dfb_tree_destroy(self.t)
+            self.t = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def new_frame(self):
+        self.lib.dfb_tree_new_frame(self.t)
+
+    def add(self, tile_id, generation, children):
+        """Returns (status, completed)."""
+        done = ctypes.c_int32(0)
+        st = self.lib.dfb_tree_add(self.t, int(tile_id), int(generation), int(children), ctypes.byref(done))
+        return st, bool(done.value)
+
+    def query(self, tile_id):
+        """(state 1/0/-1, generation, missing)."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        st = self.lib.dfb_tree_query(self.t, int(tile_id), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        if st != DFB_OK:
+            raise DfbError(st, "dfb_tree_query")
+        return a.value, b.value, c.value
+
+
 # ---------------------------------------------------------- convenience
 class Compositor:
     """Owns a handle; reads results back into numpy arrays."""
@@ -259,6 +363,15 @@ class Compositor:
 
     def set_fragments(self, frag_dev, n_blocks, layers, expected=None):
         dfb_set_fragments(self.h, frag_dev, n_blocks, layers, expected)
+
+    def set_fragments_tree(self, frag_dev, n_blocks, layers, tree, bg_children):
+        dfb_set_fragments_tree(self.h, frag_dev, n_blocks, layers, tree, bg_children)
+
+    def set_background_image(self, image_dev):
+        dfb_set_background_image(self.h, image_dev)
+
+    def assign_samples(self, extra):
+        return dfb_assign_samples(self.h, extra, self.n_tiles)
 
     def composite(self, accumulate=False):
         dfb_composite_frame(self.h, DFB_ACCUMULATE if accumulate else 0)

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libdfb.so")
-SOURCES = ["dfb_runtime.hip", "dfb_kernels.hip", "unet_runtime.hip", "unet_kernels.hip"]
+SOURCES = ["dfb_runtime.hip", "dfb_host.cpp", "dfb_kernels.hip", "unet_runtime.hip", "unet_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -46,6 +46,7 @@ struct FrameArgs {
   int32_t work_shift;          // log2(work_w) if a power of two, else -1
   int32_t big_lds;             // LDS bytes for keys + weights of the K > 32 path
   float bg[4];
+  const float* bg_image;       // [n_tiles][P][4] per-pixel background, or null
   float inv_gamma;
   uint32_t mode;
   int32_t n_acc;               // accumulation id after this frame (>= 1)
@@ -104,7 +105,11 @@ dfb_status frame_view(dfb_ctx* h, FrameView* out, bool want_denoised);
 
 // Kernel entry points for a given fragment type and register-sort cap.
 // dtype: 0 f32, 1 f16.  kcap: 8, 16 or 32 (layers handled in registers).
-const void* frame_kernel(int dtype, int kcap);
+// The persistent frame kernel for a fragment dtype, register-path capacity
+// and tile operation (dfb_tile_op).
+const void* frame_kernel(int dtype, int kcap, int op);
+// Largest-remainder assignment of extra samples (host; dfb_assign_samples_host).
+dfb_status assign_samples(const float* variance, int32_t n_tiles, int64_t extra, int32_t* counts);
 const void* accumulate_kernel();
 const void* tile_variance_kernel();
 const void* validate_kernel(int dtype);

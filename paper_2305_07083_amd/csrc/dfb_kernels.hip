@@ -161,7 +161,7 @@ __device__ __forceinline__ float finish_px(const FrameArgs& a, const Unit& u, in
 // the transmittance in front of layer l.  No lane reads another lane's
 // column, so no barrier is needed.
 template <typename FT, int KMAX>
-__device__ __forceinline__ float4 composite_px_upfront(const FrameArgs& a,
+__device__ __forceinline__ float4 composite_px_upfront(float& Tout, const FrameArgs& a,
                                                        const int64_t* __restrict__ loff, int K,
                                                        int off, int p, float* __restrict__ wl,
                                                        int NT) {
@@ -214,15 +214,15 @@ __device__ __forceinline__ float4 composite_px_upfront(const FrameArgs& a,
       B = fmaf(w, cb[l], B);
     }
   }
-  return make_float4(fmaf(T, a.bg[0], R), fmaf(T, a.bg[1], G), fmaf(T, a.bg[2], B),
-                     fmaf(T, a.bg[3], A));
+  Tout = T;
+  return make_float4(R, G, B, A);
 }
 
 // Larger K: 5K values per lane no longer fit the register file next to the
 // keys, so depth and alpha are loaded first and the colours only after the
 // walk (two memory round trips per pixel, half the registers).
 template <typename FT, int KMAX>
-__device__ __forceinline__ float4 composite_px_two_phase(const FrameArgs& a,
+__device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const FrameArgs& a,
                                                          const int64_t* __restrict__ loff, int K,
                                                          int off, int p, float* __restrict__ wl,
                                                          int NT) {
@@ -267,16 +267,28 @@ __device__ __forceinline__ float4 composite_px_two_phase(const FrameArgs& a,
       B = fmaf(w, ldf<FT>(b, 2 * P + up), B);
     }
   }
-  return make_float4(fmaf(T, a.bg[0], R), fmaf(T, a.bg[1], G), fmaf(T, a.bg[2], B),
-                     fmaf(T, a.bg[3], A));
+  Tout = T;
+  return make_float4(R, G, B, A);
 }
 
 template <typename FT, int KMAX>
-__device__ __forceinline__ float4 composite_px(const FrameArgs& a, const int64_t* __restrict__ loff,
+__device__ __forceinline__ float4 composite_px(float& T, const FrameArgs& a, const int64_t* __restrict__ loff,
                                                int K, int off, int p, float* __restrict__ wl,
                                                int NT) {
-  if constexpr (KMAX <= 16) return composite_px_upfront<FT, KMAX>(a, loff, K, off, p, wl, NT);
-  else return composite_px_two_phase<FT, KMAX>(a, loff, K, off, p, wl, NT);
+  if constexpr (KMAX <= 16) return composite_px_upfront<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
+  else return composite_px_two_phase<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
+}
+
+// The background (the generation-0 tile) behind whatever transmittance T is
+// left: a constant colour, or a per-pixel image when one is configured.
+__device__ __forceinline__ float4 with_background(const FrameArgs& a, int t, int p, float4 x, float T) {
+  float4 bg;
+  if (a.bg_image) {
+    bg = reinterpret_cast<const float4*>(a.bg_image)[static_cast<size_t>(t) * a.P + p];
+  } else {
+    bg = make_float4(a.bg[0], a.bg[1], a.bg[2], a.bg[3]);
+  }
+  return make_float4(fmaf(T, bg.x, x.x), fmaf(T, bg.y, x.y), fmaf(T, bg.z, x.z), fmaf(T, bg.w, x.w));
 }
 
 template <typename FT, int KMAX>
@@ -287,8 +299,9 @@ __device__ float unit_reg(const FrameArgs& a, const Unit& u, const int64_t* __re
   for (int q = tid; q < a.work_px; q += NT) {
     bool inside;
     const int p = unit_pixel(a, u, q, inside);
-    const float4 x = composite_px<FT, KMAX>(a, loff, K, off, p, lds + tid, NT);
-    vs += finish_px(a, u, p, inside, x);
+    float T;
+    const float4 x = composite_px<FT, KMAX>(T, a, loff, K, off, p, lds + tid, NT);
+    vs += finish_px(a, u, p, inside, with_background(a, u.t, p, x, T));
   }
   return vs;
 }
@@ -299,7 +312,107 @@ __device__ float unit_background(const FrameArgs& a, const Unit& u) {
   for (int q = threadIdx.x; q < a.work_px; q += NT) {
     bool inside;
     const int p = unit_pixel(a, u, q, inside);
-    vs += finish_px(a, u, p, inside, make_float4(a.bg[0], a.bg[1], a.bg[2], a.bg[3]));
+    vs += finish_px(a, u, p, inside, with_background(a, u.t, p, make_float4(0.f, 0.f, 0.f, 0.f), 1.f));
+  }
+  return vs;
+}
+
+// Rank-order list (the paper's alternative when a per-rank order is correct):
+// the tile's layers, ordered by generation (their source_id) back to front,
+// are blended front to back from the highest generation down -- no depth is
+// read and nothing is sorted.
+template <typename FT>
+__device__ float unit_list(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff, int K,
+                           int off) {
+  const int NT = blockDim.x;
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
+  float vs = 0.f;
+  for (int q = threadIdx.x; q < a.work_px; q += NT) {
+    bool inside;
+    const int p = unit_pixel(a, u, q, inside);
+    const uint32_t up = static_cast<uint32_t>(p);
+    float R = 0.f, G = 0.f, B = 0.f, A = 0.f, T = 1.f;
+    int i = 0;
+    for (; i + 4 <= K; i += 4) {  // 4 layers' loads in flight
+      float cr[4], cg[4], cb[4], al[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const FT* __restrict__ b = frag + loff[K - 1 - (i + j)];
+        cr[j] = ldf<FT>(b, up);
+        cg[j] = ldf<FT>(b, P + up);
+        cb[j] = ldf<FT>(b, 2 * P + up);
+        al[j] = ldf<FT>(b, 3 * P + up);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        R = fmaf(T, cr[j], R);
+        G = fmaf(T, cg[j], G);
+        B = fmaf(T, cb[j], B);
+        A = fmaf(T, al[j], A);
+        T = T * (1.f - al[j]);
+        if (a.mode & kModeKeepOrder)
+          a.order[static_cast<size_t>(off + i + j) * P + p] = static_cast<uint16_t>(K - 1 - (i + j));
+      }
+    }
+    for (; i < K; ++i) {
+      const FT* __restrict__ b = frag + loff[K - 1 - i];
+      const float al = ldf<FT>(b, 3 * P + up);
+      R = fmaf(T, ldf<FT>(b, up), R);
+      G = fmaf(T, ldf<FT>(b, P + up), G);
+      B = fmaf(T, ldf<FT>(b, 2 * P + up), B);
+      A = fmaf(T, al, A);
+      T = T * (1.f - al);
+      if (a.mode & kModeKeepOrder)
+        a.order[static_cast<size_t>(off + i) * P + p] = static_cast<uint16_t>(K - 1 - i);
+    }
+    vs += finish_px(a, u, p, inside, with_background(a, u.t, p, make_float4(R, G, B, A), T));
+  }
+  return vs;
+}
+
+// Averaging tile operation (redundant sampling, the paper's dynamic load
+// balancing): the finished pixel is the mean of the K tiles' RGBA; a tile
+// with no layers shows the background.
+template <typename FT>
+__device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff, int K) {
+  const int NT = blockDim.x;
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
+  const float inv = K > 0 ? 1.f / static_cast<float>(K) : 0.f;
+  float vs = 0.f;
+  for (int q = threadIdx.x; q < a.work_px; q += NT) {
+    bool inside;
+    const int p = unit_pixel(a, u, q, inside);
+    const uint32_t up = static_cast<uint32_t>(p);
+    float R = 0.f, G = 0.f, B = 0.f, A = 0.f;
+    int l = 0;
+    for (; l + 4 <= K; l += 4) {
+      float v[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const FT* __restrict__ b = frag + loff[l + j];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[j][c] = ldf<FT>(b, c * P + up);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        R += v[j][0];
+        G += v[j][1];
+        B += v[j][2];
+        A += v[j][3];
+      }
+    }
+    for (; l < K; ++l) {
+      const FT* __restrict__ b = frag + loff[l];
+      R += ldf<FT>(b, up);
+      G += ldf<FT>(b, P + up);
+      B += ldf<FT>(b, 2 * P + up);
+      A += ldf<FT>(b, 3 * P + up);
+    }
+    const float4 x = K > 0 ? make_float4(R * inv, G * inv, B * inv, A * inv)
+                           : with_background(a, u.t, p, make_float4(0.f, 0.f, 0.f, 0.f), 1.f);
+    vs += finish_px(a, u, p, inside, x);
   }
   return vs;
 }
@@ -533,10 +646,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         acc.z += v.z;
         acc.w += v.w;
       }
-      const float Te = tend[gm];
-      const float4 x = make_float4(fmaf(Te, a.bg[0], acc.x), fmaf(Te, a.bg[1], acc.y),
-                                   fmaf(Te, a.bg[2], acc.z), fmaf(Te, a.bg[3], acc.w));
-      vs += finish_px(a, u, p_me, in_me, x);
+      vs += finish_px(a, u, p_me, in_me, with_background(a, u.t, p_me, acc, tend[gm]));
     }
     __syncthreads();
   }
@@ -591,7 +701,7 @@ constexpr int min_waves(int kcap) {
                                 : (DFB_WAVES_K32 > 0 ? DFB_WAVES_K32 : 1);
 }
 
-template <typename FT, int KCAP>
+template <typename FT, int KCAP, int OP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(KCAP))))
 frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
                const int64_t* __restrict__ layer_off, const int32_t* __restrict__ work_list) {
@@ -623,6 +733,11 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
     const int64_t* __restrict__ blk = layer_off + off;
     float* wl = reinterpret_cast<float*>(lds);
     float vs;
+    if constexpr (OP == DFB_OP_AVERAGE) {
+      vs = unit_average<FT>(a, u, blk, K);
+    } else if constexpr (OP == DFB_OP_LIST) {
+      vs = K == 0 ? unit_background(a, u) : unit_list<FT>(a, u, blk, K, off);
+    } else {
     if (K == 0) vs = unit_background(a, u);
     else if (K <= 1) vs = unit_reg<FT, 1>(a, u, blk, K, off, wl);
     else if (K <= 2) vs = unit_reg<FT, 2>(a, u, blk, K, off, wl);
@@ -635,6 +750,7 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
     else if (KCAP >= 32 && K <= 24) vs = unit_reg<FT, (KCAP >= 32 ? 24 : 1)>(a, u, blk, K, off, wl);
     else if (KCAP >= 32 && K <= 32) vs = unit_reg<FT, (KCAP >= 32 ? 32 : 1)>(a, u, blk, K, off, wl);
     else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
+    }
     const bool acc = (a.mode & kModeAccumulate) != 0;
     if (acc) {
       vs = wave_sum(vs);  // fixed-order reductions only: deterministic
@@ -709,15 +825,19 @@ __global__ void __launch_bounds__(256) validate_kernel_t(ValidateArgs a) {
 
 }  // namespace
 
-const void* frame_kernel(int dtype, int kcap) {
+const void* frame_kernel(int dtype, int kcap, int op) {
   if (dtype == 0) {
-    if (kcap <= 8) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8>);
-    if (kcap <= 16) return reinterpret_cast<const void*>(&frame_kernel_t<float, 16>);
-    return reinterpret_cast<const void*>(&frame_kernel_t<float, 32>);
+    if (op == DFB_OP_LIST) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8, DFB_OP_LIST>);
+    if (op == DFB_OP_AVERAGE) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8, DFB_OP_AVERAGE>);
+    if (kcap <= 8) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8, 0>);
+    if (kcap <= 16) return reinterpret_cast<const void*>(&frame_kernel_t<float, 16, 0>);
+    return reinterpret_cast<const void*>(&frame_kernel_t<float, 32, 0>);
   }
-  if (kcap <= 8) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 8>);
-  if (kcap <= 16) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 16>);
-  return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 32>);
+  if (op == DFB_OP_LIST) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 8, DFB_OP_LIST>);
+  if (op == DFB_OP_AVERAGE) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 8, DFB_OP_AVERAGE>);
+  if (kcap <= 8) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 8, 0>);
+  if (kcap <= 16) return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 16, 0>);
+  return reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 32, 0>);
 }
 
 const void* accumulate_kernel() { return reinterpret_cast<const void*>(&accumulate_kernel_t); }

@@ -15,6 +15,7 @@
 
 #include "../../include/dfb.h"
 #include "dfb_internal.h"
+#include "dfb_tree.h"
 
 namespace {
 
@@ -25,11 +26,11 @@ std::string g_create_error;
 enum class State { kEmpty, kReady, kComposited };
 
 struct AutotuneKey {
-  int device, width, height, tile_w, tile_h, dtype, max_k;
+  int device, width, height, tile_w, tile_h, dtype, op, max_k;
   uint64_t digest;
   bool operator<(const AutotuneKey& o) const {
-    return std::tie(device, width, height, tile_w, tile_h, dtype, max_k, digest) <
-           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.max_k, o.digest);
+    return std::tie(device, width, height, tile_w, tile_h, dtype, op, max_k, digest) <
+           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.op, o.max_k, o.digest);
   }
 };
 struct Shape {
@@ -59,6 +60,7 @@ struct dfb_ctx {
   uint16_t* order = nullptr;
   size_t order_cap = 0;
   float* denoised = nullptr;  // dfb_denoise result
+  const float* bg_image = nullptr;  // borrowed background texture, or null
   int acc_n = 0;          // frames folded in
   bool have_finished = false;
 
@@ -172,6 +174,18 @@ dfb_status check_config(const dfb_config* c, std::string& msg) {
   }
   if (!(c->tonemap_gamma > 0.f) || !std::isfinite(c->tonemap_gamma)) { msg = "tonemap_gamma must be > 0"; return DFB_ERR_INVALID_ARG; }
   if (c->flags & ~(DFB_VALIDATE | DFB_KEEP_SORT_ORDER | DFB_KEEP_FINISHED)) { msg = "unknown flag"; return DFB_ERR_INVALID_ARG; }
+  if (c->tile_op != DFB_OP_ALPHA_BLEND && c->tile_op != DFB_OP_LIST && c->tile_op != DFB_OP_AVERAGE) {
+    msg = "tile_op must be DFB_OP_ALPHA_BLEND, DFB_OP_LIST or DFB_OP_AVERAGE";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (c->tile_op == DFB_OP_AVERAGE && (c->flags & DFB_KEEP_SORT_ORDER)) {
+    msg = "DFB_KEEP_SORT_ORDER has no meaning for DFB_OP_AVERAGE";
+    return DFB_ERR_INVALID_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(c->background_image) % 16) {
+    msg = "background_image must be 16-byte aligned";
+    return DFB_ERR_INVALID_ARG;
+  }
   return DFB_OK;
 }
 
@@ -192,6 +206,11 @@ dfb_status validate_layers(const dfb_config* c, int64_t n_blocks, const dfb_laye
     }
     if (L.block < 0 || L.block >= n_blocks) {
       msg = "layer " + std::to_string(i) + ": block " + std::to_string(L.block) + " out of range";
+      return DFB_ERR_INVALID_ARG;
+    }
+    if (c->tile_op == DFB_OP_LIST && L.source_id == 0) {
+      msg = "layer " + std::to_string(i) + ": DFB_OP_LIST takes the generation as source_id, and generation 0 "
+            "is the background tile";
       return DFB_ERR_INVALID_ARG;
     }
     counts[L.tile_id]++;
@@ -272,7 +291,7 @@ std::vector<Shape> candidates(const dfb_config& c, int max_k) {
   if (c.waves_per_tile) waves.push_back(c.waves_per_tile);
   else waves = {1, 2, 4};
   std::vector<int> ldss{dfb::big_lds_bytes(max_k)};
-  if (max_k > 128) ldss.push_back(64 * 1024);
+  if (max_k > 128 && c.tile_op == DFB_OP_ALPHA_BLEND) ldss.push_back(64 * 1024);
   std::vector<Shape> out;
   for (auto& s : sizes)
     for (int w : waves)
@@ -339,6 +358,7 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   for (int k = 0; k < 16; ++k)
     if ((1 << k) == h->shape.work_w) a.work_shift = k;
   for (int c = 0; c < 4; ++c) a.bg[c] = h->cfg.background[c];
+  a.bg_image = h->bg_image;
   a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
   a.mode = mode;
   a.n_acc = h->acc_n;
@@ -392,8 +412,10 @@ dfb::VarianceArgs make_var_args(dfb_ctx* h) {
 dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0 = nullptr,
                         hipEvent_t t1 = nullptr) {
   const int threads = 64 * h->shape.waves;
-  const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap);
-  const size_t lds = dfb::frame_lds_bytes(h->kcap, threads, h->max_k, h->shape.big_lds);
+  const bool sorting = h->cfg.tile_op == DFB_OP_ALPHA_BLEND;
+  const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap, h->cfg.tile_op);
+  // the list and averaging operations keep nothing in LDS
+  const size_t lds = sorting ? dfb::frame_lds_bytes(h->kcap, threads, h->max_k, h->shape.big_lds) : 0;
   const bool acc = (mode & dfb::kModeAccumulate) != 0;
   int grid = 0;
   dfb_status st = grid_for(h, func, threads, lds, grid);
@@ -460,7 +482,7 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0
 
 dfb_status autotune(dfb_ctx* h) {
   AutotuneKey key{h->device, h->cfg.width, h->cfg.height, h->cfg.tile_w, h->cfg.tile_h,
-                  h->cfg.frag_dtype, h->max_k, h->digest};
+                  h->cfg.frag_dtype, h->cfg.tile_op, h->max_k, h->digest};
   auto cands = candidates(h->cfg, h->max_k);
   if (cands.size() == 1) {
     h->shape = cands[0];
@@ -585,6 +607,7 @@ const char* dfb_status_string(dfb_status s) {
     case DFB_ERR_OOM: return "out of memory";
     case DFB_ERR_HIP: return "HIP error";
     case DFB_ERR_UNSUPPORTED: return "unsupported";
+    case DFB_ERR_TREE: return "dependency tree received more tiles than declared";
   }
   return "unknown status";
 }
@@ -622,6 +645,7 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
   dfb_ctx* h = new (std::nothrow) dfb_ctx();
   if (!h) return fail(nullptr, DFB_ERR_OOM, "host allocation failed");
   h->cfg = *cfg;
+  h->bg_image = cfg->background_image;
   h->stream = static_cast<hipStream_t>(hip_stream);
   auto bail = [&](dfb_status st) {
     g_create_error = h->err;
@@ -770,6 +794,73 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
     if (s != DFB_OK) return s;
   }
   h->state = State::kReady;
+  return DFB_OK;
+}
+
+dfb_status dfb_set_fragments_tree(dfb_handle h, const void* frag_dev, int64_t n_blocks, const dfb_layer* layers,
+                                  const dfb_tree_node* tree, int32_t n_layers, const int32_t* bg_children) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (n_layers < 0 || (n_layers > 0 && (!layers || !tree)) || !bg_children)
+    return fail(h, DFB_ERR_INVALID_ARG, "layers, tree and bg_children are required");
+  std::vector<dfb::TileTree> trees(h->n_tiles);
+  for (int t = 0; t < h->n_tiles; ++t) {
+    trees[t].reset();
+    bool done;
+    if (bg_children[t] < 0) return fail(h, DFB_ERR_INVALID_ARG, "tile " + std::to_string(t) + ": negative children");
+    trees[t].add(0, bg_children[t], done);
+  }
+  for (int32_t i = 0; i < n_layers; ++i) {
+    const dfb_layer& L = layers[i];
+    const dfb_tree_node& N = tree[i];
+    if (L.tile_id < 0 || L.tile_id >= h->n_tiles)
+      return fail(h, DFB_ERR_INVALID_ARG, "layer " + std::to_string(i) + ": tile_id out of range");
+    if (N.generation < 1 || N.generation > dfb::kMaxGeneration || N.children < 0)
+      return fail(h, DFB_ERR_INVALID_ARG, "layer " + std::to_string(i) + ": generation must be in [1, " +
+                                              std::to_string(dfb::kMaxGeneration) + "], children >= 0");
+    bool done;
+    if (!trees[L.tile_id].add(N.generation, N.children, done))
+      return fail(h, DFB_ERR_TREE, "tile " + std::to_string(L.tile_id) + ": layer " + std::to_string(i) +
+                                       " is more than its dependency tree declared");
+  }
+  for (int t = 0; t < h->n_tiles; ++t)
+    if (trees[t].state() != dfb::TileTree::kComplete)
+      return fail(h, DFB_ERR_INCOMPLETE, "tile " + std::to_string(t) + ": generation " +
+                                             std::to_string(trees[t].generation()) + " still waits for " +
+                                             std::to_string(trees[t].missing()) + " tiles");
+  if (h->cfg.tile_op != DFB_OP_LIST) return dfb_set_fragments(h, frag_dev, n_blocks, layers, n_layers, nullptr);
+  // a list: one tile per generation, blended by generation
+  std::vector<dfb_layer> byg(layers, layers + n_layers);
+  for (int32_t i = 0; i < n_layers; ++i) {
+    if (trees[layers[i].tile_id].count(tree[i].generation) != 1)
+      return fail(h, DFB_ERR_INVALID_ARG, "tile " + std::to_string(layers[i].tile_id) +
+                                              ": DFB_OP_LIST needs one tile per generation");
+    byg[i].source_id = static_cast<uint32_t>(tree[i].generation);
+  }
+  return dfb_set_fragments(h, frag_dev, n_blocks, byg.data(), n_layers, nullptr);
+}
+
+dfb_status dfb_set_background_image(dfb_handle h, const float* image_dev) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (reinterpret_cast<uintptr_t>(image_dev) % 16)
+    return fail(h, DFB_ERR_INVALID_ARG, "background image must be 16-byte aligned");
+  h->bg_image = image_dev;
+  h->cfg.background_image = image_dev;
+  return DFB_OK;
+}
+
+dfb_status dfb_assign_samples(dfb_handle h, int64_t extra, int32_t* counts) {
+  dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  if (!counts || extra < 0 || extra > INT32_MAX) return fail(h, DFB_ERR_INVALID_ARG, "bad extra or counts");
+  std::vector<float> v(h->n_tiles, INFINITY);  // uniform before two accumulated frames
+  if (h->acc_n >= 2) {
+    DFB_HIP(h, hipMemcpyAsync(v.data(), h->tile_var, v.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    DFB_HIP(h, hipStreamSynchronize(h->stream));
+  }
+  s = dfb::assign_samples(v.data(), h->n_tiles, extra, counts);
+  if (s != DFB_OK) return fail(h, s, "sample assignment failed");
   return DFB_OK;
 }
 

@@ -78,6 +78,9 @@ def test_validate_layers_counts_and_errors(dfb):
     (dict(width=64, height=64, gamma=0.0), -1),
     (dict(width=64, height=64, flags=0x80), -1),
     (dict(width=1 << 20, height=1 << 20, tile_w=16), -6),
+    (dict(width=64, height=64, op=3), -1),
+    (dict(width=64, height=64, op=2, flags=0x2), -1),       # sort order means nothing for AVERAGE
+    (dict(width=64, height=64, background_image=0x1008), -1),  # not 16-byte aligned
 ])
 def test_config_errors(dfb, kw, status):
     kw = dict(kw)
@@ -87,6 +90,20 @@ def test_config_errors(dfb, kw, status):
     with pytest.raises(dfb.DfbError) as e:
         dfb.dfb_validate_layers(cfg, 0, np.zeros(0, dtype=dfb.LAYER_DTYPE))
     assert e.value.status == status
+
+
+def test_list_op_rejects_generation_zero(dfb):
+    lay = np.zeros(2, dtype=dfb.LAYER_DTYPE)
+    lay["source_id"] = [1, 2]
+    lay["block"] = [0, 1]
+    cfg = dfb.make_config(64, 64, 64, op=dfb.DFB_OP_LIST)
+    assert dfb.dfb_validate_layers(cfg, 2, lay).tolist() == [2]
+    lay["source_id"] = [0, 2]
+    with pytest.raises(dfb.DfbError) as e:
+        dfb.dfb_validate_layers(cfg, 2, lay)
+    assert e.value.status == dfb.DFB_ERR_INVALID_ARG
+    # the other operations take any source id
+    assert dfb.dfb_validate_layers(dfb.make_config(64, 64, 64, op=dfb.DFB_OP_AVERAGE), 2, lay).tolist() == [2]
 
 
 def test_sorting_network_zero_one_principle(tmp_path):

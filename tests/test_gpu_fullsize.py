@@ -129,3 +129,44 @@ def test_zipf_8192_sampled_tiles(dfb):
         assert np.array_equal(gord, ref["order"][i, :, :K[t]]), t
     del frag
     torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(300)
+def test_list_2048_every_pixel(dfb):
+    """The 2048x2048 brick frame as a generation list, in the benchmark's
+    launch configuration: every pixel against the oracle's list operation,
+    and (the rank order being correct for this view) against its sort."""
+    f = workloads.bricks_2048_list()
+    cfg = dfb.make_config(2048, 2048, 64, work=0, waves=0, op=dfb.DFB_OP_LIST,
+                          flags=dfb.DFB_KEEP_FINISHED | dfb.DFB_KEEP_SORT_ORDER)
+    buf = upload(f.frag)
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        c.set_fragments(buf, f.frag.shape[0], f.layers, f.expected)
+        c.composite()
+        got = c.read(dfb.DFB_BUF_FINISHED_F32)
+        final = c.read(dfb.DFB_BUF_FINAL)
+        order = c.read(dfb.DFB_BUF_SORT_ORDER)
+    ref = oracle.composite(f.frag, f.layers, 2048, 2048, 64, 64, expected=f.expected, want_mag=True,
+                           want_order=True, op="list")
+    assert_colour(got, ref["rgba"], ref["mag"], "list 2048")
+    assert_rgba8(final, ref["rgba"], what="list 2048")
+    gord = order_as_sources(order, f.layers, np.arange(f.n_tiles), f.expected, f.P)
+    for t in range(f.n_tiles):
+        assert np.array_equal(gord[t], ref["order"][t, :, :f.expected[t]]), t
+    srt = oracle.composite(f.frag, workloads.c2().layers, 2048, 2048, 64, 64, want_mag=True)
+    assert_colour(got, srt["rgba"], srt["mag"], "list 2048 vs per-pixel sort")
+
+
+@pytest.mark.timeout(300)
+def test_average_2048_every_pixel(dfb):
+    f = workloads.redundant_2048()
+    cfg = dfb.make_config(2048, 2048, 64, work=0, waves=0, op=dfb.DFB_OP_AVERAGE, flags=dfb.DFB_KEEP_FINISHED)
+    buf = upload(f.frag)
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        c.set_fragments(buf, f.frag.shape[0], f.layers, f.expected)
+        c.composite()
+        got = c.read(dfb.DFB_BUF_FINISHED_F32)
+        final = c.read(dfb.DFB_BUF_FINAL)
+    ref = oracle.composite(f.frag, f.layers, 2048, 2048, 64, 64, expected=f.expected, want_mag=True, op="average")
+    assert_colour(got, ref["rgba"], ref["mag"], "average 2048")
+    assert_rgba8(final, ref["rgba"], what="average 2048")

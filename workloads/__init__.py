@@ -408,3 +408,168 @@ class DeviceNoise:
                             dtype=torch.float32)
         self.out[:, 0:3, :] += noise * self.mask
         return self.out
+
+
+# --------------------------------------------------------------------------
+# Inputs of the other tile operations: generation lists, redundant renders,
+# multi-generation trees and background textures
+# --------------------------------------------------------------------------
+def ragged_counts(n_tiles, kmax, seed, p_empty=0.1):
+    """Per-tile layer counts: 0 with probability p_empty, else U{1..kmax}.
+    Draws: U(0,1) [n_tiles], then the integers [n_tiles]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    empty = rng.random(n_tiles) < p_empty
+    k = rng.integers(1, kmax + 1, size=n_tiles)
+    return np.where(empty, 0, k).astype(np.int32)
+
+
+def generation_frame(width, height, tile, counts, seed, depth_by_generation=True, name="generations"):
+    """Tile t holds counts[t] layers whose source ids are the generations
+    1..counts[t]; alpha ~ U(0,1), colour = alpha * U(0,1).  Depth: with
+    ``depth_by_generation`` generation g of K lies in the slab
+    ((K - g + U) / (K + 1)), so a higher generation is nearer at every
+    pixel (a rank order that is correct); else U(0,1).
+
+    Draw order: alpha [L, P], U [L, 3, P], U_depth [L, P] (L = sum counts,
+    layers tile by tile, generation ascending), then the arrival permutation.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tiles_x, tiles_y = -(-width // tile), -(-height // tile)
+    T, P = tiles_x * tiles_y, tile * tile
+    counts = np.asarray(counts, dtype=np.int64)
+    assert len(counts) == T
+    L = int(counts.sum())
+    tile_ids = np.repeat(np.arange(T, dtype=np.int32), counts)
+    gens = (np.arange(L) - np.repeat(np.cumsum(counts) - counts, counts) + 1).astype(np.int64)
+    Ks = np.repeat(counts, counts).astype(np.float32)
+    alpha = rng.random((L, P), dtype=np.float32)
+    U = rng.random((L, 3, P), dtype=np.float32)
+    ud = rng.random((L, P), dtype=np.float32)
+    frag = np.empty((L, 5, P), dtype=np.float32)
+    frag[:, 0:3, :] = alpha[:, None, :] * U
+    frag[:, 3, :] = alpha
+    if depth_by_generation:
+        frag[:, 4, :] = (Ks[:, None] - gens[:, None].astype(np.float32) + ud) / (Ks[:, None] + 1)
+    else:
+        frag[:, 4, :] = ud
+    layers = np.empty(L, dtype=LAYER_DTYPE)
+    layers["tile_id"] = tile_ids
+    layers["source_id"] = gens.astype(np.uint32)
+    layers["block"] = np.arange(L, dtype=np.int64)
+    layers = _shuffle_arrival(rng, layers)
+    return Frame(width, height, tile, tile, frag, layers, counts.astype(np.int32),
+                 np.ones((L, P), dtype=bool), name)
+
+
+def redundant_frame(width, height, tile, counts, sigma, seed, name="redundant"):
+    """Redundant renders for dynamic load balancing: tile t is rendered
+    counts[t] times with different seeds; render r of a tile is a fixed
+    image (alpha ~ U(0.2,1), colour = alpha * U(0,1)) plus N(0, sigma) per
+    RGBA channel, depth 0.  Source ids are 0..counts[t]-1.
+
+    Draw order: base alpha [T, P], base U [T, 3, P], then one normal
+    [L, 4, P] (layers tile by tile), then the arrival permutation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tiles_x, tiles_y = -(-width // tile), -(-height // tile)
+    T, P = tiles_x * tiles_y, tile * tile
+    counts = np.asarray(counts, dtype=np.int64)
+    assert len(counts) == T
+    L = int(counts.sum())
+    a = (0.2 + 0.8 * rng.random((T, P), dtype=np.float32)).astype(np.float32)
+    U = rng.random((T, 3, P), dtype=np.float32)
+    base = np.empty((T, 4, P), dtype=np.float32)
+    base[:, 0:3] = a[:, None, :] * U
+    base[:, 3] = a
+    noise = rng.standard_normal((L, 4, P), dtype=np.float32) * np.float32(sigma)
+    tile_ids = np.repeat(np.arange(T, dtype=np.int32), counts)
+    frag = np.zeros((L, 5, P), dtype=np.float32)
+    frag[:, 0:4] = base[tile_ids] + noise
+    layers = np.empty(L, dtype=LAYER_DTYPE)
+    layers["tile_id"] = tile_ids
+    layers["source_id"] = (np.arange(L) - np.repeat(np.cumsum(counts) - counts, counts)).astype(np.uint32)
+    layers["block"] = np.arange(L, dtype=np.int64)
+    layers = _shuffle_arrival(rng, layers)
+    return Frame(width, height, tile, tile, frag, layers, counts.astype(np.int32),
+                 np.ones((L, P), dtype=bool), name), base
+
+
+def background_texture(n_tiles, P, seed):
+    """A background texture [n_tiles, P, 4]: alpha ~ U(0,1), colour =
+    alpha * U(0,1) (premultiplied), float32.  Draws: alpha [T, P], U [T, P, 3]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.random((n_tiles, P), dtype=np.float32)
+    U = rng.random((n_tiles, P, 3), dtype=np.float32)
+    out = np.empty((n_tiles, P, 4), dtype=np.float32)
+    out[..., 0:3] = a[..., None] * U
+    out[..., 3] = a
+    return out
+
+
+def random_trees(n_tiles, seed, max_gen=3, max_children=3):
+    """One complete dependency tree per tile, built top down: the background
+    tile declares c0 ~ U{0..max_children} children, each tile of generation g
+    < max_gen declares U{0..max_children} (0 at max_gen), and exactly the
+    declared number of tiles is made for every generation.  Returns
+    (bg_children [n_tiles], per-layer tile ids, generations, children), the
+    layers tile by tile, generation ascending.  Draws: the integers in that
+    order, tile by tile."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    bg = np.zeros(n_tiles, dtype=np.int32)
+    tid, gen, ch = [], [], []
+    for t in range(n_tiles):
+        c0 = int(rng.integers(0, max_children + 1))
+        bg[t] = c0
+        want, g = c0, 1
+        while want > 0:
+            nxt = 0
+            for _ in range(want):
+                c = int(rng.integers(0, max_children + 1)) if g < max_gen else 0
+                tid.append(t)
+                gen.append(g)
+                ch.append(c)
+                nxt += c
+            want, g = nxt, g + 1
+    return (bg, np.asarray(tid, dtype=np.int32), np.asarray(gen, dtype=np.int32),
+            np.asarray(ch, dtype=np.int32))
+
+
+def brick_generations(bricks=(4, 4, 4), azimuth=30.0, elevation=25.0):
+    """Generation of every brick when a frame's tiles are handed over as a
+    list ordered back to front: 1 for the brick whose centre lies farthest
+    along the view direction, increasing towards the camera; among equal
+    centre depths the larger brick id is taken as the farther one.
+    Returns uint32 [n_bricks] indexed by brick id (the frame's source id)."""
+    d, _, _ = camera_basis(azimuth, elevation)
+    nx, ny, nz = bricks
+    n = nx * ny * nz
+    depth = np.empty(n)
+    for b in range(n):
+        bx, by, bz = b % nx, (b // nx) % ny, b // (nx * ny)
+        depth[b] = float(np.dot(d, [(bx + 0.5) / nx, (by + 0.5) / ny, (bz + 0.5) / nz]))
+    back_to_front = sorted(range(n), key=lambda b: (-depth[b], -b))
+    gen = np.empty(n, dtype=np.uint32)
+    for i, b in enumerate(back_to_front):
+        gen[b] = i + 1
+    return gen
+
+
+def as_generation_list(frame: Frame, generations):
+    """The same frame with every layer's source id replaced by its brick's
+    generation (input of the list tile operation)."""
+    lay = frame.layers.copy()
+    lay["source_id"] = np.asarray(generations, dtype=np.uint32)[lay["source_id"]]
+    return dataclasses.replace(frame, layers=lay, name=frame.name + "-list")
+
+
+def bricks_2048_list(seed=0):
+    """The 2048x2048 4x4x4-brick frame handed over as a generation list
+    (input of the list tile operation at full size)."""
+    return as_generation_list(c2(seed), brick_generations((4, 4, 4)))
+
+
+def redundant_2048(seed=0, kmax=8, sigma=0.2):
+    """2048x2048, 64x64 tiles, every tile rendered U{1..kmax} times (input of
+    the averaging tile operation at full size)."""
+    counts = ragged_counts(32 * 32, kmax, seed, p_empty=0.0)
+    f, _ = redundant_frame(2048, 2048, 64, counts, sigma, seed + 1, name="redundant-2048")
+    return f
