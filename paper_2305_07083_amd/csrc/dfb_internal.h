@@ -13,6 +13,15 @@ namespace dfb {
 constexpr int kRegMax = 32;
 // Largest layer count per tile the LDS sort supports (keys + weights of one
 // pixel must fit the LDS budget below).
+// Work queue: the work list is dealt round-robin to kQueues counters, each
+// in its own 4 KB page, served first by the workgroups with the same index
+// mod kQueues, so same-address atomics do not serialise the whole chip.
+// Each counter has kSlots per-frame slots used as a ring: frame f counts in
+// slot f mod kSlots and clears slot (f + kSlots/2) mod kSlots, which no
+// frame in flight uses, so nothing is reset between frames.
+constexpr int kQueues = 16;
+constexpr int kQueueStride = 1024;  // 4-byte counters between queues
+constexpr int kSlots = 64;
 constexpr int kMaxLayers = 4096;
 // Largest LDS budget of the large-K path for keys (u64) and weights (f32);
 // the host passes 64, 96 or 112 KB depending on the frame's largest tile.
@@ -37,14 +46,16 @@ enum ModeBits : uint32_t {
 // Passed by value (a graph node's parameters are updated per frame).
 struct FrameArgs {
   const void* frag;            // fragment blocks (caller's buffer)
-  unsigned long long* queue;   // work-queue counter (monotonic across frames)
-  unsigned long long q_base;   // queue value at this frame's start
+  uint32_t* queue;             // kQueues x kSlots counters, queues kQueueStride apart
+  int32_t slot, clear_slot;    // this frame's counter slot; the slot it clears
+  int32_t n_queues;            // counters in use: min(kQueues, grid)
   int32_t n_work;
   int32_t width, height, tiles_x, n_tiles;
   int32_t tile_w, tile_h, P;
   int32_t work_w, work_h, subs_x, subs_per_tile, work_px;
   int32_t work_shift;          // log2(work_w) if a power of two, else -1
   int32_t big_lds;             // LDS bytes for keys + weights of the K > 32 path
+  int32_t vec_ok;              // 16-byte plane loads possible (alignment, work_w, tile_w)
   float bg[4];
   const float* bg_image;       // [n_tiles][P][4] per-pixel background, or null
   float inv_gamma;

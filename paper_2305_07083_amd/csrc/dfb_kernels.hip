@@ -43,6 +43,11 @@ namespace {
 #ifndef DFB_WAVES_K32
 #define DFB_WAVES_K32 0
 #endif
+// Layers whose plane loads the list and averaging operations keep in flight
+// per lane.
+#ifndef DFB_OP_CHUNK
+#define DFB_OP_CHUNK 4
+#endif
 
 // Plane loads: `base` is uniform across the wave (a layer's block start) and
 // `i` a 32-bit element offset inside the block, so each load is one
@@ -64,6 +69,16 @@ __device__ __forceinline__ float ldf<_Float16>(const _Float16* __restrict__ base
 #else
   return static_cast<float>(base[i]);
 #endif
+}
+
+// Workgroup barrier for LDS traffic only.  Threads of a workgroup share
+// nothing through global memory inside these kernels, so a barrier need not
+// wait for the wave's global stores to complete (which __syncthreads does:
+// that wait costs a memory round trip at every unit boundary).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Order-preserving map of a depth to 32 bits: NaN above everything, -0 == +0.
@@ -371,6 +386,210 @@ __device__ float unit_list(const FrameArgs& a, const Unit& u, const int64_t* __r
   return vs;
 }
 
+// 16-byte plane loads: V consecutive elements of one plane (4 fp32 or 8
+// fp16 pixels), converted to float.  The element offset is a multiple of V
+// and the block start is 16-byte aligned (checked on the host).
+template <typename FT>
+struct VecWidth;
+template <>
+struct VecWidth<float> {
+  static constexpr int V = 4;
+};
+template <>
+struct VecWidth<_Float16> {
+  static constexpr int V = 8;
+};
+
+template <typename FT>
+__device__ __forceinline__ void ldv(const FT* __restrict__ base, uint32_t i, float* out);
+template <>
+__device__ __forceinline__ void ldv<float>(const float* __restrict__ base, uint32_t i, float* out) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(base + i));
+  out[0] = v.x;
+  out[1] = v.y;
+  out[2] = v.z;
+  out[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void ldv<_Float16>(const _Float16* __restrict__ base, uint32_t i, float* out) {
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+  const h8 v = __builtin_nontemporal_load(reinterpret_cast<const h8*>(base + i));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) out[k] = static_cast<float>(v[k]);
+}
+
+// Block offsets of a tile's layers [base, base + 64) held one per lane, so a
+// layer's offset is a register read (no dependent scalar load in the loop).
+__device__ __forceinline__ int64_t lane_offsets(const int64_t* __restrict__ loff, int base, int K) {
+  const int l = base + static_cast<int>(__lane_id());
+  return (l >= 0 && l < K) ? loff[l] : 0;
+}
+__device__ __forceinline__ int64_t offset_of(int64_t held, int k) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(held), k);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(static_cast<uint64_t>(held) >> 32), k);
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// V pixels of one unit row per lane; the finished pixels go through the same
+// per-pixel epilogue as the scalar path.
+template <int V, bool BG>
+__device__ __forceinline__ float finish_row(const FrameArgs& a, const Unit& u, int q0, int p0, const float* R,
+                                            const float* G, const float* B, const float* A, const float* T) {
+  float vs = 0.f;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    bool inside;
+    unit_pixel(a, u, q0 + v, inside);
+    float4 x = make_float4(R[v], G[v], B[v], A[v]);
+    if constexpr (BG) x = with_background(a, u.t, p0 + v, x, T[v]);
+    vs += finish_px(a, u, p0 + v, inside, x);
+  }
+  return vs;
+}
+
+// The list operation with 16-byte loads: C layers' four planes in flight per
+// lane, blended front to back from the highest generation.
+template <typename FT>
+__device__ float unit_list_vec(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff, int K,
+                               int off) {
+  constexpr int V = VecWidth<FT>::V;
+  constexpr int C = DFB_OP_CHUNK;
+  const int NT = blockDim.x;
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
+  float vs = 0.f;
+  // whole waves run the loop (the held offsets need every lane); lanes past
+  // the unit's end load a valid row again and store nothing
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  for (int base = static_cast<int>(threadIdx.x >> 6) * 64 * V; base < a.work_px; base += NT * V) {
+    const bool act = base + lane * V < a.work_px;
+    const int q0 = act ? base + lane * V : base;
+    bool in0;
+    const int p0 = unit_pixel(a, u, q0, in0);
+    const uint32_t up = static_cast<uint32_t>(p0);
+    float R[V], G[V], B[V], A[V], T[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      R[v] = G[v] = B[v] = A[v] = 0.f;
+      T[v] = 1.f;
+    }
+    int i = 0;
+    int64_t held = 0;
+    for (; i + C <= K; i += C) {
+      if ((i & 63) == 0) held = lane_offsets(loff, K - 64 - i, K);  // layers K-64-i .. K-1-i
+      float x[C][4][V];
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const FT* __restrict__ b = frag + offset_of(held, 63 - ((i + j) & 63));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ldv<FT>(b, c * P + up, x[j][c]);
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          R[v] = fmaf(T[v], x[j][0][v], R[v]);
+          G[v] = fmaf(T[v], x[j][1][v], G[v]);
+          B[v] = fmaf(T[v], x[j][2][v], B[v]);
+          A[v] = fmaf(T[v], x[j][3][v], A[v]);
+          T[v] = T[v] * (1.f - x[j][3][v]);
+        }
+        if ((a.mode & kModeKeepOrder) && act) {
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            a.order[static_cast<size_t>(off + i + j) * P + p0 + v] = static_cast<uint16_t>(K - 1 - (i + j));
+        }
+      }
+    }
+    for (; i < K; ++i) {
+      if ((i & 63) == 0) held = lane_offsets(loff, K - 64 - i, K);
+      float x[4][V];
+      const FT* __restrict__ b = frag + offset_of(held, 63 - (i & 63));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ldv<FT>(b, c * P + up, x[c]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        R[v] = fmaf(T[v], x[0][v], R[v]);
+        G[v] = fmaf(T[v], x[1][v], G[v]);
+        B[v] = fmaf(T[v], x[2][v], B[v]);
+        A[v] = fmaf(T[v], x[3][v], A[v]);
+        T[v] = T[v] * (1.f - x[3][v]);
+      }
+      if ((a.mode & kModeKeepOrder) && act) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          a.order[static_cast<size_t>(off + i) * P + p0 + v] = static_cast<uint16_t>(K - 1 - i);
+      }
+    }
+    if (act) vs += finish_row<V, true>(a, u, q0, p0, R, G, B, A, T);
+  }
+  return vs;
+}
+
+// The averaging operation with 16-byte loads (layers summed in layer order;
+// K > 0: a tile without renders is the background, handled by the caller).
+template <typename FT>
+__device__ float unit_average_vec(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff, int K) {
+  constexpr int V = VecWidth<FT>::V;
+  constexpr int C = DFB_OP_CHUNK;
+  const int NT = blockDim.x;
+  const uint32_t P = static_cast<uint32_t>(a.P);
+  const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
+  const float inv = K > 0 ? 1.f / static_cast<float>(K) : 0.f;
+  float vs = 0.f;
+  // whole waves run the loop (the held offsets need every lane); lanes past
+  // the unit's end load a valid row again and store nothing
+  const int lane = static_cast<int>(threadIdx.x & 63);
+  for (int base = static_cast<int>(threadIdx.x >> 6) * 64 * V; base < a.work_px; base += NT * V) {
+    const bool act = base + lane * V < a.work_px;
+    const int q0 = act ? base + lane * V : base;
+    bool in0;
+    const int p0 = unit_pixel(a, u, q0, in0);
+    const uint32_t up = static_cast<uint32_t>(p0);
+    float S[4][V];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < V; ++v) S[c][v] = 0.f;
+    int l = 0;
+    int64_t held = 0;
+    for (; l + C <= K; l += C) {
+      if ((l & 63) == 0) held = lane_offsets(loff, l, K);
+      float x[C][4][V];
+#pragma unroll
+      for (int j = 0; j < C; ++j) {
+        const FT* __restrict__ b = frag + offset_of(held, (l + j) & 63);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ldv<FT>(b, c * P + up, x[j][c]);
+      }
+#pragma unroll
+      for (int j = 0; j < C; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int v = 0; v < V; ++v) S[c][v] += x[j][c][v];
+    }
+    for (; l < K; ++l) {
+      if ((l & 63) == 0) held = lane_offsets(loff, l, K);
+      float x[4][V];
+      const FT* __restrict__ b = frag + offset_of(held, l & 63);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ldv<FT>(b, c * P + up, x[c]);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < V; ++v) S[c][v] += x[c][v];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int v = 0; v < V; ++v) S[c][v] *= inv;
+    if (act) vs += finish_row<V, false>(a, u, q0, p0, S[0], S[1], S[2], S[3], nullptr);
+  }
+  return vs;
+}
+
 // Averaging tile operation (redundant sampling, the paper's dynamic load
 // balancing): the finished pixel is the mean of the K tiles' RGBA; a tile
 // with no layers shows the background.
@@ -520,7 +739,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     // 2. sort every row: blocks of 16 in registers first
     for (int b = tid; b < nblk; b += NT) {
       uint64_t k[kBlk];
@@ -530,7 +749,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       sort_network<kBlk>(k);
       block_store(r, base, k);
     }
-    __syncthreads();
+    lds_barrier();
     for (int ls = 5; ls <= lk; ++ls) {          // merge size 2^ls
       for (int lt = ls - 1; lt >= 4; --lt) {     // strides >= 16 through LDS
         const int str = 1 << lt;
@@ -559,7 +778,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
             }
           }
         }
-        __syncthreads();
+        lds_barrier();
       }
       for (int b = tid; b < nblk; b += NT) {     // strides 8..1 in registers
         uint64_t k[kBlk];
@@ -569,7 +788,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         block_half_clean(k);
         block_store(r, base, k);
       }
-      __syncthreads();
+      lds_barrier();
     }
     // 3. front-to-back walk: chunk products, exclusive scan over the S chunks.
     //    Rows past the unit's last pixel hold only padding keys: skipped.
@@ -585,10 +804,10 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       prod = prod * (1.f - wrow[kslot(l)]);
     }
     red[tid].x = prod;
-    __syncthreads();
+    lds_barrier();
     float T = 1.f;
     for (int s2 = 0; s2 < sm; ++s2) T = T * red[s2 * G + gm].x;
-    __syncthreads();
+    lds_barrier();
     float Ap = 0.f;
     bool in_me = false;
     const int p_me = live ? unit_pixel(a, u, qme, in_me) : 0;
@@ -602,7 +821,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       if (a.mode & kModeKeepOrder)
         a.order[static_cast<size_t>(off + i) * P + p_me] = static_cast<uint16_t>(l);
     }
-    __syncthreads();
+    lds_barrier();
     // 4. colour in layer order (coalesced over the G pixels), 4 layers per step
     float R = 0.f, Gc = 0.f, B = 0.f;
     if (live) {
@@ -636,7 +855,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     const int last = (K - 1) / C;
     red[tid] = make_float4(R, Gc, B, Ap);
     if (sm == last) tend[gm] = T;
-    __syncthreads();
+    lds_barrier();
     if (sm == 0 && live) {
       float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
       for (int s2 = 0; s2 < S; ++s2) {
@@ -648,7 +867,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       }
       vs += finish_px(a, u, p_me, in_me, with_background(a, u.t, p_me, acc, tend[gm]));
     }
-    __syncthreads();
+    lds_barrier();
   }
   return vs;
 }
@@ -665,20 +884,47 @@ __device__ __forceinline__ float variance_of_mean(float sum, int inside_px, int 
                 static_cast<float>(n - 1));
 }
 
-// Work queue.  take_ticket: lane 0 of the calling wave issues the atomic; the
-// result is only read (ticket_to_unit) at the end of the current unit, so the
-// atomic's latency overlaps the unit's work.  Call both from wave-uniform code.
-__device__ __forceinline__ unsigned long long take_ticket(const FrameArgs& a) {
-  unsigned long long v = 0;
-  if (__lane_id() == 0) v = atomicAdd(a.queue, 1ull);
+// Work queue.  Counter s (of S = n_queues) holds the work-list positions
+// congruent to s, in order; workgroup b starts on counter b mod S, and its
+// first unit there is its rank r = b / S among those workgroups (no
+// atomic).  Each ticket c of a counter names its unit g + c, g being the
+// number of workgroups that start on it.  Lane 0 of wave 0 takes the next
+// ticket at the start of a unit and the result is read at its end, so the
+// atomic's latency hides behind the unit's work.  A drained counter sends
+// the workgroup on to the next one (s + 1, s + 2, ... mod S); a coherent
+// read skips counters that are already drained without an atomic.
+struct Queue {
+  uint32_t* ctr;
+  int s, g, n;
+};
+
+__device__ __forceinline__ Queue queue_of(const FrameArgs& a, int s) {
+  const int S = a.n_queues;
+  Queue q;
+  q.s = s;
+  q.g = (static_cast<int>(gridDim.x) - s + S - 1) / S;
+  q.n = (a.n_work - s + S - 1) / S;
+  q.ctr = a.queue + static_cast<size_t>(s) * kQueueStride + a.slot;
+  return q;
+}
+
+__device__ __forceinline__ uint32_t take_ticket(const Queue& q) {
+  uint32_t v = 0;
+  if (__lane_id() == 0) v = atomicAdd(q.ctr, 1u);
   return v;
 }
 
-__device__ __forceinline__ int ticket_to_unit(const FrameArgs& a, unsigned long long v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-  const unsigned long long d = ((static_cast<unsigned long long>(hi) << 32) | lo) - a.q_base;
-  return d < static_cast<unsigned long long>(a.n_work) ? static_cast<int>(d) : a.n_work;
+__device__ __forceinline__ int ticket_to_unit(const FrameArgs& a, const Queue& q, uint32_t v) {
+  const int64_t j = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(v)) + q.g;
+  return j < q.n ? static_cast<int>(j) * a.n_queues + q.s : a.n_work;
+}
+
+// Whether a counter may still hand out a unit (never wrong the other way:
+// counters only grow within a frame).
+__device__ __forceinline__ bool queue_open(const Queue& q) {
+  uint32_t v = 0;
+  if (__lane_id() == 0) v = __hip_atomic_load(q.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return static_cast<int64_t>(__builtin_amdgcn_readfirstlane(v)) + q.g < q.n;
 }
 
 // A unit's M2 sum (all waves) -> var_partial[w].  Runs on all lanes of wave
@@ -711,15 +957,17 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
   const int tid = threadIdx.x;
   const int n_waves = static_cast<int>(blockDim.x >> 6);
   const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < 64;  // uniform per wave
-  if (wave0) {
-    const int v = ticket_to_unit(a, take_ticket(a));
-    if (__lane_id() == 0) s_item = v;
-  }
-  __syncthreads();
-  int it = __builtin_amdgcn_readfirstlane(s_item);
+  if (blockIdx.x == 0 && tid < kQueues)  // recycle the slot of the frame kSlots/2 ahead
+    __hip_atomic_store(a.queue + static_cast<size_t>(tid) * kQueueStride + a.clear_slot, 0u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  const int home = static_cast<int>(blockIdx.x) % a.n_queues;
+  Queue q = queue_of(a, home);
+  int drained = 0;  // counters this workgroup has found empty
+  const int r = static_cast<int>(blockIdx.x) / a.n_queues;
+  int it = r < q.n ? r * a.n_queues + home : a.n_work;  // the first unit is static
   while (it < a.n_work) {
     // the next unit's ticket is taken now and read after this unit's work
-    const unsigned long long next = wave0 ? take_ticket(a) : 0ull;
+    const uint32_t next = wave0 ? take_ticket(q) : 0u;
     const int w = work_list[it];
     Unit u;
     u.t = w / a.subs_per_tile;
@@ -734,9 +982,10 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
     float* wl = reinterpret_cast<float*>(lds);
     float vs;
     if constexpr (OP == DFB_OP_AVERAGE) {
-      vs = unit_average<FT>(a, u, blk, K);
+      vs = (a.vec_ok && K > 0) ? unit_average_vec<FT>(a, u, blk, K) : unit_average<FT>(a, u, blk, K);
     } else if constexpr (OP == DFB_OP_LIST) {
-      vs = K == 0 ? unit_background(a, u) : unit_list<FT>(a, u, blk, K, off);
+      vs = K == 0 ? unit_background(a, u)
+                  : (a.vec_ok ? unit_list_vec<FT>(a, u, blk, K, off) : unit_list<FT>(a, u, blk, K, off));
     } else {
     if (K == 0) vs = unit_background(a, u);
     else if (K <= 1) vs = unit_reg<FT, 1>(a, u, blk, K, off, wl);
@@ -756,13 +1005,17 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
       vs = wave_sum(vs);  // fixed-order reductions only: deterministic
       if ((tid & 63) == 0) s_red[tid >> 6] = vs;
     }
-    __syncthreads();  // s_red complete; every lane has read s_item
+    lds_barrier();  // s_red complete; every lane has read s_item
     if (wave0) {
       if (acc) store_partial(a, w, s_red, n_waves);
-      const int v = ticket_to_unit(a, next);
+      int v = ticket_to_unit(a, q, next);
+      while (v == a.n_work && ++drained < a.n_queues) {  // move on to the next counter
+        q = queue_of(a, (home + drained) % a.n_queues);
+        if (queue_open(q)) v = ticket_to_unit(a, q, take_ticket(q));
+      }
       if (__lane_id() == 0) s_item = v;
     }
-    __syncthreads();
+    lds_barrier();
     it = __builtin_amdgcn_readfirstlane(s_item);
   }
 }
@@ -797,7 +1050,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel_t(AccumArgs a) {
   }
   vs = wave_sum(vs);
   if ((tid & 63) == 0) s_red[tid >> 6] = vs;
-  __syncthreads();
+  lds_barrier();
   if (__builtin_amdgcn_readfirstlane(tid) < 64) {
     const int n_waves = static_cast<int>(blockDim.x >> 6);
     float sum = 0.f;

@@ -81,9 +81,9 @@ struct dfb_ctx {
   size_t work_cap = 0;
   float* d_var_partial = nullptr;
   size_t partial_cap = 0;
-  unsigned long long* d_queue = nullptr;
   uint32_t* d_flag = nullptr;
-  unsigned long long q_base = 0;
+  uint32_t* d_queue_ring = nullptr;  // kQueues x kSlots counters
+  unsigned long long frame_seq = 0;  // frame launches so far (selects the counter slot)
 
   // launch shape
   Shape shape{0, 0, 0, 64 * 1024};
@@ -338,8 +338,10 @@ dfb_status ensure_accum(dfb_ctx* h) {
 FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   FrameArgs a{};
   a.frag = h->frag;
-  a.queue = h->d_queue;
-  a.q_base = h->q_base;
+  a.queue = h->d_queue_ring;
+  a.slot = static_cast<int32_t>(h->frame_seq % dfb::kSlots);
+  a.clear_slot = static_cast<int32_t>((h->frame_seq + dfb::kSlots / 2) % dfb::kSlots);
+  a.n_queues = 1;  // set by launch_frame once the grid is known
   a.n_work = h->n_work;
   a.width = h->cfg.width;
   a.height = h->cfg.height;
@@ -357,6 +359,11 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   a.work_shift = -1;
   for (int k = 0; k < 16; ++k)
     if ((1 << k) == h->shape.work_w) a.work_shift = k;
+  // 16-byte plane loads of V = 16 / sizeof(element) pixels need aligned
+  // blocks (P % V == 0 follows from tile_w % V == 0) and rows of whole vectors
+  const int V = h->cfg.frag_dtype == DFB_F16 ? 8 : 4;
+  a.vec_ok = (reinterpret_cast<uintptr_t>(h->frag) % 16 == 0) && h->cfg.tile_w % V == 0 &&
+             h->shape.work_w % V == 0;
   for (int c = 0; c < 4; ++c) a.bg[c] = h->cfg.background[c];
   a.bg_image = h->bg_image;
   a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
@@ -422,6 +429,7 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0
   if (st != DFB_OK) return st;
   if (lds > 64 * 1024) DFB_HIP(h, hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
   h->graph_args = make_args(h, mode);
+  h->graph_args.n_queues = std::min(dfb::kQueues, grid);
   h->var_args = make_var_args(h);
   h->tab_off = h->d_off;
   h->tab_layer = h->d_block;
@@ -476,7 +484,7 @@ dfb_status launch_frame(dfb_ctx* h, uint32_t mode, bool use_graph, hipEvent_t t0
   }
   DFB_HIP(h, hipGetLastError());
   h->grid = grid;
-  h->q_base += static_cast<unsigned long long>(h->n_work) + static_cast<unsigned long long>(grid);
+  h->frame_seq += 1;
   return DFB_OK;
 }
 
@@ -672,9 +680,11 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
     if ((s = alloc_plain(h, &h->final_out, px * 16)) != DFB_OK) return bail(s);
   }
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->tile_var), h->n_tiles * sizeof(float))) != DFB_OK) return bail(s);
-  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_queue), 64)) != DFB_OK) return bail(s);
+  const size_t queue_bytes = sizeof(uint32_t) * dfb::kQueues * dfb::kQueueStride;
+  static_assert(dfb::kSlots <= dfb::kQueueStride, "a queue's slots fit in its stride");
+  if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_queue_ring), queue_bytes)) != DFB_OK) return bail(s);
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_flag), 64)) != DFB_OK) return bail(s);
-  e = hipMemsetAsync(h->d_queue, 0, 64, h->stream);
+  e = hipMemsetAsync(h->d_queue_ring, 0, queue_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->tile_var, 0, h->n_tiles * sizeof(float), h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) { hip_fail(h, e, "initialising device state"); return bail(DFB_ERR_HIP); }
@@ -696,7 +706,7 @@ dfb_status dfb_destroy(dfb_handle h) {
   if (h->idle0) (void)hipEventDestroy(h->idle0);
   if (h->idle1) (void)hipEventDestroy(h->idle1);
   void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->denoised, h->d_off,
-                  h->d_block, h->d_work, h->d_var_partial, h->d_queue, h->d_flag};
+                  h->d_block, h->d_work, h->d_var_partial, h->d_queue_ring, h->d_flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete h;
