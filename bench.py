@@ -78,6 +78,24 @@ def measured_traffic(workload, accumulate):
     return (fetch + write) * 1024.0
 
 
+def measured_op_traffic(op):
+    """HBM bytes per launch of the list / average operation from the committed
+    counter summary of the tile-op legs (current kernel source only)."""
+    path = os.path.join(ROOT, "profiles", "frame_kernel_tile_ops_2048_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash() or op + "_fetch_kib_per_dispatch" not in kv:
+        return None
+    fetch = float(kv[op + "_fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+    write = float(kv[op + "_write_kib_per_dispatch"]) * float(kv["write_scale"])
+    return (fetch + write) * 1024.0
+
+
 BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -215,7 +233,9 @@ def tile_ops_leg(dfb, torch, steps=30, warmup=5, copies=4):
                      "wall_ms_per_frame": wall, "fragments_per_s": f.n_fragments / (kms * 1e-3),
                      "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
                      "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                                  "frac": gbps / HBM_PEAK_GBPS, "algorithmic_bytes_per_launch": alg}}
+                                  "frac": gbps / HBM_PEAK_GBPS,
+                                  "traffic": measured_op_traffic(name) if name in ("list", "average") else None,
+                                  "algorithmic_bytes_per_launch": alg}}
     return out
 
 
