@@ -27,9 +27,12 @@ struct Shape {
   __host__ __device__ long long pixels() const { return static_cast<long long>(n) * h * w; }
 };
 
-// y = bf16(relu(conv3x3(x) + b)); x channels must be a multiple of 8.
+// y = bf16(relu(conv3x3(x') + b)) at the output shape s, where x' = x, or
+// with `up` the nearest-neighbour 2x up-sampling of x (x at s/2).  x channels
+// must be a multiple of 8; s.h and s.w even with `up` or `pool`.  With `pool`,
+// also pool = bf16(2x2 average of y) at s/2.
 hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y,
-                       const Shape& s, hipStream_t st);
+                       const Shape& s, hipStream_t st, bool up = false, const Map* pool = nullptr);
 // dx = conv3x3^T(bf16(dy * (y > 0))) (overwrites dx).
 hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, const MapF& dx,
                          const Shape& s, hipStream_t st);

@@ -5,7 +5,7 @@
 // deterministic.
 //
 // The three convolutions are one GEMM shape, D[M][N] += A[M][K] B[K][N],
-// staged through LDS in 32-wide K slices:
+// read from LDS in 32-wide K slices:
 //   forward  M = pixels, N = c_out, K = (tap, c_in)   A = x[p + tap], B = W
 //   dgrad    M = pixels, N = c_in,  K = (tap, c_out)  A = dy[p - tap], B = W^T
 //   wgrad    M = c_in,   N = c_out, K = pixels (per tap, split over chunks)
@@ -63,55 +63,180 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
   return (static_cast<long long>(q.n) * s.h + rr) * s.w + cc;
 }
 
-// ------------------------------------------------------------- forward
-template <int BN>
-__global__ void __launch_bounds__(256) conv_fwd_k(Map x, const uint16_t* __restrict__ w,
-                                                  const float* __restrict__ bias, Map y, Shape s) {
-  __shared__ __align__(16) uint16_t As[BM * LDK];
-  __shared__ __align__(16) uint16_t Bs[BN * LDK];
+// ------------------------------------------------------------- forward, spatial tiles
+// One workgroup computes a TH x 32 tile of output pixels for all BN output
+// channels.  The (TH+2) x 34 input halo (every input channel, zero outside
+// the image; read through the nearest-neighbour up-sampling when UP) is
+// staged in LDS once, so the nine taps re-read it from LDS instead of from
+// memory; the weights are staged one tap at a time, double-buffered, the
+// next tap's loads in flight during this tap's MFMAs.  Wave w owns tile rows
+// w*TH/4 .. +TH/4-1 (TH/2 row blocks of 16 pixels) and every 16-column block
+// of BN.  K runs tap-major, then 32-channel slices.  Epilogue: bias, ReLU, bf16 into LDS, 16-byte
+// coalesced stores, and optionally the 2x2 average pool of the tile (the
+// tile origin and TH are even).
+constexpr int kTW = 32;
+
+template <int BN, int CP, int TH>
+struct TileCfg {
+  static constexpr int HW = kTW + 2, HH = TH + 2;
+  static constexpr int LDR = CP + 8;     // one halo pixel, bf16
+  static constexpr int LDB = CP + 8;     // one output channel's weights of a tap
+  static constexpr int LDO = BN + 8;     // one output pixel in the staging tile
+  static constexpr int HALO = HH * HW * LDR;
+  static constexpr int BTAP = BN * LDB;
+  static constexpr int OUT = TH * kTW * LDO;
+  static constexpr int ELEMS = (HALO + 2 * BTAP) > OUT ? (HALO + 2 * BTAP) : OUT;
+  static constexpr size_t BYTES = static_cast<size_t>(ELEMS) * 2;
+};
+
+template <int BN, int CP, int TH, bool UP>
+__global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __restrict__ w,
+                                                       const float* __restrict__ bias, Map y, Map pool, Shape s) {
+  using C = TileCfg<BN, CP, TH>;
+  constexpr int WR = TH / 4, MB = 2 * WR, NB = BN / 16, CH8 = CP / 8;
+  constexpr int BCH = BN * CH8, BPT = (BCH + 255) / 256;
+  extern __shared__ __align__(16) uint16_t smem[];
+  uint16_t* halo = smem;
+  uint16_t* bbuf = smem + C::HALO;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const long long m0 = static_cast<long long>(blockIdx.x) * BM;
-  const int ap = tid >> 2, ach = (tid & 3) * 8;
-  const Pix q = pixel_of(m0 + ap, s);
-  f32x4 acc[BN / 16];
+  const int tiles_x = (s.w + kTW - 1) / kTW, tiles_y = (s.h + TH - 1) / TH;
+  int blk = static_cast<int>(blockIdx.x);
+  const int n = blk / (tiles_x * tiles_y);
+  blk -= n * tiles_x * tiles_y;
+  const int oy0 = (blk / tiles_x) * TH, ox0 = (blk % tiles_x) * kTW;
+  const int hi = UP ? s.h / 2 : s.h, wi = UP ? s.w / 2 : s.w;  // the map x is read from
+  // every halo load is issued before the first LDS store, so their
+  // latencies overlap instead of adding up
+  constexpr int HTOT = C::HH * C::HW * CH8, HIT = (HTOT + 255) / 256;
+  uint4 hreg[HIT];
 #pragma unroll
-  for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nk = (x.c + 31) / 32;
-  for (int tap = 0; tap < 9; ++tap) {
-    bool in;
-    const long long src = shifted(q, tap / 3 - 1, tap % 3 - 1, s, in);
-    for (int kc = 0; kc < nk; ++kc) {
-      const int c0 = kc * 32 + ach;
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (in && c0 < x.c) v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + c0);
-      *reinterpret_cast<uint4*>(As + ap * LDK + ach) = v;
-      for (int e = tid; e < BN * 4; e += 256) {
-        const int co = e >> 2, ci0 = kc * 32 + (e & 3) * 8;
-        uint4 wv = {0u, 0u, 0u, 0u};
-        if (ci0 < x.c) wv = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + co) * x.c + ci0);
-        *reinterpret_cast<uint4*>(Bs + co * LDK + (e & 3) * 8) = wv;
-      }
-      __syncthreads();
-      const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+  for (int i = 0; i < HIT; ++i) {
+    const int e = tid + i * 256;
+    const int hp = e / CH8, cc = e - hp * CH8;
+    const int r = oy0 - 1 + hp / C::HW, c = ox0 - 1 + hp % C::HW;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (e < HTOT && r >= 0 && r < s.h && c >= 0 && c < s.w && cc * 8 < x.c) {
+      const long long src = UP ? (static_cast<long long>(n) * hi + (r >> 1)) * wi + (c >> 1)
+                               : (static_cast<long long>(n) * hi + r) * wi + c;
+      v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + cc * 8);
+    }
+    hreg[i] = v;
+  }
 #pragma unroll
-      for (int j = 0; j < BN / 16; ++j) {
-        const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-      }
-      __syncthreads();
+  for (int i = 0; i < HIT; ++i) {
+    const int e = tid + i * 256;
+    if (e < HTOT) {
+      const int hp = e / CH8, cc = e - hp * CH8;
+      *reinterpret_cast<uint4*>(halo + hp * C::LDR + cc * 8) = hreg[i];
     }
   }
-  const long long P = s.pixels();
+  uint4 breg[BPT];
+  auto load_b = [&](int tap) {
 #pragma unroll
-  for (int j = 0; j < BN / 16; ++j) {
-    const int col = j * 16 + (lane & 15);
-    const float bb = bias[col];
+    for (int i = 0; i < BPT; ++i) {
+      const int e = tid + i * 256;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (e < BCH) {
+        const int co = e / CH8, cc = e - co * CH8;
+        if (cc * 8 < x.c) v = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + co) * x.c + cc * 8);
+      }
+      breg[i] = v;
+    }
+  };
+  auto store_b = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long p = m0 + wave * 16 + (lane >> 4) * 4 + r;
-      if (p < P) {
-        const float v = acc[j][r] + bb;
-        y.p[p * y.ld + y.off + col] = to_bf16(v > 0.f ? v : 0.f);
+    for (int i = 0; i < BPT; ++i) {
+      const int e = tid + i * 256;
+      if (e < BCH) {
+        const int co = e / CH8, cc = e - co * CH8;
+        *reinterpret_cast<uint4*>(bbuf + buf * C::BTAP + co * C::LDB + cc * 8) = breg[i];
+      }
+    }
+  };
+  load_b(0);
+  store_b(0);
+  f32x4 acc[MB][NB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+  for (int tap = 0; tap < 9; ++tap) {
+    if (tap + 1 < 9) load_b(tap + 1);
+    const int dr = tap / 3, dc = tap - (tap / 3) * 3;
+    const uint16_t* B = bbuf + (tap & 1) * C::BTAP;
+#pragma unroll
+    for (int ks = 0; ks < CP / 32; ++ks) {
+      bf16x8 bf[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bf[j] = lds_frag(B + (j * 16 + (lane & 15)) * C::LDB + ks * 32 + (lane >> 4) * 8);
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
+        const bf16x8 a = lds_frag(halo + ((row + dr) * C::HW + col + dc) * C::LDR + ks * 32 + (lane >> 4) * 8);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[j], acc[m][j], 0, 0, 0);
+      }
+    }
+    if (tap + 1 < 9) store_b((tap + 1) & 1);
+    __syncthreads();
+  }
+  // epilogue: bias + ReLU + bf16 into the staging tile (the halo is no longer read)
+  uint16_t* ot = smem;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int ch = j * 16 + (lane & 15);
+    const float bb = bias[ch];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int row = wave * WR + m / 2;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = (m & 1) * 16 + (lane >> 4) * 4 + r;
+        const float v = acc[m][j][r] + bb;
+        ot[(row * kTW + col) * C::LDO + ch] = to_bf16(v > 0.f ? v : 0.f);
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int OCH = BN / 8;
+  for (int e = tid; e < TH * kTW * OCH; e += 256) {
+    const int pi = e / OCH, cc = e - pi * OCH;
+    const int r = oy0 + pi / kTW, c = ox0 + pi % kTW;
+    if (r < s.h && c < s.w) {
+      const long long p = (static_cast<long long>(n) * s.h + r) * s.w + c;
+      *reinterpret_cast<uint4*>(y.p + p * y.ld + y.off + cc * 8) = *reinterpret_cast<const uint4*>(ot + pi * C::LDO + cc * 8);
+    }
+  }
+  if (pool.p) {
+    const int ph = s.h / 2, pw = s.w / 2;
+    for (int e = tid; e < (TH / 2) * (kTW / 2) * OCH; e += 256) {
+      const int qi = e / OCH, cc = e - qi * OCH;
+      const int qr = qi / (kTW / 2), qc = qi - qr * (kTW / 2);
+      const int r = oy0 / 2 + qr, c = ox0 / 2 + qc;
+      if (r < ph && c < pw) {
+        const uint16_t* t00 = ot + ((2 * qr) * kTW + 2 * qc) * C::LDO + cc * 8;
+        const uint4 a = *reinterpret_cast<const uint4*>(t00);
+        const uint4 b = *reinterpret_cast<const uint4*>(t00 + C::LDO);
+        const uint4 c2 = *reinterpret_cast<const uint4*>(t00 + kTW * C::LDO);
+        const uint4 d = *reinterpret_cast<const uint4*>(t00 + (kTW + 1) * C::LDO);
+        const uint32_t A[4] = {a.x, a.y, a.z, a.w}, Bw[4] = {b.x, b.y, b.z, b.w}, Cw[4] = {c2.x, c2.y, c2.z, c2.w},
+                       D[4] = {d.x, d.y, d.z, d.w};
+        uint32_t o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          uint32_t packed = 0;
+#pragma unroll
+          for (int hlf = 0; hlf < 2; ++hlf) {
+            const int sh = hlf * 16;
+            const float v = from_bf16(static_cast<uint16_t>(A[k] >> sh)) + from_bf16(static_cast<uint16_t>(Bw[k] >> sh)) +
+                            from_bf16(static_cast<uint16_t>(Cw[k] >> sh)) + from_bf16(static_cast<uint16_t>(D[k] >> sh));
+            packed |= static_cast<uint32_t>(to_bf16(0.25f * v)) << sh;
+          }
+          o[k] = packed;
+        }
+        const long long p = (static_cast<long long>(n) * ph + r) * pw + c;
+        *reinterpret_cast<uint4*>(pool.p + p * pool.ld + pool.off + cc * 8) = uint4{o[0], o[1], o[2], o[3]};
       }
     }
   }
@@ -266,28 +391,50 @@ __global__ void __launch_bounds__(256) wgrad_reduce_k(const float* __restrict__ 
   dw[e] = sum;
 }
 
-// db[co] partials per chunk: sum over the chunk's pixels in order.
-__global__ void __launch_bounds__(128) bias_partial_k(MapF dy, Map y, float* __restrict__ partial, Shape s) {
-  const int co = threadIdx.x, chunk = blockIdx.x;
-  if (co >= dy.c) return;
+// db[co] partials per chunk of kBiasChunk pixels: thread (co, g) sums the
+// chunk's pixels g, g + G, ... in order (G = 256 / c_out groups, lanes of a
+// wave on consecutive channels of one pixel), then the groups are added in
+// group order: deterministic.
+constexpr int kBiasChunk = 256;
+__global__ void __launch_bounds__(256) bias_partial_k(MapF dy, Map y, float* __restrict__ partial, Shape s) {
+  __shared__ float red[256];
+  const int C = dy.c, G = 256 / C;
+  const int t = threadIdx.x, co = t % C, g = t / C;
   const long long P = s.pixels();
-  const long long p0 = static_cast<long long>(chunk) * kWgradChunk;
-  const long long p1 = p0 + kWgradChunk < P ? p0 + kWgradChunk : P;
+  const long long p0 = static_cast<long long>(blockIdx.x) * kBiasChunk;
+  const long long p1 = p0 + kBiasChunk < P ? p0 + kBiasChunk : P;
   float sum = 0.f;
-  for (long long p = p0; p < p1; ++p) {
-    const uint16_t yh = y.p[p * y.ld + y.off + co];
-    sum += from_bf16(yh) > 0.f ? dy.p[p * dy.ld + dy.off + co] : 0.f;
+  if (g < G) {
+    for (long long p = p0 + g; p < p1; p += G) {
+      const uint16_t yh = y.p[p * y.ld + y.off + co];
+      sum += from_bf16(yh) > 0.f ? dy.p[p * dy.ld + dy.off + co] : 0.f;
+    }
   }
-  partial[static_cast<size_t>(chunk) * dy.c + co] = sum;
+  red[t] = sum;
+  __syncthreads();
+  if (t < C) {
+    float v = 0.f;
+    for (int k = 0; k < G; ++k) v += red[k * C + t];
+    partial[static_cast<size_t>(blockIdx.x) * C + t] = v;
+  }
 }
 
-__global__ void __launch_bounds__(128) chunk_reduce_k(const float* __restrict__ partial, float* __restrict__ out,
+// out[i] = sum over chunks of partial[chunk][i]: one workgroup per output;
+// thread t sums chunks t, t + 256, ... in order, then a fixed-shape tree
+// over the threads (deterministic).
+__global__ void __launch_bounds__(256) chunk_reduce_k(const float* __restrict__ partial, float* __restrict__ out,
                                                       int chunks, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  __shared__ float red[256];
+  const int i = blockIdx.x, t = threadIdx.x;
   float sum = 0.f;
-  for (int c = 0; c < chunks; ++c) sum += partial[static_cast<size_t>(c) * n + i];
-  out[i] = sum;
+  for (int c = t; c < chunks; c += 256) sum += partial[static_cast<size_t>(c) * n + i];
+  red[t] = sum;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[i] = red[0];
 }
 
 // ------------------------------------------------------------- glue kernels
@@ -359,59 +506,76 @@ __global__ void out_fwd_k(Map x, const float* __restrict__ w, const float* __res
   if (p >= s.pixels()) return;
   float o0 = base[p * base_ld] + b[0], o1 = base[p * base_ld + 1] + b[1], o2 = base[p * base_ld + 2] + b[2];
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  for (int i = 0; i < x.c; ++i) {
-    const float xi = from_bf16(x.p[p * x.ld + x.off + i]);
-    a0 = fmaf(xi, w[i * 3 + 0], a0);
-    a1 = fmaf(xi, w[i * 3 + 1], a1);
-    a2 = fmaf(xi, w[i * 3 + 2], a2);
+  const uint16_t* row = x.p + p * x.ld + x.off;
+  for (int i0 = 0; i0 < x.c; i0 += 8) {  // x.c, ld and off are multiples of 8
+    const uint4 v = *reinterpret_cast<const uint4*>(row + i0);
+    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k;
+      const float xi = from_bf16(static_cast<uint16_t>(vw[k >> 1] >> ((k & 1) * 16)));
+      a0 = fmaf(xi, w[i * 3 + 0], a0);
+      a1 = fmaf(xi, w[i * 3 + 1], a1);
+      a2 = fmaf(xi, w[i * 3 + 2], a2);
+    }
   }
   out[p * 3 + 0] = o0 + a0;
   out[p * 3 + 1] = o1 + a1;
   out[p * 3 + 2] = o2 + a2;
 }
 
-// Per pixel: dout = 2 (out - t) / count; dx = dout w^T.  Per chunk of pixels
-// (in order): partial[chunk] = {dw[ci][3], db[3], sum (out - t)^2}.
-constexpr int kOutChunk = 1024;
-__global__ void __launch_bounds__(64) out_bwd_k(Map x, const float* __restrict__ out, const float* __restrict__ tgt,
-                                                const float* __restrict__ w, MapF dx, float* __restrict__ partial,
-                                                Shape s, float scale) {
-  // one workgroup (one wave) per chunk; lane i < ci accumulates dw[i][*]
-  const int chunk = blockIdx.x, lane = threadIdx.x;
+// Per pixel: dout = 2 (out - t) / count; dx = dout w^T.  Per chunk of
+// kOutChunk pixels: partial[chunk] = {dw[ci][3], db[3], sum (out - t)^2}.
+// Thread (g, i) of G = 256 / ci groups handles channel i of the chunk's
+// pixels g, g + G, ... in order; the groups are added in group order.
+constexpr int kOutChunk = 256;
+__global__ void __launch_bounds__(256) out_bwd_k(Map x, const float* __restrict__ out, const float* __restrict__ tgt,
+                                                 const float* __restrict__ w, MapF dx, float* __restrict__ partial,
+                                                 Shape s, float scale) {
+  __shared__ float red[7][256];
+  const int chunk = blockIdx.x, t = threadIdx.x;
+  const int ci = x.c, G = 256 / ci, i = t % ci, g = t / ci;
   const long long P = s.pixels();
   const long long p0 = static_cast<long long>(chunk) * kOutChunk;
   const long long p1 = p0 + kOutChunk < P ? p0 + kOutChunk : P;
-  const int ci = x.c;
   float dw0 = 0.f, dw1 = 0.f, dw2 = 0.f, db0 = 0.f, db1 = 0.f, db2 = 0.f, ls = 0.f;
-  for (long long p = p0; p < p1; ++p) {
-    const float e0 = out[p * 3] - tgt[p * 3], e1 = out[p * 3 + 1] - tgt[p * 3 + 1], e2 = out[p * 3 + 2] - tgt[p * 3 + 2];
-    const float g0 = scale * e0, g1 = scale * e1, g2 = scale * e2;
-    if (lane < ci) {
-      const float xi = from_bf16(x.p[p * x.ld + x.off + lane]);
+  if (g < G) {
+    const float w0 = w[i * 3], w1 = w[i * 3 + 1], w2 = w[i * 3 + 2];
+    for (long long p = p0 + g; p < p1; p += G) {
+      const float e0 = out[p * 3] - tgt[p * 3], e1 = out[p * 3 + 1] - tgt[p * 3 + 1], e2 = out[p * 3 + 2] - tgt[p * 3 + 2];
+      const float g0 = scale * e0, g1 = scale * e1, g2 = scale * e2;
+      const float xi = from_bf16(x.p[p * x.ld + x.off + i]);
       dw0 = fmaf(xi, g0, dw0);
       dw1 = fmaf(xi, g1, dw1);
       dw2 = fmaf(xi, g2, dw2);
-      dx.p[p * dx.ld + dx.off + lane] = g0 * w[lane * 3] + g1 * w[lane * 3 + 1] + g2 * w[lane * 3 + 2];
+      dx.p[p * dx.ld + dx.off + i] = g0 * w0 + g1 * w1 + g2 * w2;
+      db0 += g0;
+      db1 += g1;
+      db2 += g2;
+      ls = fmaf(e0, e0, ls);
+      ls = fmaf(e1, e1, ls);
+      ls = fmaf(e2, e2, ls);
     }
-    db0 += g0;
-    db1 += g1;
-    db2 += g2;
-    ls = fmaf(e0, e0, ls);
-    ls = fmaf(e1, e1, ls);
-    ls = fmaf(e2, e2, ls);
   }
+  const float v[7] = {dw0, dw1, dw2, db0, db1, db2, ls};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) red[k][t] = v[k];
+  __syncthreads();
   const int n = ci * 3 + 4;
   float* q = partial + static_cast<size_t>(chunk) * n;
-  if (lane < ci) {
-    q[lane * 3] = dw0;
-    q[lane * 3 + 1] = dw1;
-    q[lane * 3 + 2] = dw2;
-  }
-  if (lane == 0) {
-    q[ci * 3] = db0;
-    q[ci * 3 + 1] = db1;
-    q[ci * 3 + 2] = db2;
-    q[ci * 3 + 3] = ls;
+  if (t < ci) {  // dw[t][*]: this channel's groups in order
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float a = 0.f;
+      for (int gg = 0; gg < G; ++gg) a += red[k][gg * ci + t];
+      q[t * 3 + k] = a;
+    }
+  } else if (t < ci + 4) {  // db and the loss: every (group, channel) thread, in thread order
+    const int k = 3 + (t - ci);
+    float a = 0.f;
+    for (int u = 0; u < G * ci; u += ci)  // one value per group: the threads of channel 0
+      a += red[k][u];
+    q[ci * 3 + (t - ci)] = a;
   }
 }
 
@@ -505,17 +669,42 @@ inline unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t
 
 }  // namespace
 
-hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y, const Shape& s,
-                       hipStream_t st) {
-  const unsigned g = blocks(s.pixels(), BM);
-  if (x.c % 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
-  switch (y.c) {
-    case 32: conv_fwd_k<32><<<g, 256, 0, st>>>(x, w_fwd, bias, y, s); break;
-    case 64: conv_fwd_k<64><<<g, 256, 0, st>>>(x, w_fwd, bias, y, s); break;
-    case 128: conv_fwd_k<128><<<g, 256, 0, st>>>(x, w_fwd, bias, y, s); break;
-    default: return hipErrorInvalidValue;
+template <int BN, int CP, int TH, bool UP>
+hipError_t launch_tile(const Map& x, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
+                       const Shape& s, hipStream_t st) {
+  using C = TileCfg<BN, CP, TH>;
+  const void* f = reinterpret_cast<const void*>(&conv_fwd_tile_k<BN, CP, TH, UP>);
+  if (C::BYTES > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(C::BYTES));
+    if (e != hipSuccess) return e;
   }
+  const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
+  conv_fwd_tile_k<BN, CP, TH, UP><<<static_cast<unsigned>(tiles), 256, C::BYTES, st>>>(x, w, bias, y, pool, s);
   return hipGetLastError();
+}
+
+template <bool UP>
+hipError_t conv_tile(const Map& x, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
+                     const Shape& s, hipStream_t st) {
+  const int cp = (x.c + 31) / 32 * 32;
+  if (y.c == 32 && cp == 32) return launch_tile<32, 32, 8, UP>(x, w, bias, y, pool, s, st);
+  if (y.c == 32 && cp == 64) return launch_tile<32, 64, 8, UP>(x, w, bias, y, pool, s, st);
+  if (y.c == 64 && cp == 32) return launch_tile<64, 32, 8, UP>(x, w, bias, y, pool, s, st);
+  if (y.c == 64 && cp == 64) return launch_tile<64, 64, 8, UP>(x, w, bias, y, pool, s, st);
+  if (y.c == 64 && cp == 128) return launch_tile<64, 128, 4, UP>(x, w, bias, y, pool, s, st);
+  if (y.c == 128 && cp == 64) return launch_tile<128, 64, 4, UP>(x, w, bias, y, pool, s, st);
+  if (y.c == 128 && cp == 128) return launch_tile<128, 128, 4, UP>(x, w, bias, y, pool, s, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y, const Shape& s,
+                       hipStream_t st, bool up, const Map* pool) {
+  if (x.c % 8 || x.ld % 8 || x.off % 8 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
+  if ((up || pool) && (s.h % 2 || s.w % 2)) return hipErrorInvalidValue;
+  const Map none{nullptr, 0, 0, 0};
+  const Map& pl = pool ? *pool : none;
+  if (pool && (pl.ld % 8 || pl.off % 8 || pl.c != y.c)) return hipErrorInvalidValue;
+  return up ? conv_tile<true>(x, w_fwd, bias, y, pl, s, st) : conv_tile<false>(x, w_fwd, bias, y, pl, s, st);
 }
 
 hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, const MapF& dx, const Shape& s,
@@ -533,7 +722,9 @@ hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, 
 
 size_t conv3x3_wgrad_scratch(int ci, int co, const Shape& s) {
   const long long chunks = (s.pixels() + kWgradChunk - 1) / kWgradChunk;
-  return static_cast<size_t>(chunks) * 9 * ci * co;
+  const long long bchunks = (s.pixels() + kBiasChunk - 1) / kBiasChunk;
+  const size_t wsum = static_cast<size_t>(chunks) * 9 * ci * co, bsum = static_cast<size_t>(bchunks) * co;
+  return wsum > bsum ? wsum : bsum;
 }
 
 hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, float* db, float* partial,
@@ -553,8 +744,9 @@ hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, 
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // bias partials reuse the front of the scratch (the weight sums are done)
-  bias_partial_k<<<chunks, 128, 0, st>>>(dy, y, partial, s);
-  chunk_reduce_k<<<1, 128, 0, st>>>(partial, db, chunks, dy.c);
+  const int bchunks = static_cast<int>((s.pixels() + kBiasChunk - 1) / kBiasChunk);
+  bias_partial_k<<<bchunks, 256, 0, st>>>(dy, y, partial, s);
+  chunk_reduce_k<<<dy.c, 256, 0, st>>>(partial, db, bchunks, dy.c);
   return hipGetLastError();
 }
 
@@ -596,12 +788,12 @@ hipError_t out_conv_backward(const Map& x, const float* out, const float* target
   if (x.c > 64) return hipErrorInvalidValue;
   const int chunks = static_cast<int>((s.pixels() + kOutChunk - 1) / kOutChunk);
   const float scale = 2.f / static_cast<float>(s.pixels() * 3);
-  out_bwd_k<<<chunks, 64, 0, st>>>(x, out, target, w, dx, partial, s, scale);
+  out_bwd_k<<<chunks, 256, 0, st>>>(x, out, target, w, dx, partial, s, scale);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = x.c * 3 + 4;
   // dw (ci*3), db (3) and the loss sum are consecutive in each partial row
-  chunk_reduce_k<<<blocks(n, 128), 128, 0, st>>>(partial, partial + static_cast<size_t>(chunks) * n, chunks, n);
+  chunk_reduce_k<<<n, 256, 0, st>>>(partial, partial + static_cast<size_t>(chunks) * n, chunks, n);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const float* red = partial + static_cast<size_t>(chunks) * n;

@@ -134,29 +134,31 @@ dfb_status refresh(dfb_denoiser_ctx* n) {
   return DFB_OK;
 }
 
-// forward on in (f32 NHWC 6 ch) -> n->out
-dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0) {
+// forward on in (f32 NHWC 6 ch) -> n->out.  The 2x2 pools come out of the
+// enc1b / enc2b epilogues and the up-sampling is read through by up2 / up1;
+// `training` also materialises the up-sampled maps the backward pass reads.
+dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training) {
   const Shape s1{s0.n, s0.h / 2, s0.w / 2}, s2{s0.n, s0.h / 4, s0.w / 4};
   hipStream_t st = n->stream;
   const float* W = n->w;
   auto B = [&](int i) { return W + n->off_b[i]; };
+  using dfb::unet::conv3x3_fwd;
+  const Map pool1 = mp(n->pool1, 32, 0, 32), pool2 = mp(n->pool2, 64, 0, 64);
   NHIP(n, dfb::unet::pack_input(in, 6, n->xin, s0, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->xin, 8, 0, 8), n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->e1a, 32, 0, 32), n->wf[ENC1B], B(ENC1B), mp(n->cat1, 64, 32, 32), s0, st));
-  NHIP(n, dfb::unet::avgpool2(mp(n->cat1, 64, 32, 32), mp(n->pool1, 32, 0, 32), s0, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->pool1, 32, 0, 32), n->wf[ENC2A], B(ENC2A), mp(n->e2a, 64, 0, 64), s1, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->e2a, 64, 0, 64), n->wf[ENC2B], B(ENC2B), mp(n->cat2, 128, 64, 64), s1, st));
-  NHIP(n, dfb::unet::avgpool2(mp(n->cat2, 128, 64, 64), mp(n->pool2, 64, 0, 64), s1, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->pool2, 64, 0, 64), n->wf[ENC3A], B(ENC3A), mp(n->e3a, 128, 0, 128), s2, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->e3a, 128, 0, 128), n->wf[ENC3B], B(ENC3B), mp(n->e3b, 128, 0, 128), s2, st));
-  NHIP(n, dfb::unet::upsample2(mp(n->e3b, 128, 0, 128), mp(n->up3, 128, 0, 128), s2, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->up3, 128, 0, 128), n->wf[UP2], B(UP2), mp(n->cat2, 128, 0, 64), s1, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->cat2, 128, 0, 128), n->wf[DEC2A], B(DEC2A), mp(n->d2a, 64, 0, 64), s1, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->d2a, 64, 0, 64), n->wf[DEC2B], B(DEC2B), mp(n->d2b, 64, 0, 64), s1, st));
-  NHIP(n, dfb::unet::upsample2(mp(n->d2b, 64, 0, 64), mp(n->upd2, 64, 0, 64), s1, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->upd2, 64, 0, 64), n->wf[UP1], B(UP1), mp(n->cat1, 64, 0, 32), s0, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
-  NHIP(n, dfb::unet::conv3x3_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), mp(n->d1b, 32, 0, 32), s0, st));
+  NHIP(n, conv3x3_fwd(mp(n->xin, 8, 0, 8), n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
+  NHIP(n, conv3x3_fwd(mp(n->e1a, 32, 0, 32), n->wf[ENC1B], B(ENC1B), mp(n->cat1, 64, 32, 32), s0, st, false, &pool1));
+  NHIP(n, conv3x3_fwd(pool1, n->wf[ENC2A], B(ENC2A), mp(n->e2a, 64, 0, 64), s1, st));
+  NHIP(n, conv3x3_fwd(mp(n->e2a, 64, 0, 64), n->wf[ENC2B], B(ENC2B), mp(n->cat2, 128, 64, 64), s1, st, false, &pool2));
+  NHIP(n, conv3x3_fwd(pool2, n->wf[ENC3A], B(ENC3A), mp(n->e3a, 128, 0, 128), s2, st));
+  NHIP(n, conv3x3_fwd(mp(n->e3a, 128, 0, 128), n->wf[ENC3B], B(ENC3B), mp(n->e3b, 128, 0, 128), s2, st));
+  if (training) NHIP(n, dfb::unet::upsample2(mp(n->e3b, 128, 0, 128), mp(n->up3, 128, 0, 128), s2, st));
+  NHIP(n, conv3x3_fwd(mp(n->e3b, 128, 0, 128), n->wf[UP2], B(UP2), mp(n->cat2, 128, 0, 64), s1, st, true));
+  NHIP(n, conv3x3_fwd(mp(n->cat2, 128, 0, 128), n->wf[DEC2A], B(DEC2A), mp(n->d2a, 64, 0, 64), s1, st));
+  NHIP(n, conv3x3_fwd(mp(n->d2a, 64, 0, 64), n->wf[DEC2B], B(DEC2B), mp(n->d2b, 64, 0, 64), s1, st));
+  if (training) NHIP(n, dfb::unet::upsample2(mp(n->d2b, 64, 0, 64), mp(n->upd2, 64, 0, 64), s1, st));
+  NHIP(n, conv3x3_fwd(mp(n->d2b, 64, 0, 64), n->wf[UP1], B(UP1), mp(n->cat1, 64, 0, 32), s0, st, true));
+  NHIP(n, conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
+  NHIP(n, conv3x3_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), mp(n->d1b, 32, 0, 32), s0, st));
   NHIP(n, dfb::unet::out_conv_fwd(mp(n->d1b, 32, 0, 32), W + n->off_ow, W + n->off_ob, in, 6, n->out, s0, st));
   n->last = s0;
   return DFB_OK;
@@ -341,7 +343,7 @@ dfb_status dfb_denoiser_forward(dfb_denoiser n, const float* in, float* out, int
   if (!in || !out) return nfail(n, DFB_ERR_INVALID_ARG, "null tensor");
   if ((s = check_shape(n, b, h, w)) != DFB_OK) return s;
   const Shape s0{b, h, w};
-  if ((s = forward(n, in, s0)) != DFB_OK) return s;
+  if ((s = forward(n, in, s0, false)) != DFB_OK) return s;
   NHIP(n, hipMemcpyAsync(out, n->out, static_cast<size_t>(s0.pixels()) * 3 * sizeof(float), hipMemcpyDeviceToDevice,
                          n->stream));
   return DFB_OK;
@@ -354,7 +356,7 @@ dfb_status dfb_denoiser_train_step(dfb_denoiser n, const float* in, const float*
   if (!in || !target) return nfail(n, DFB_ERR_INVALID_ARG, "null tensor");
   if ((s = check_shape(n, b, h, w)) != DFB_OK) return s;
   const Shape s0{b, h, w};
-  if ((s = forward(n, in, s0)) != DFB_OK) return s;
+  if ((s = forward(n, in, s0, true)) != DFB_OK) return s;
   if ((s = backward(n, target, s0)) != DFB_OK) return s;
   if (apply_update) {
     n->step += 1;
@@ -427,7 +429,7 @@ dfb_status dfb_denoise(dfb_handle h, dfb_denoiser n, float var_threshold) {
     NHIP(n, hipEventDestroy(e));
   }
   NHIP(n, dfb::unet::frame_to_input(fv.glue, n->frame_in, n->stream));
-  if ((s = forward(n, n->frame_in, Shape{1, H, W})) != DFB_OK) return s;
+  if ((s = forward(n, n->frame_in, Shape{1, H, W}, false)) != DFB_OK) return s;
   NHIP(n, dfb::unet::frame_from_output(fv.glue, n->out, var_threshold, fv.denoised, fv.final_out, fv.display_mode,
                                        fv.inv_gamma, n->stream));
   if (n->stream != fv.stream) {
