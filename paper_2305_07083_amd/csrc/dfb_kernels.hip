@@ -43,6 +43,12 @@ namespace {
 #ifndef DFB_WAVES_K32
 #define DFB_WAVES_K32 0
 #endif
+// Largest register-sort bucket that loads all five planes up front (larger
+// buckets load depth and alpha first and the colours after the walk);
+// 0 = chosen per kernel capacity (upfront_max).
+#ifndef DFB_UPFRONT_MAX
+#define DFB_UPFRONT_MAX 0
+#endif
 // Layers whose plane loads the list and averaging operations keep in flight
 // per lane.
 #ifndef DFB_OP_CHUNK
@@ -88,6 +94,44 @@ __device__ __forceinline__ uint32_t depth_bits(float d) {
   if (b == 0x80000000u) b = 0u;
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
+
+// Order-preserving map of a binary16 depth to 16 bits, same rules.
+__device__ __forceinline__ uint32_t half_depth_bits(uint16_t h) {
+  if ((h & 0x7C00u) == 0x7C00u && (h & 0x03FFu)) return 0xFFFFu;
+  if (h == 0x8000u) h = 0;
+  return (h & 0x8000u) ? (~static_cast<uint32_t>(h) & 0xFFFFu) : (static_cast<uint32_t>(h) | 0x8000u);
+}
+
+// Sort keys of the register path: (ordered depth bits, layer index), as one
+// integer so that one compare orders by depth and breaks ties by index (the
+// layers of a tile are in source-id order).  fp32 depths need 64-bit keys;
+// fp16 depths and an index below 65536 fit 32 bits, which halves the
+// registers and the compare work of the sorting network.
+template <typename FT>
+struct SortKey;
+template <>
+struct SortKey<float> {
+  using K = uint64_t;
+  static constexpr K kPad = ~0ull;
+  __device__ static __forceinline__ K make(const float* __restrict__ b, uint32_t i, int l) {
+    return (static_cast<uint64_t>(depth_bits(ldf<float>(b, i))) << 32) | static_cast<uint32_t>(l);
+  }
+  __device__ static __forceinline__ int index(K k) { return static_cast<int>(static_cast<uint32_t>(k)); }
+};
+template <>
+struct SortKey<_Float16> {
+  using K = uint32_t;
+  static constexpr K kPad = ~0u;
+  __device__ static __forceinline__ K make(const _Float16* __restrict__ b, uint32_t i, int l) {
+#if DFB_NT_LOADS
+    const _Float16 d = __builtin_nontemporal_load(b + i);
+#else
+    const _Float16 d = b[i];
+#endif
+    return (half_depth_bits(__builtin_bit_cast(uint16_t, d)) << 16) | static_cast<uint32_t>(l);
+  }
+  __device__ static __forceinline__ int index(K k) { return static_cast<int>(k & 0xFFFFu); }
+};
 
 __device__ __forceinline__ uint32_t quantise(float x, bool gamma, float inv_gamma) {
   float y = x > 0.f ? x : 0.f;  // NaN compares false -> 0
@@ -183,34 +227,31 @@ __device__ __forceinline__ float4 composite_px_upfront(float& Tout, const FrameA
   const uint32_t P = static_cast<uint32_t>(a.P);
   const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
   const uint32_t up = static_cast<uint32_t>(p);
-  float dep[KMAX], alp[KMAX], cr[KMAX], cg[KMAX], cb[KMAX];
+  using SK = SortKey<FT>;
+  typename SK::K key[KMAX];
+  float alp[KMAX], cr[KMAX], cg[KMAX], cb[KMAX];
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
     if (l < K) {
       const FT* __restrict__ b = frag + loff[l];
-      dep[l] = ldf<FT>(b, 4 * P + up);
+      key[l] = SK::make(b, 4 * P + up, l);
       alp[l] = ldf<FT>(b, 3 * P + up);
       cr[l] = ldf<FT>(b, up);
       cg[l] = ldf<FT>(b, P + up);
       cb[l] = ldf<FT>(b, 2 * P + up);
-    }
-  }
-  uint64_t key[KMAX];
-#pragma unroll
-  for (int l = 0; l < KMAX; ++l) {
-    if (l < K) {
-      key[l] = (static_cast<uint64_t>(depth_bits(dep[l])) << 32) | static_cast<uint32_t>(l);
-      wl[l * NT] = alp[l];
     } else {
-      key[l] = ~0ull;
+      key[l] = SK::kPad;
     }
   }
+#pragma unroll
+  for (int l = 0; l < KMAX; ++l)
+    if (l < K) wl[l * NT] = alp[l];
   sort_network<KMAX>(key);
   float T = 1.f, A = 0.f;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
     if (i < K) {
-      const int l = static_cast<int>(static_cast<uint32_t>(key[i]));
+      const int l = SK::index(key[i]);
       const float al = wl[l * NT];
       wl[l * NT] = T;
       A = fmaf(T, al, A);
@@ -244,17 +285,16 @@ __device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const Fram
   const uint32_t P = static_cast<uint32_t>(a.P);
   const FT* __restrict__ frag = static_cast<const FT*>(a.frag);
   const uint32_t up = static_cast<uint32_t>(p);
-  uint64_t key[KMAX];
+  using SK = SortKey<FT>;
+  typename SK::K key[KMAX];
 #pragma unroll
   for (int l = 0; l < KMAX; ++l) {
     if (l < K) {
       const FT* __restrict__ b = frag + loff[l];
-      const float d = ldf<FT>(b, 4 * P + up);
-      const float al = ldf<FT>(b, 3 * P + up);
-      key[l] = (static_cast<uint64_t>(depth_bits(d)) << 32) | static_cast<uint32_t>(l);
-      wl[l * NT] = al;
+      key[l] = SK::make(b, 4 * P + up, l);
+      wl[l * NT] = ldf<FT>(b, 3 * P + up);
     } else {
-      key[l] = ~0ull;
+      key[l] = SK::kPad;
     }
   }
   sort_network<KMAX>(key);
@@ -262,7 +302,7 @@ __device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const Fram
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
     if (i < K) {
-      const int l = static_cast<int>(static_cast<uint32_t>(key[i]));
+      const int l = SK::index(key[i]);
       const float al = wl[l * NT];
       wl[l * NT] = T;
       A = fmaf(T, al, A);
@@ -286,11 +326,19 @@ __device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const Fram
   return make_float4(R, G, B, A);
 }
 
-template <typename FT, int KMAX>
+// Up-front loads for buckets up to upfront_max(KCAP): the kernel's register
+// allocation follows its largest bucket, so a kernel for tiles of at most 16
+// layers keeps more waves resident when its 12/16 buckets load in two phases;
+// the 32-layer kernel is bound by its 24/32 buckets either way.
+constexpr int upfront_max(int kcap) {
+  return DFB_UPFRONT_MAX > 0 ? DFB_UPFRONT_MAX : (kcap <= 16 ? 8 : 16);
+}
+
+template <typename FT, int KMAX, int KCAP>
 __device__ __forceinline__ float4 composite_px(float& T, const FrameArgs& a, const int64_t* __restrict__ loff,
                                                int K, int off, int p, float* __restrict__ wl,
                                                int NT) {
-  if constexpr (KMAX <= 16) return composite_px_upfront<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
+  if constexpr (KMAX <= upfront_max(KCAP)) return composite_px_upfront<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
   else return composite_px_two_phase<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
 }
 
@@ -306,16 +354,17 @@ __device__ __forceinline__ float4 with_background(const FrameArgs& a, int t, int
   return make_float4(fmaf(T, bg.x, x.x), fmaf(T, bg.y, x.y), fmaf(T, bg.z, x.z), fmaf(T, bg.w, x.w));
 }
 
-template <typename FT, int KMAX>
+template <typename FT, int KMAX, int KCAP>
 __device__ float unit_reg(const FrameArgs& a, const Unit& u, const int64_t* __restrict__ loff, int K, int off,
                           float* lds) {
+  static_assert(KMAX <= KCAP, "bucket within the kernel's capacity");
   const int NT = blockDim.x, tid = threadIdx.x;
   float vs = 0.f;
   for (int q = tid; q < a.work_px; q += NT) {
     bool inside;
     const int p = unit_pixel(a, u, q, inside);
     float T;
-    const float4 x = composite_px<FT, KMAX>(T, a, loff, K, off, p, lds + tid, NT);
+    const float4 x = composite_px<FT, KMAX, KCAP>(T, a, loff, K, off, p, lds + tid, NT);
     vs += finish_px(a, u, p, inside, with_background(a, u.t, p, x, T));
   }
   return vs;
@@ -988,16 +1037,16 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
                   : (a.vec_ok ? unit_list_vec<FT>(a, u, blk, K, off) : unit_list<FT>(a, u, blk, K, off));
     } else {
     if (K == 0) vs = unit_background(a, u);
-    else if (K <= 1) vs = unit_reg<FT, 1>(a, u, blk, K, off, wl);
-    else if (K <= 2) vs = unit_reg<FT, 2>(a, u, blk, K, off, wl);
-    else if (K <= 3) vs = unit_reg<FT, 3>(a, u, blk, K, off, wl);
-    else if (K <= 4) vs = unit_reg<FT, 4>(a, u, blk, K, off, wl);
-    else if (K <= 6) vs = unit_reg<FT, 6>(a, u, blk, K, off, wl);
-    else if (K <= 8) vs = unit_reg<FT, 8>(a, u, blk, K, off, wl);
-    else if (KCAP >= 16 && K <= 12) vs = unit_reg<FT, (KCAP >= 16 ? 12 : 1)>(a, u, blk, K, off, wl);
-    else if (KCAP >= 16 && K <= 16) vs = unit_reg<FT, (KCAP >= 16 ? 16 : 1)>(a, u, blk, K, off, wl);
-    else if (KCAP >= 32 && K <= 24) vs = unit_reg<FT, (KCAP >= 32 ? 24 : 1)>(a, u, blk, K, off, wl);
-    else if (KCAP >= 32 && K <= 32) vs = unit_reg<FT, (KCAP >= 32 ? 32 : 1)>(a, u, blk, K, off, wl);
+    else if (K <= 1) vs = unit_reg<FT, 1, KCAP>(a, u, blk, K, off, wl);
+    else if (K <= 2) vs = unit_reg<FT, 2, KCAP>(a, u, blk, K, off, wl);
+    else if (K <= 3) vs = unit_reg<FT, 3, KCAP>(a, u, blk, K, off, wl);
+    else if (K <= 4) vs = unit_reg<FT, 4, KCAP>(a, u, blk, K, off, wl);
+    else if (K <= 6) vs = unit_reg<FT, 6, KCAP>(a, u, blk, K, off, wl);
+    else if (K <= 8) vs = unit_reg<FT, 8, KCAP>(a, u, blk, K, off, wl);
+    else if (KCAP >= 16 && K <= 12) vs = unit_reg<FT, (KCAP >= 16 ? 12 : 1), KCAP>(a, u, blk, K, off, wl);
+    else if (KCAP >= 16 && K <= 16) vs = unit_reg<FT, (KCAP >= 16 ? 16 : 1), KCAP>(a, u, blk, K, off, wl);
+    else if (KCAP >= 32 && K <= 24) vs = unit_reg<FT, (KCAP >= 32 ? 24 : 1), KCAP>(a, u, blk, K, off, wl);
+    else if (KCAP >= 32 && K <= 32) vs = unit_reg<FT, (KCAP >= 32 ? 32 : 1), KCAP>(a, u, blk, K, off, wl);
     else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
     }
     const bool acc = (a.mode & kModeAccumulate) != 0;
