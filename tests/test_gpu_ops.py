@@ -293,3 +293,65 @@ def test_dynamic_load_balancing_round_trip(dfb):
     g = run(dfb, f, dfb.DFB_OP_AVERAGE)
     ref = ref_of(f, "average", order=False)
     assert_colour(g["finished"], ref["rgba"], ref["mag"], "rebalanced average")
+
+
+# ------------------------------------------------------------------ more layers, other widths
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_list_and_average_past_64_layers(dfb, dtype):
+    """Tiles of up to 150 layers: the vector paths hold 64 layer offsets at a
+    time, so the walk crosses two reloads."""
+    counts = workloads.ragged_counts(16, 150, 90, p_empty=0.1)
+    counts[3] = 150
+    counts[7] = 65
+    f = workloads.generation_frame(256, 256, 64, counts, 91, depth_by_generation=False).as_dtype(dtype)
+    g = run(dfb, f, dfb.DFB_OP_LIST, work=32, waves=4)
+    ref = ref_of(f, "list")
+    assert_colour(g["finished"], ref["rgba"], ref["mag"], "list K<=150")
+    check_order(g, ref, f)
+    r, _ = workloads.redundant_frame(256, 256, 64, counts, 0.2, 92)
+    r = r.as_dtype(dtype)
+    g = run(dfb, r, dfb.DFB_OP_AVERAGE, work=64, waves=2)
+    ref = ref_of(r, "average", order=False)
+    assert_colour(g["finished"], ref["rgba"], ref["mag"], "average K<=150")
+
+
+@pytest.mark.parametrize("op", ["list", "average"])
+def test_scalar_path_for_narrow_rows(dfb, op):
+    """Tile rows of 30 pixels cannot be read 4 (fp32) or 8 (fp16) pixels at a
+    time: the per-pixel path runs and gives the same results."""
+    counts = workloads.ragged_counts(6, 20, 93, p_empty=0.2)
+    code = dfb.DFB_OP_LIST if op == "list" else dfb.DFB_OP_AVERAGE
+    for dtype in (np.float32, np.float16):
+        if op == "list":
+            f = workloads.generation_frame(90, 60, 30, counts, 94, depth_by_generation=False)
+        else:
+            f, _ = workloads.redundant_frame(90, 60, 30, counts, 0.2, 95)
+        f = f.as_dtype(dtype)
+        g = run(dfb, f, code, work=0, waves=0, bg=(0.2, 0.1, 0.0, 0.5))
+        ref = ref_of(f, op, (0.2, 0.1, 0.0, 0.5), order=(op == "list"))
+        assert_colour(g["finished"], ref["rgba"], ref["mag"], op + " narrow")
+        if op == "list":
+            check_order(g, ref, f)
+
+
+def test_texture_with_accumulation(dfb):
+    """The texture goes into the accumulated mean like any finished pixel."""
+    counts = workloads.ragged_counts(16, 12, 96, p_empty=0.3)
+    base = workloads.generation_frame(256, 256, 64, counts, 97)
+    img = workloads.background_texture(16, base.P, 98)
+    d_img = upload(img)
+    cfg = dfb.make_config(256, 256, 64, work=32, waves=2, background_image=d_img)
+    mu = np.zeros((16 * base.P, 4))
+    m2 = np.zeros((16 * base.P, 3))
+    keep = []
+    with dfb.Compositor(cfg, stream_handle()) as c:
+        for n in range(1, 4):
+            f = workloads.generation_frame(256, 256, 64, counts, 97 + 10 * n)
+            buf = upload(f.frag)
+            keep.append(buf)
+            c.set_fragments(buf, f.frag.shape[0], f.layers)
+            c.composite(accumulate=True)
+            x = ref_of(f, "blend", image=img.astype(np.float64), order=False)["rgba"]
+            oracle.accumulate(mu, m2, x.reshape(-1, 4), n)
+        acc = c.read(dfb.DFB_BUF_ACCUM_F32)
+    np.testing.assert_allclose(acc.reshape(-1, 4), mu, rtol=0, atol=3e-5)
