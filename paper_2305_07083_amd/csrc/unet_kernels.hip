@@ -68,8 +68,9 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // channels.  The (TH+2) x 34 input halo (every input channel, zero outside
 // the image; read through the nearest-neighbour up-sampling when UP) is
 // staged in LDS once, so the nine taps re-read it from LDS instead of from
-// memory; the weights are staged one tap at a time, double-buffered, the
-// next tap's loads in flight during this tap's MFMAs.  Wave w owns tile rows
+// memory; the weights are staged one tap at a time, the next tap's loads in
+// flight during this tap's MFMAs (double-buffered in LDS where that does not
+// cost resident workgroups).  Wave w owns tile rows
 // w*TH/4 .. +TH/4-1 (TH/2 row blocks of 16 pixels) and every 16-column block
 // of BN.  K runs tap-major, then 32-channel slices.  Epilogue: bias, ReLU, bf16 into LDS, 16-byte
 // coalesced stores, and optionally the 2x2 average pool of the tile (the
@@ -85,7 +86,11 @@ struct TileCfg {
   static constexpr int HALO = HH * HW * LDR;
   static constexpr int BTAP = BN * LDB;
   static constexpr int OUT = TH * kTW * LDO;
-  static constexpr int ELEMS = (HALO + 2 * BTAP) > OUT ? (HALO + 2 * BTAP) : OUT;
+  static constexpr int elems(int nbuf) { return (HALO + nbuf * BTAP) > OUT ? (HALO + nbuf * BTAP) : OUT; }
+  // weight buffers: two (the next tap is stored while this one is read) unless
+  // one buffer lets more workgroups share a compute unit's 160 KB of LDS
+  static constexpr int NBUF = (160 * 1024) / (elems(1) * 2) > (160 * 1024) / (elems(2) * 2) ? 1 : 2;
+  static constexpr int ELEMS = elems(NBUF);
   static constexpr size_t BYTES = static_cast<size_t>(ELEMS) * 2;
 };
 
@@ -100,38 +105,11 @@ __global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __
   uint16_t* bbuf = smem + C::HALO;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tiles_x = (s.w + kTW - 1) / kTW, tiles_y = (s.h + TH - 1) / TH;
-  int blk = static_cast<int>(blockIdx.x);
-  const int n = blk / (tiles_x * tiles_y);
-  blk -= n * tiles_x * tiles_y;
-  const int oy0 = (blk / tiles_x) * TH, ox0 = (blk % tiles_x) * kTW;
   const int hi = UP ? s.h / 2 : s.h, wi = UP ? s.w / 2 : s.w;  // the map x is read from
-  // every halo load is issued before the first LDS store, so their
-  // latencies overlap instead of adding up
-  constexpr int HTOT = C::HH * C::HW * CH8, HIT = (HTOT + 255) / 256;
-  uint4 hreg[HIT];
-#pragma unroll
-  for (int i = 0; i < HIT; ++i) {
-    const int e = tid + i * 256;
-    const int hp = e / CH8, cc = e - hp * CH8;
-    const int r = oy0 - 1 + hp / C::HW, c = ox0 - 1 + hp % C::HW;
-    uint4 v = {0u, 0u, 0u, 0u};
-    if (e < HTOT && r >= 0 && r < s.h && c >= 0 && c < s.w && cc * 8 < x.c) {
-      const long long src = UP ? (static_cast<long long>(n) * hi + (r >> 1)) * wi + (c >> 1)
-                               : (static_cast<long long>(n) * hi + r) * wi + c;
-      v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + cc * 8);
-    }
-    hreg[i] = v;
-  }
-#pragma unroll
-  for (int i = 0; i < HIT; ++i) {
-    const int e = tid + i * 256;
-    if (e < HTOT) {
-      const int hp = e / CH8, cc = e - hp * CH8;
-      *reinterpret_cast<uint4*>(halo + hp * C::LDR + cc * 8) = hreg[i];
-    }
-  }
-  uint4 breg[BPT];
-  auto load_b = [&](int tap) {
+  // Weights of one tap: BCH 16-byte chunks, BPT per thread.  Taps 1..D are
+  // loaded at the start and every later tap D taps before it is needed, so a
+  // tap's short MFMA phase does not wait for a load (D by register budget).
+  auto load_b = [&](int tap, uint4* reg) {
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + i * 256;
@@ -140,103 +118,142 @@ __global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __
         const int co = e / CH8, cc = e - co * CH8;
         if (cc * 8 < x.c) v = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + co) * x.c + cc * 8);
       }
-      breg[i] = v;
+      reg[i] = v;
     }
   };
-  auto store_b = [&](int buf) {
+  auto store_b = [&](int buf, const uint4* reg) {
 #pragma unroll
     for (int i = 0; i < BPT; ++i) {
       const int e = tid + i * 256;
       if (e < BCH) {
         const int co = e / CH8, cc = e - co * CH8;
-        *reinterpret_cast<uint4*>(bbuf + buf * C::BTAP + co * C::LDB + cc * 8) = breg[i];
+        *reinterpret_cast<uint4*>(bbuf + buf * C::BTAP + co * C::LDB + cc * 8) = reg[i];
       }
     }
   };
-  load_b(0);
-  store_b(0);
-  f32x4 acc[MB][NB];
+  // every halo load is issued (after the weight prologue's) before the first
+  // LDS store, so their latencies overlap instead of adding up
+  constexpr int HTOT = C::HH * C::HW * CH8, HIT = (HTOT + 255) / 256;
+  constexpr int D = BPT >= 8 ? 1 : (BPT >= 4 ? 2 : (BPT >= 2 ? 4 : 8));
+  uint4 b0[BPT], ring[D][BPT], hreg[HIT];
+  const int t = static_cast<int>(blockIdx.x);
+  {
+    const int n = t / (tiles_x * tiles_y);
+    const int b = t - n * tiles_x * tiles_y;
+    const int oy0 = (b / tiles_x) * TH, ox0 = (b % tiles_x) * kTW;
+    load_b(0, b0);
 #pragma unroll
-  for (int m = 0; m < MB; ++m)
+    for (int j = 1; j <= D; ++j) load_b(j, ring[(j - 1) % D]);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  __syncthreads();
-  for (int tap = 0; tap < 9; ++tap) {
-    if (tap + 1 < 9) load_b(tap + 1);
-    const int dr = tap / 3, dc = tap - (tap / 3) * 3;
-    const uint16_t* B = bbuf + (tap & 1) * C::BTAP;
+    for (int i = 0; i < HIT; ++i) {
+      const int e = tid + i * 256;
+      const int hp = e / CH8, cc = e - hp * CH8;
+      const int r = oy0 - 1 + hp / C::HW, c = ox0 - 1 + hp % C::HW;
+      uint4 v = {0u, 0u, 0u, 0u};
+      if (e < HTOT && r >= 0 && r < s.h && c >= 0 && c < s.w && cc * 8 < x.c) {
+        const long long src = UP ? (static_cast<long long>(n) * hi + (r >> 1)) * wi + (c >> 1)
+                                 : (static_cast<long long>(n) * hi + r) * wi + c;
+        v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + cc * 8);
+      }
+      hreg[i] = v;
+    }
 #pragma unroll
-    for (int ks = 0; ks < CP / 32; ++ks) {
-      bf16x8 bf[NB];
+    for (int i = 0; i < HIT; ++i) {
+      const int e = tid + i * 256;
+      if (e < HTOT) {
+        const int hp = e / CH8, cc = e - hp * CH8;
+        *reinterpret_cast<uint4*>(halo + hp * C::LDR + cc * 8) = hreg[i];
+      }
+    }
+    store_b(0, b0);
+    __syncthreads();
+    f32x4 acc[MB][NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) bf[j] = lds_frag(B + (j * 16 + (lane & 15)) * C::LDB + ks * 32 + (lane >> 4) * 8);
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dr = tap / 3, dc = tap - (tap / 3) * 3;
+      const uint16_t* B = bbuf + (C::NBUF == 2 ? (tap & 1) : 0) * C::BTAP;
+#pragma unroll
+      for (int ks = 0; ks < CP / 32; ++ks) {
+        bf16x8 bf[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) bf[j] = lds_frag(B + (j * 16 + (lane & 15)) * C::LDB + ks * 32 + (lane >> 4) * 8);
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
+          const bf16x8 a = lds_frag(halo + ((row + dr) * C::HW + col + dc) * C::LDR + ks * 32 + (lane >> 4) * 8);
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[j], acc[m][j], 0, 0, 0);
+        }
+      }
+      if (tap + 1 < 9) {
+        if (C::NBUF == 1) __syncthreads();  // every wave is done with the single buffer
+        store_b(C::NBUF == 2 ? (tap + 1) & 1 : 0, ring[tap % D]);  // the slot of tap + 1
+        if (tap + 1 + D < 9) load_b(tap + 1 + D, ring[tap % D]);
+      }
+      __syncthreads();
+    }
+    // epilogue: bias + ReLU + bf16 into the staging tile (the halo is no longer read)
+    uint16_t* ot = smem;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int ch = j * 16 + (lane & 15);
+      const float bb = bias[ch];
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
-        const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
-        const bf16x8 a = lds_frag(halo + ((row + dr) * C::HW + col + dc) * C::LDR + ks * 32 + (lane >> 4) * 8);
+        const int row = wave * WR + m / 2;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[j], acc[m][j], 0, 0, 0);
-      }
-    }
-    if (tap + 1 < 9) store_b((tap + 1) & 1);
-    __syncthreads();
-  }
-  // epilogue: bias + ReLU + bf16 into the staging tile (the halo is no longer read)
-  uint16_t* ot = smem;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int ch = j * 16 + (lane & 15);
-    const float bb = bias[ch];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-      const int row = wave * WR + m / 2;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int col = (m & 1) * 16 + (lane >> 4) * 4 + r;
-        const float v = acc[m][j][r] + bb;
-        ot[(row * kTW + col) * C::LDO + ch] = to_bf16(v > 0.f ? v : 0.f);
-      }
-    }
-  }
-  __syncthreads();
-  constexpr int OCH = BN / 8;
-  for (int e = tid; e < TH * kTW * OCH; e += 256) {
-    const int pi = e / OCH, cc = e - pi * OCH;
-    const int r = oy0 + pi / kTW, c = ox0 + pi % kTW;
-    if (r < s.h && c < s.w) {
-      const long long p = (static_cast<long long>(n) * s.h + r) * s.w + c;
-      *reinterpret_cast<uint4*>(y.p + p * y.ld + y.off + cc * 8) = *reinterpret_cast<const uint4*>(ot + pi * C::LDO + cc * 8);
-    }
-  }
-  if (pool.p) {
-    const int ph = s.h / 2, pw = s.w / 2;
-    for (int e = tid; e < (TH / 2) * (kTW / 2) * OCH; e += 256) {
-      const int qi = e / OCH, cc = e - qi * OCH;
-      const int qr = qi / (kTW / 2), qc = qi - qr * (kTW / 2);
-      const int r = oy0 / 2 + qr, c = ox0 / 2 + qc;
-      if (r < ph && c < pw) {
-        const uint16_t* t00 = ot + ((2 * qr) * kTW + 2 * qc) * C::LDO + cc * 8;
-        const uint4 a = *reinterpret_cast<const uint4*>(t00);
-        const uint4 b = *reinterpret_cast<const uint4*>(t00 + C::LDO);
-        const uint4 c2 = *reinterpret_cast<const uint4*>(t00 + kTW * C::LDO);
-        const uint4 d = *reinterpret_cast<const uint4*>(t00 + (kTW + 1) * C::LDO);
-        const uint32_t A[4] = {a.x, a.y, a.z, a.w}, Bw[4] = {b.x, b.y, b.z, b.w}, Cw[4] = {c2.x, c2.y, c2.z, c2.w},
-                       D[4] = {d.x, d.y, d.z, d.w};
-        uint32_t o[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t packed = 0;
-#pragma unroll
-          for (int hlf = 0; hlf < 2; ++hlf) {
-            const int sh = hlf * 16;
-            const float v = from_bf16(static_cast<uint16_t>(A[k] >> sh)) + from_bf16(static_cast<uint16_t>(Bw[k] >> sh)) +
-                            from_bf16(static_cast<uint16_t>(Cw[k] >> sh)) + from_bf16(static_cast<uint16_t>(D[k] >> sh));
-            packed |= static_cast<uint32_t>(to_bf16(0.25f * v)) << sh;
-          }
-          o[k] = packed;
+        for (int r = 0; r < 4; ++r) {
+          const int col = (m & 1) * 16 + (lane >> 4) * 4 + r;
+          const float v = acc[m][j][r] + bb;
+          ot[(row * kTW + col) * C::LDO + ch] = to_bf16(v > 0.f ? v : 0.f);
         }
-        const long long p = (static_cast<long long>(n) * ph + r) * pw + c;
-        *reinterpret_cast<uint4*>(pool.p + p * pool.ld + pool.off + cc * 8) = uint4{o[0], o[1], o[2], o[3]};
+      }
+    }
+    __syncthreads();
+    constexpr int OCH = BN / 8;
+    for (int e = tid; e < TH * kTW * OCH; e += 256) {
+      const int pi = e / OCH, cc = e - pi * OCH;
+      const int r = oy0 + pi / kTW, c = ox0 + pi % kTW;
+      if (r < s.h && c < s.w) {
+        const long long p = (static_cast<long long>(n) * s.h + r) * s.w + c;
+        *reinterpret_cast<uint4*>(y.p + p * y.ld + y.off + cc * 8) =
+            *reinterpret_cast<const uint4*>(ot + pi * C::LDO + cc * 8);
+      }
+    }
+    if (pool.p) {
+      const int ph = s.h / 2, pw = s.w / 2;
+      for (int e = tid; e < (TH / 2) * (kTW / 2) * OCH; e += 256) {
+        const int qi = e / OCH, cc = e - qi * OCH;
+        const int qr = qi / (kTW / 2), qc = qi - qr * (kTW / 2);
+        const int r = oy0 / 2 + qr, c = ox0 / 2 + qc;
+        if (r < ph && c < pw) {
+          const uint16_t* t00 = ot + ((2 * qr) * kTW + 2 * qc) * C::LDO + cc * 8;
+          const uint4 a = *reinterpret_cast<const uint4*>(t00);
+          const uint4 bq = *reinterpret_cast<const uint4*>(t00 + C::LDO);
+          const uint4 c2 = *reinterpret_cast<const uint4*>(t00 + kTW * C::LDO);
+          const uint4 d = *reinterpret_cast<const uint4*>(t00 + (kTW + 1) * C::LDO);
+          const uint32_t A[4] = {a.x, a.y, a.z, a.w}, Bw[4] = {bq.x, bq.y, bq.z, bq.w},
+                         Cw[4] = {c2.x, c2.y, c2.z, c2.w}, Dw[4] = {d.x, d.y, d.z, d.w};
+          uint32_t o[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            uint32_t packed = 0;
+#pragma unroll
+            for (int hlf = 0; hlf < 2; ++hlf) {
+              const int sh = hlf * 16;
+              const float v = from_bf16(static_cast<uint16_t>(A[k] >> sh)) + from_bf16(static_cast<uint16_t>(Bw[k] >> sh)) +
+                              from_bf16(static_cast<uint16_t>(Cw[k] >> sh)) + from_bf16(static_cast<uint16_t>(Dw[k] >> sh));
+              packed |= static_cast<uint32_t>(to_bf16(0.25f * v)) << sh;
+            }
+            o[k] = packed;
+          }
+          const long long p = (static_cast<long long>(n) * ph + r) * pw + c;
+          *reinterpret_cast<uint4*>(pool.p + p * pool.ld + pool.off + cc * 8) = uint4{o[0], o[1], o[2], o[3]};
+        }
       }
     }
   }
@@ -679,6 +696,7 @@ hipError_t launch_tile(const Map& x, const uint16_t* w, const float* bias, const
     if (e != hipSuccess) return e;
   }
   const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
+  if (tiles > (1LL << 30)) return hipErrorInvalidValue;
   conv_fwd_tile_k<BN, CP, TH, UP><<<static_cast<unsigned>(tiles), 256, C::BYTES, st>>>(x, w, bias, y, pool, s);
   return hipGetLastError();
 }
