@@ -18,7 +18,9 @@ import time
 
 import numpy as np
 
-import paper_2305_07083_amd as dfb
+if __package__ in (None, ""):  # run as a script: make the package importable
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import paper_2305_07083_amd as dfb  # noqa: E402
 
 N_INPUTS = (1, 2, 4, 8)
 SIGMA = 0.2
@@ -231,6 +233,42 @@ def run(scenes=12, steps=1500, batch=8, crop=128, size=2048, log=print):
         raise
 
 
+def time_kernels(size=2048, passes=5, steps=10, batch=8, crop=128, log=print):
+    """Device time of the network alone, randomly initialised: forward passes
+    on a random 1 x size x size x 6 input, then training steps on random
+    batch x crop x crop crops (3 untimed warm-up calls each)."""
+    torch = _torch()
+    dfb.load()
+    res = {}
+    with dfb.Denoiser(max(size * size, batch * crop * crop), seed=0) as net:
+        x = torch.rand((1, size, size, 6), device="cuda")
+        out = torch.empty((1, size, size, 3), device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            dfb.dfb_denoiser_forward(net.net, x, out, 1, size, size)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(passes):
+            dfb.dfb_denoiser_forward(net.net, x, out, 1, size, size)
+        e1.record()
+        torch.cuda.synchronize()
+        res["ms_forward"] = e0.elapsed_time(e1) / passes
+        xin = torch.rand((batch, crop, crop, 6), device="cuda")
+        tgt = torch.rand((batch, crop, crop, 3), device="cuda")
+        for _ in range(3):
+            dfb.dfb_denoiser_train_step(net.net, xin, tgt, batch, crop, crop, 1e-3, True, want_loss=False)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            dfb.dfb_denoiser_train_step(net.net, xin, tgt, batch, crop, crop, 1e-3, True, want_loss=False)
+        e1.record()
+        torch.cuda.synchronize()
+        res["ms_train_step"] = e0.elapsed_time(e1) / steps
+    log("forward %dx%d: %.3f ms; train step %dx%dx%d: %.3f ms" % (size, size, res["ms_forward"], batch, crop, crop,
+                                                                 res["ms_train_step"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--scenes", type=int, default=12)
@@ -238,7 +276,12 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--crop", type=int, default=128)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--time-only", action="store_true",
+                    help="only time the network's kernels (random weights, random inputs)")
     a = ap.parse_args()
+    if a.time_only:
+        time_kernels(log=lambda m: print(m, flush=True))
+        return
     res, net, _ = run(a.scenes, a.steps, a.batch, a.crop, log=lambda m: print(m, flush=True))
     net.close()
     txt = json.dumps(res, default=float)
@@ -249,5 +292,4 @@ def main():
 
 
 if __name__ == "__main__":
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     main()
