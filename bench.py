@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--denoise-steps", type=int, default=1000)
     ap.add_argument("--no-ops", action="store_true",
                     help="skip the list / average tile-operation legs")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the 4096x1024 (fp32, fp16) and 8192x8192 sort-path legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device to device (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -273,6 +275,58 @@ def tile_ops_leg(dfb, torch, steps=30, warmup=5, copies=4):
     return out
 
 
+def other_workloads_leg(dfb, torch, steps=10, warmup=3):
+    """The sort path on the other frame shapes, accumulating frames (the
+    4096x1024 progressive case, fp32 and fp16) and plain frames (the 8192x8192
+    heavy-tailed case), autotuned, 2 rotating copies (1 for the device-drawn
+    8192x8192 set).  Algorithmic bytes as for the headline."""
+    import numpy as np
+    import workloads
+    out = {}
+    dev = torch.device("cuda:0")
+    for name, accumulate in (("c3", True), ("c3f16", True), ("c4", False)):
+        f, desc = make_frame(name)
+        if name == "c4":
+            copies = [workloads.uniform_values_torch(len(f.layers), f.P, seed=0, device=dev)]
+            f16 = False
+        else:
+            copies = [torch.from_numpy(f.frag).to(dev) for _ in range(2)]
+            f16 = f.frag.dtype == np.float16
+        torch.cuda.synchronize()
+        cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=0, waves=0,
+                              dtype=dfb.DFB_F16 if f16 else dfb.DFB_F32)
+        n_blocks = copies[0].shape[0]
+        with dfb.Compositor(cfg, torch.cuda.current_stream().cuda_stream) as c:
+            c.set_fragments(copies[0], n_blocks, f.layers, f.expected)
+            c.composite()  # autotune
+            for i in range(warmup):
+                c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+                c.composite(accumulate=accumulate)
+            torch.cuda.synchronize()
+            dfb.dfb_set_timing(c.h, True)
+            for i in range(steps):
+                c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+                c.composite(accumulate=accumulate)
+            torch.cuda.synchronize()
+            kms = dfb.dfb_kernel_ms(c.h)
+            info = c.info()
+        del copies
+        torch.cuda.empty_cache()
+        px = f.n_tiles * f.P
+        alg = f.n_fragments * (10 if f16 else 20) + px * (4 + (56 if accumulate else 0)) + f.n_tiles * 4 \
+            + len(f.layers) * 8
+        gbps = alg / (kms * 1e-3) / 1e9
+        out[name] = {"workload": desc + (", composite + accumulate + per-tile variance + RGBA8" if accumulate
+                                         else ", composite + RGBA8"),
+                     "fragments_per_frame": f.n_fragments, "kernel_ms": kms,
+                     "fragments_per_s": f.n_fragments / (kms * 1e-3),
+                     "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
+                     "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                  "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                                  "algorithmic_bytes_per_launch": alg}}
+    return out
+
+
 def cpu_baseline(f, accumulate, budget_s=12.0):
     """The FP64 oracle as it stands, on whole frames, repeated for about
     ``budget_s`` seconds on this host's cores."""
@@ -390,6 +444,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(f, accumulate)
     if not args.no_ops and args.workload == "c2":
         out["tile_ops"] = tile_ops_leg(dfb, torch)
+    if not args.no_other and args.workload == "c2":
+        del copies
+        torch.cuda.empty_cache()
+        out["other_workloads"] = other_workloads_leg(dfb, torch)
     if not args.no_denoise and args.workload == "c2":
         out["denoise"] = denoise_leg(args.denoise_scenes, args.denoise_steps)
     print(json.dumps(out), flush=True)
