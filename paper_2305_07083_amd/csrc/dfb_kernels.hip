@@ -1029,7 +1029,7 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
     const int K = tile_off[u.t + 1] - off;
     const int64_t* __restrict__ blk = layer_off + off;
     float* wl = reinterpret_cast<float*>(lds);
-    float vs;
+    float vs = 0.f;
     if constexpr (OP == DFB_OP_AVERAGE) {
       vs = (a.vec_ok && K > 0) ? unit_average_vec<FT>(a, u, blk, K) : unit_average<FT>(a, u, blk, K);
     } else if constexpr (OP == DFB_OP_LIST) {
@@ -1043,11 +1043,18 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
     else if (K <= 4) vs = unit_reg<FT, 4, KCAP>(a, u, blk, K, off, wl);
     else if (K <= 6) vs = unit_reg<FT, 6, KCAP>(a, u, blk, K, off, wl);
     else if (K <= 8) vs = unit_reg<FT, 8, KCAP>(a, u, blk, K, off, wl);
-    else if (KCAP >= 16 && K <= 12) vs = unit_reg<FT, (KCAP >= 16 ? 12 : 1), KCAP>(a, u, blk, K, off, wl);
-    else if (KCAP >= 16 && K <= 16) vs = unit_reg<FT, (KCAP >= 16 ? 16 : 1), KCAP>(a, u, blk, K, off, wl);
-    else if (KCAP >= 32 && K <= 24) vs = unit_reg<FT, (KCAP >= 32 ? 24 : 1), KCAP>(a, u, blk, K, off, wl);
-    else if (KCAP >= 32 && K <= 32) vs = unit_reg<FT, (KCAP >= 32 ? 32 : 1), KCAP>(a, u, blk, K, off, wl);
-    else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
+    else if constexpr (KCAP >= 16) {
+      // the kernel of a frame whose tiles have at most KCAP layers carries
+      // no code for more: K <= KCAP here (the host picks KCAP >= the
+      // frame's largest tile)
+      if (K <= 12) vs = unit_reg<FT, 12, KCAP>(a, u, blk, K, off, wl);
+      else if (KCAP == 16 || K <= 16) vs = unit_reg<FT, 16, KCAP>(a, u, blk, K, off, wl);
+      else if constexpr (KCAP >= 32) {
+        if (K <= 24) vs = unit_reg<FT, 24, KCAP>(a, u, blk, K, off, wl);
+        else if (K <= 32) vs = unit_reg<FT, 32, KCAP>(a, u, blk, K, off, wl);
+        else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
+      }
+    }
     }
     const bool acc = (a.mode & kModeAccumulate) != 0;
     if (acc) {

@@ -125,6 +125,27 @@ def test_layer_counts_across_register_and_lds_paths(dfb, ranks):
     check_frame(dfb, f, bg=(0.3, 0.2, 0.1, 0.9))
 
 
+@pytest.mark.parametrize("ranks", [1500, 2048, 2100])
+def test_thousands_of_layers(dfb, ranks):
+    """Padded layer counts of 2048 and 4096 in the LDS sort: against the
+    oracle, order bit-exact."""
+    f = workloads.uniform_frame(16, 16, 16, ranks=ranks, seed=ranks)
+    check_frame(dfb, f, work=0, waves=0, bg=(0.1, 0.1, 0.1, 1.0))
+
+
+@pytest.mark.parametrize("work", [16, 32, 64])
+def test_work_units_identical_for_many_layers(dfb, work):
+    """With the waves per unit fixed, the LDS path splits each pixel's
+    colour sum over the same lanes for every work-unit size: identical
+    results (across waves per unit the split differs, so only the oracle's
+    tolerance applies there)."""
+    f = workloads.uniform_frame(128, 128, 64, ranks=100, seed=21)
+    base = composite_gpu(dfb, f, work=32, waves=4)
+    g = composite_gpu(dfb, f, work=work, waves=4)
+    assert np.array_equal(base["finished"], g["finished"])
+    assert np.array_equal(base["order"], g["order"])
+
+
 @pytest.mark.parametrize("ranks", [6, 40])
 def test_depth_ties_break_by_source(dfb, ranks):
     f = workloads.uniform_frame(64, 64, 64, ranks=ranks, seed=3)
