@@ -360,8 +360,8 @@ def cpu_baseline(f, accumulate, budget_s=12.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
-              "(the per-tile exchange between GPUs is not implemented)", file=sys.stderr)
+        print("bench.py measures one GPU: the per-tile exchange between GPUs is not implemented, "
+              "so only --gpus 1 runs", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
