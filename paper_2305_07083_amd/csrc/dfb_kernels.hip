@@ -702,19 +702,30 @@ __device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* 
 //
 // S = NT / G lanes share a pixel for the front-to-back walk (a product scan
 // over S chunks) and for the colour sums (a fixed-order reduction).
-constexpr int kBlk = 16;
+#ifndef DFB_BLK_LOG
+#define DFB_BLK_LOG 4
+#endif
+constexpr int kBlkLog = DFB_BLK_LOG;   // keys sorted per lane in registers: 2^kBlkLog
+constexpr int kBlk = 1 << kBlkLog;
 
 __device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
 
+// a block is read as runs of 16 keys, none of which straddles a pad slot
 __device__ __forceinline__ void block_load(const uint64_t* r, int base, uint64_t (&k)[kBlk]) {
-  const uint64_t* q = r + kslot(base);  // a block never straddles a pad slot
 #pragma unroll
-  for (int i = 0; i < kBlk; ++i) k[i] = q[i];
+  for (int h = 0; h < kBlk / 16; ++h) {
+    const uint64_t* q = r + kslot(base + 16 * h);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) k[16 * h + i] = q[i];
+  }
 }
 __device__ __forceinline__ void block_store(uint64_t* r, int base, const uint64_t (&k)[kBlk]) {
-  uint64_t* q = r + kslot(base);
 #pragma unroll
-  for (int i = 0; i < kBlk; ++i) q[i] = k[i];
+  for (int h = 0; h < kBlk / 16; ++h) {
+    uint64_t* q = r + kslot(base + 16 * h);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) q[i] = k[16 * h + i];
+  }
 }
 // strides 8, 4, 2, 1 of a merge larger than the block (half-cleaners)
 __device__ __forceinline__ void block_half_clean(uint64_t (&k)[kBlk]) {
@@ -755,7 +766,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
   float4* red = reinterpret_cast<float4*>(lds + a.big_lds);  // [NT]
   float* tend = reinterpret_cast<float*>(red + NT);           // [G]
   const int gm = tid & (G - 1), sm = tid >> lg;
-  const int nblk = G << (lk - 4);  // 16-key blocks over all rows
+  const int nblk = G << (lk - kBlkLog);  // register blocks over all rows
   float vs = 0.f;
   for (int q0 = 0; q0 < a.work_px; q0 += G) {
     // 1. keys and alpha (coalesced over the G pixels); 8 elements per lane
@@ -792,15 +803,15 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     // 2. sort every row: blocks of 16 in registers first
     for (int b = tid; b < nblk; b += NT) {
       uint64_t k[kBlk];
-      uint64_t* r = keys + (b >> (lk - 4)) * RS;
-      const int base = (b & ((1 << (lk - 4)) - 1)) * kBlk;
+      uint64_t* r = keys + (b >> (lk - kBlkLog)) * RS;
+      const int base = (b & ((1 << (lk - kBlkLog)) - 1)) * kBlk;
       block_load(r, base, k);
       sort_network<kBlk>(k);
       block_store(r, base, k);
     }
     lds_barrier();
-    for (int ls = 5; ls <= lk; ++ls) {          // merge size 2^ls
-      for (int lt = ls - 1; lt >= 4; --lt) {     // strides >= 16 through LDS
+    for (int ls = kBlkLog + 1; ls <= lk; ++ls) {  // merge size 2^ls
+      for (int lt = ls - 1; lt >= kBlkLog; --lt) {  // strides >= kBlk through LDS
         const int str = 1 << lt;
         const int pairs = G << (lk - 1);
         for (int e0 = tid; e0 < pairs; e0 += 4 * NT) {  // 4 pairs per lane in flight
@@ -831,8 +842,8 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       }
       for (int b = tid; b < nblk; b += NT) {     // strides 8..1 in registers
         uint64_t k[kBlk];
-        uint64_t* r = keys + (b >> (lk - 4)) * RS;
-        const int base = (b & ((1 << (lk - 4)) - 1)) * kBlk;
+        uint64_t* r = keys + (b >> (lk - kBlkLog)) * RS;
+        const int base = (b & ((1 << (lk - kBlkLog)) - 1)) * kBlk;
         block_load(r, base, k);
         block_half_clean(k);
         block_store(r, base, k);
