@@ -688,27 +688,65 @@ __device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* 
 // ---------------------------------------------------------------- K > 32
 // The workgroup handles G pixels at a time.  LDS holds one row per pixel:
 // Kp keys (u64) and, in a second array of the same shape, Kp floats (alpha,
-// later the transmittance T).  Position i of a row is stored at
-// i + i/16 (one pad slot per 16) and rows are RS = Kp*17/16 + 1 slots apart,
-// so the coalesced fill (lanes across rows), the LDS sort stages (lanes along
-// a row) and the register blocks (a lane per 16 consecutive keys) all hit
-// distinct banks.
+// later the transmittance T); and the unit's layer offsets.  Position i of a
+// row is stored at i + i/16 (one pad slot per 16) and rows are
+// RS = Kp*17/16 + 1 slots apart, so the fill (lanes across rows), the LDS
+// sort passes (lanes along a row) and the register blocks (a lane per 16
+// consecutive keys) all hit distinct banks.
+//
+// Lane (g, s), s < S = NT / G, owns layers s, s + S, s + 2S, ... of pixel g.
+// It loads their depth, alpha and colour together at the start of the group
+// (the colours of its first kBigC layers wait in registers until the walk
+// has produced the weights), so one memory round trip serves the group.
 //
 // Sort: bitonic, every comparator min-to-lower.  Comparators closer than 16
 // positions never leave a 16-key block, so each block is sorted (sizes
 // 2..16) or half-cleaned (strides 8..1 of every later merge) by one lane in
-// registers; only strides >= 16 go through LDS with a barrier each.  For
-// Kp = 512 that is 21 barriers instead of 45.
+// registers.  The strides >= 16 of a merge go through LDS up to four at a
+// time: a lane loads the 2^m keys that m consecutive stages compare only
+// among themselves, runs the m stages in registers and writes the keys
+// back, one barrier per pass.  For Kp = 512 that is 6 LDS passes, not 15.
 //
-// S = NT / G lanes share a pixel for the front-to-back walk (a product scan
-// over S chunks) and for the colour sums (a fixed-order reduction).
+// The walk: the S lanes of a pixel take a product scan over S chunks of the
+// sorted row; then colour sums in layer order and a fixed-order reduction
+// over the S lanes.
 #ifndef DFB_BLK_LOG
 #define DFB_BLK_LOG 4
 #endif
 constexpr int kBlkLog = DFB_BLK_LOG;   // keys sorted per lane in registers: 2^kBlkLog
 constexpr int kBlk = 1 << kBlkLog;
+#ifndef DFB_BIG_C
+#define DFB_BIG_C 8
+#endif
+#ifndef DFB_MAX_M
+#define DFB_MAX_M 4
+#endif
+constexpr int kBigC = DFB_BIG_C;              // layers per lane whose colours are loaded with the keys
 
 __device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
+
+// Keys of this path.  The sort order (ordered depth bits, then layer index)
+// is that of the 44-bit integer x = depth_bits << 12 | l (l < 4096).  Held as
+// the double 2^52 + x (bit pattern 0x433 << 52 | x), every key is a normal
+// double whose value orders like x, so a comparator is one v_min_f64 and one
+// v_max_f64 instead of two 64-bit integer compares and four selects.  The
+// layer index is the low 12 bits of the pattern.
+constexpr uint64_t kKeyBias = 0x4330000000000000ull;
+constexpr uint64_t kKeyPad = kKeyBias | 0x00000FFFFFFFFFFFull;  // not below any real key
+__device__ __forceinline__ uint64_t big_key(uint32_t dbits, int l) {
+  return kKeyBias | (static_cast<uint64_t>(dbits) << 12) | static_cast<uint32_t>(l);
+}
+__device__ __forceinline__ int key_layer(uint64_t k) { return static_cast<int>(k & 0xFFFu); }
+struct KeyMinMax {
+  __device__ __forceinline__ void operator()(uint64_t& a, uint64_t& b) const {
+    const double x = __builtin_bit_cast(double, a), y = __builtin_bit_cast(double, b);
+    double lo, hi;
+    asm("v_min_f64 %0, %1, %2" : "=v"(lo) : "v"(x), "v"(y));
+    asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(x), "v"(y));
+    a = __builtin_bit_cast(uint64_t, lo);
+    b = __builtin_bit_cast(uint64_t, hi);
+  }
+};
 
 // a block is read as runs of 16 keys, none of which straddles a pad slot
 __device__ __forceinline__ void block_load(const uint64_t* r, int base, uint64_t (&k)[kBlk]) {
@@ -733,7 +771,58 @@ __device__ __forceinline__ void block_half_clean(uint64_t (&k)[kBlk]) {
   for (int str = kBlk / 2; str > 0; str >>= 1)
 #pragma unroll
     for (int i = 0; i < kBlk; ++i)
-      if ((i & str) == 0) compare_exchange(k[i], k[i + str]);
+      if ((i & str) == 0) KeyMinMax()(k[i], k[i + str]);
+}
+
+// One LDS pass over every row: M consecutive stages of the merge of size
+// 2^ls, the first with stride 2^lt, the last with stride 2^lo (lo = lt-M+1).
+// Group c of a row is the positions b + r 2^lo (r < 2^M), b being c with M
+// zero bits inserted at lo..lt; these meet only each other in the M stages.
+// When lt = ls - 1 the first stage is the merge's mirrored one (x against
+// x ^ (2^ls - 1)) and the upper half of a group is the mirror image of its
+// lower half, in increasing position order.
+template <int M>
+__device__ __forceinline__ void lds_stages(uint64_t* keys, int RS, int G, int lk, int ls, int lt,
+                                           int NT, int tid) {
+  constexpr int N = 1 << M, H = N / 2, U = M >= 3 ? 1 : (M == 2 ? 2 : 4);  // groups in flight
+  const int lo = lt - M + 1, glog = lk - M, total = G << glog;
+  const bool mirror = lt == ls - 1;
+  const int mask = (2 << lt) - 1;
+  for (int e0 = tid; e0 < total; e0 += U * NT) {
+    uint64_t v[U][N];
+    int ix[U][N];
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+      const int e = min(e0 + w * NT, total - 1);  // reads in range; writes guarded below
+      const int g = e >> glog, c = e & ((1 << glog) - 1);
+      const int b = ((c >> lo) << (lt + 1)) | (c & ((1 << lo) - 1));
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        const int pos = (mirror && r >= H) ? ((b + ((N - 1 - r) << lo)) ^ mask) : b + (r << lo);
+        ix[w][r] = g * RS + kslot(pos);
+        v[w][r] = keys[ix[w][r]];
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+      if (mirror) {
+#pragma unroll
+        for (int r = 0; r < H; ++r) KeyMinMax()(v[w][r], v[w][N - 1 - r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < H; ++r) KeyMinMax()(v[w][r], v[w][r + H]);
+      }
+#pragma unroll
+      for (int k = M - 2; k >= 0; --k)
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+          if ((r & (1 << k)) == 0) KeyMinMax()(v[w][r], v[w][r | (1 << k)]);
+      if (e0 + w * NT < total) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) keys[ix[w][r]] = v[w][r];
+      }
+    }
+  }
 }
 
 // G (pixels per group) for a padded layer count 2^lk and an LDS budget.
@@ -760,42 +849,83 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
   int lg = 0;
   while ((1 << lg) < G) ++lg;
   const int S = NT / G;                   // lanes per pixel
-  const int C = Kp / S > 0 ? Kp / S : 1;  // sorted positions per lane
+  const int C = Kp / S > 0 ? Kp / S : 1;  // layers (and sorted positions) per lane
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
   float* wv = reinterpret_cast<float*>(keys + static_cast<size_t>(G) * RS);
   float4* red = reinterpret_cast<float4*>(lds + a.big_lds);  // [NT]
-  float* tend = reinterpret_cast<float*>(red + NT);           // [G]
+  float* tend = reinterpret_cast<float*>(red + NT);           // [G], G <= 64
+  int64_t* lofs = reinterpret_cast<int64_t*>(tend + 64);      // [K]
+  for (int i = tid; i < K; i += NT) lofs[i] = loff[i];
+  lds_barrier();
   const int gm = tid & (G - 1), sm = tid >> lg;
   const int nblk = G << (lk - kBlkLog);  // register blocks over all rows
+  uint64_t* krow = keys + gm * RS;
+  float* wrow = wv + gm * RS;
   float vs = 0.f;
   for (int q0 = 0; q0 < a.work_px; q0 += G) {
-    // 1. keys and alpha (coalesced over the G pixels); 8 elements per lane
-    //    per step so that their loads are in flight together
-    for (int e0 = tid; e0 < (G << lk); e0 += 8 * NT) {
+    const int qme = q0 + gm;
+    const bool live = qme < a.work_px;
+    bool in_me = false;
+    const int p_me = live ? unit_pixel(a, u, qme, in_me) : 0;
+    // 1. depth, alpha and colour of the lane's layers l = sm + j S, all
+    //    loads issued before the first LDS store; padding keys sort last
+    float cr[kBigC], cg[kBigC], cb[kBigC];
+    {
+      float dv[kBigC], av[kBigC];
+#pragma unroll
+      for (int j = 0; j < kBigC; ++j) {
+        const int l = sm + j * S;
+        dv[j] = 0.f;
+        av[j] = 0.f;
+        cr[j] = 0.f;
+        cg[j] = 0.f;
+        cb[j] = 0.f;
+        if (j < C && live && l < K) {
+          const FT* __restrict__ b = frag + lofs[l];
+          dv[j] = ldf<FT>(b, 4 * P + p_me);
+          av[j] = ldf<FT>(b, 3 * P + p_me);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kBigC; ++j) {
+        const int l = sm + j * S;
+        if (j < C && live && l < K) {
+          const FT* __restrict__ b = frag + lofs[l];
+          cr[j] = ldf<FT>(b, p_me);
+          cg[j] = ldf<FT>(b, P + p_me);
+          cb[j] = ldf<FT>(b, 2 * P + p_me);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kBigC; ++j) {
+        const int l = sm + j * S;
+        if (j < C) {
+          krow[kslot(l)] = (live && l < K)
+                               ? big_key(depth_bits(dv[j]), l) : kKeyPad;
+          wrow[kslot(l)] = av[j];
+        }
+      }
+    }
+    for (int j0 = kBigC; j0 < C; j0 += 8) {  // more layers than kBigC per lane: keys only here
       float dv[8], av[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int e = e0 + j * NT;
-        const int g = e & (G - 1), l = e >> lg, q = q0 + g;
+        const int l = sm + (j0 + j) * S;
         dv[j] = 0.f;
         av[j] = 0.f;
-        if (e < (G << lk) && l < K && q < a.work_px) {
-          bool in;
-          const int p = unit_pixel(a, u, q, in);
-          const FT* __restrict__ b = frag + loff[l];
-          dv[j] = ldf<FT>(b, 4 * P + p);
-          av[j] = ldf<FT>(b, 3 * P + p);
+        if (j0 + j < C && live && l < K) {
+          const FT* __restrict__ b = frag + lofs[l];
+          dv[j] = ldf<FT>(b, 4 * P + p_me);
+          av[j] = ldf<FT>(b, 3 * P + p_me);
         }
       }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int e = e0 + j * NT;
-        const int g = e & (G - 1), l = e >> lg, q = q0 + g;
-        if (e < (G << lk)) {
-          const bool real = l < K && q < a.work_px;
-          keys[g * RS + kslot(l)] =
-              real ? ((static_cast<uint64_t>(depth_bits(dv[j])) << 32) | static_cast<uint32_t>(l)) : ~0ull;
-          wv[g * RS + kslot(l)] = av[j];
+        const int l = sm + (j0 + j) * S;
+        if (j0 + j < C) {
+          krow[kslot(l)] = (live && l < K)
+                               ? big_key(depth_bits(dv[j]), l) : kKeyPad;
+          wrow[kslot(l)] = av[j];
         }
       }
     }
@@ -806,38 +936,18 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       uint64_t* r = keys + (b >> (lk - kBlkLog)) * RS;
       const int base = (b & ((1 << (lk - kBlkLog)) - 1)) * kBlk;
       block_load(r, base, k);
-      sort_network<kBlk>(k);
+      sort_network<kBlk>(k, KeyMinMax());
       block_store(r, base, k);
     }
     lds_barrier();
     for (int ls = kBlkLog + 1; ls <= lk; ++ls) {  // merge size 2^ls
-      for (int lt = ls - 1; lt >= kBlkLog; --lt) {  // strides >= kBlk through LDS
-        const int str = 1 << lt;
-        const int pairs = G << (lk - 1);
-        for (int e0 = tid; e0 < pairs; e0 += 4 * NT) {  // 4 pairs per lane in flight
-          int ia[4], ib[4];
-          uint64_t x[4], y[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int e = e0 + j * NT;
-            const int g = e >> (lk - 1), c = e & ((1 << (lk - 1)) - 1);
-            const int lo = ((c >> lt) << (lt + 1)) | (c & (str - 1));
-            const int hi = (lt == ls - 1) ? (lo ^ ((1 << ls) - 1)) : (lo + str);
-            ia[j] = g * RS + kslot(lo);
-            ib[j] = g * RS + kslot(hi);
-            if (e < pairs) {
-              x[j] = keys[ia[j]];
-              y[j] = keys[ib[j]];
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (e0 + j * NT < pairs && y[j] < x[j]) {
-              keys[ia[j]] = y[j];
-              keys[ib[j]] = x[j];
-            }
-          }
-        }
+      for (int lt = ls - 1; lt >= kBlkLog;) {     // strides >= kBlk through LDS
+        const int m = lt - kBlkLog + 1 >= DFB_MAX_M ? DFB_MAX_M : lt - kBlkLog + 1;
+        if (m == 4) lds_stages<4>(keys, RS, G, lk, ls, lt, NT, tid);
+        else if (m == 3) lds_stages<3>(keys, RS, G, lk, ls, lt, NT, tid);
+        else if (m == 2) lds_stages<2>(keys, RS, G, lk, ls, lt, NT, tid);
+        else lds_stages<1>(keys, RS, G, lk, ls, lt, NT, tid);
+        lt -= m;
         lds_barrier();
       }
       for (int b = tid; b < nblk; b += NT) {     // strides 8..1 in registers
@@ -852,15 +962,11 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     }
     // 3. front-to-back walk: chunk products, exclusive scan over the S chunks.
     //    Rows past the unit's last pixel hold only padding keys: skipped.
-    const uint64_t* row = keys + gm * RS;
-    float* wrow = wv + gm * RS;
-    const int qme = q0 + gm;
-    const bool live = qme < a.work_px;
     const int i0 = sm * C, i1 = live ? ((i0 + C < K) ? i0 + C : K) : 0;
     float prod = 1.f;
 #pragma unroll 8
     for (int i = i0; i < i1; ++i) {
-      const int l = static_cast<int>(static_cast<uint32_t>(row[kslot(i)]));
+      const int l = key_layer(krow[kslot(i)]);
       prod = prod * (1.f - wrow[kslot(l)]);
     }
     red[tid].x = prod;
@@ -869,11 +975,9 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
     for (int s2 = 0; s2 < sm; ++s2) T = T * red[s2 * G + gm].x;
     lds_barrier();
     float Ap = 0.f;
-    bool in_me = false;
-    const int p_me = live ? unit_pixel(a, u, qme, in_me) : 0;
 #pragma unroll 4
     for (int i = i0; i < i1; ++i) {
-      const int l = static_cast<int>(static_cast<uint32_t>(row[kslot(i)]));
+      const int l = key_layer(krow[kslot(i)]);
       const float al = wrow[kslot(l)];
       wrow[kslot(l)] = T;
       Ap = fmaf(T, al, Ap);
@@ -882,29 +986,41 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         a.order[static_cast<size_t>(off + i) * P + p_me] = static_cast<uint16_t>(l);
     }
     lds_barrier();
-    // 4. colour in layer order (coalesced over the G pixels), 4 layers per step
+    // 4. colour sums in layer order: T_l * c_l
     float R = 0.f, Gc = 0.f, B = 0.f;
+    int sm4 = sm;
+    asm volatile("" : "+v"(sm4));  // addresses are recomputed here, not kept across the sort
     if (live) {
-      int l = sm;
+#pragma unroll
+      for (int j = 0; j < kBigC; ++j) {
+        const int l = sm4 + j * S;
+        if (j < C && l < K) {
+          const float w = wrow[kslot(l)];
+          R = fmaf(w, cr[j], R);
+          Gc = fmaf(w, cg[j], Gc);
+          B = fmaf(w, cb[j], B);
+        }
+      }
+      int l = sm4 + kBigC * S;
       for (; l + 3 * S < K; l += 4 * S) {
-        float w[4], cr[4], cg[4], cb[4];
+        float w[4], r4[4], g4[4], b4[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const FT* __restrict__ b = frag + loff[l + j * S];
+          const FT* __restrict__ b = frag + lofs[l + j * S];
           w[j] = wrow[kslot(l + j * S)];
-          cr[j] = ldf<FT>(b, p_me);
-          cg[j] = ldf<FT>(b, P + p_me);
-          cb[j] = ldf<FT>(b, 2 * P + p_me);
+          r4[j] = ldf<FT>(b, p_me);
+          g4[j] = ldf<FT>(b, P + p_me);
+          b4[j] = ldf<FT>(b, 2 * P + p_me);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          R = fmaf(w[j], cr[j], R);
-          Gc = fmaf(w[j], cg[j], Gc);
-          B = fmaf(w[j], cb[j], B);
+          R = fmaf(w[j], r4[j], R);
+          Gc = fmaf(w[j], g4[j], Gc);
+          B = fmaf(w[j], b4[j], B);
         }
       }
       for (; l < K; l += S) {
-        const FT* __restrict__ b = frag + loff[l];
+        const FT* __restrict__ b = frag + lofs[l];
         const float w = wrow[kslot(l)];
         R = fmaf(w, ldf<FT>(b, p_me), R);
         Gc = fmaf(w, ldf<FT>(b, P + p_me), Gc);
@@ -1177,7 +1293,8 @@ int big_lds_bytes(int max_layers) {
 size_t frame_lds_bytes(int kcap, int threads, int max_layers, int big_lds) {
   size_t small = static_cast<size_t>(kcap) * threads * sizeof(float);
   size_t big = 0;
-  if (max_layers > kcap) big = big_lds + static_cast<size_t>(threads) * 16 + 64 * 4;
+  // keys + alpha, the reduction rows [threads] float4, T_end [64], layer offsets [max_layers]
+  if (max_layers > kcap) big = big_lds + static_cast<size_t>(threads) * 16 + 64 * 4 + static_cast<size_t>(max_layers) * 8;
   return small > big ? small : big;
 }
 

@@ -23,8 +23,14 @@ __host__ __device__ __forceinline__ void compare_exchange(K& a, K& b) {
   b = hi;
 }
 
-template <int N, typename K>
-__host__ __device__ __forceinline__ void sort_network(K (&k)[N]) {
+template <typename K>
+struct CompareExchange {
+  __host__ __device__ __forceinline__ void operator()(K& a, K& b) const { compare_exchange(a, b); }
+};
+
+// The network with a given comparator ce(a, b): min to a, max to b.
+template <int N, typename K, typename CE>
+__host__ __device__ __forceinline__ void sort_network(K (&k)[N], CE ce) {
   constexpr int NP = pow2_ceil(N);
 #pragma unroll
   for (int size = 2; size <= NP; size <<= 1) {
@@ -34,10 +40,15 @@ __host__ __device__ __forceinline__ void sort_network(K (&k)[N]) {
       for (int c = 0; c < NP / 2; ++c) {
         const int lo = (c / stride) * (2 * stride) + (c % stride);
         const int hi = (stride == (size >> 1)) ? (lo ^ (size - 1)) : (lo + stride);
-        if (hi < N) compare_exchange(k[lo], k[hi]);
+        if (hi < N) ce(k[lo], k[hi]);
       }
     }
   }
+}
+
+template <int N, typename K>
+__host__ __device__ __forceinline__ void sort_network(K (&k)[N]) {
+  sort_network<N>(k, CompareExchange<K>());
 }
 
 }  // namespace dfb

@@ -154,8 +154,11 @@ def test_depth_ties_break_by_source(dfb, ranks):
     check_frame(dfb, workloads.Frame(64, 64, 64, 64, frag, f.layers, f.expected, None, "ties"))
 
 
-def test_special_depth_values(dfb):
-    f = workloads.uniform_frame(64, 64, 64, ranks=12, seed=12)
+@pytest.mark.parametrize("ranks", [12, 40, 300])
+def test_special_depth_values(dfb, ranks):
+    """NaN, signed zeros, infinities and denormals in the register sort and
+    in the LDS sort (ranks > 32)."""
+    f = workloads.uniform_frame(64, 64, 64, ranks=ranks, seed=12)
     frag = f.frag.copy()
     rng = np.random.default_rng(0)
     special = np.array([np.nan, 0.0, -0.0, np.inf, -np.inf, 1e-40, -1e-40, -1.0], dtype=np.float32)
