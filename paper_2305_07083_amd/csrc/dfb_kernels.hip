@@ -706,6 +706,9 @@ __device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* 
 // time: a lane loads the 2^m keys that m consecutive stages compare only
 // among themselves, runs the m stages in registers and writes the keys
 // back, one barrier per pass.  For Kp = 512 that is 6 LDS passes, not 15.
+// Positions K..Kp-1 hold the padding key, which no real key exceeds; as
+// every comparator is min-to-lower they keep it throughout, so blocks and
+// groups that lie wholly in the padding are skipped.
 //
 // The walk: the S lanes of a pixel take a product scan over S chunks of the
 // sorted row; then colour sums in layer order and a fixed-order reduction
@@ -783,7 +786,7 @@ __device__ __forceinline__ void block_half_clean(uint64_t (&k)[kBlk]) {
 // lower half, in increasing position order.
 template <int M>
 __device__ __forceinline__ void lds_stages(uint64_t* keys, int RS, int G, int lk, int ls, int lt,
-                                           int NT, int tid) {
+                                           int K, int NT, int tid) {
   constexpr int N = 1 << M, H = N / 2, U = M >= 3 ? 1 : (M == 2 ? 2 : 4);  // groups in flight
   const int lo = lt - M + 1, glog = lk - M, total = G << glog;
   const bool mirror = lt == ls - 1;
@@ -791,16 +794,18 @@ __device__ __forceinline__ void lds_stages(uint64_t* keys, int RS, int G, int lk
   for (int e0 = tid; e0 < total; e0 += U * NT) {
     uint64_t v[U][N];
     int ix[U][N];
+    bool act[U];
 #pragma unroll
     for (int w = 0; w < U; ++w) {
-      const int e = min(e0 + w * NT, total - 1);  // reads in range; writes guarded below
+      const int e = e0 + w * NT;
       const int g = e >> glog, c = e & ((1 << glog) - 1);
       const int b = ((c >> lo) << (lt + 1)) | (c & ((1 << lo) - 1));
+      act[w] = e < total && b < K;  // b is the group's lowest position
 #pragma unroll
       for (int r = 0; r < N; ++r) {
         const int pos = (mirror && r >= H) ? ((b + ((N - 1 - r) << lo)) ^ mask) : b + (r << lo);
         ix[w][r] = g * RS + kslot(pos);
-        v[w][r] = keys[ix[w][r]];
+        v[w][r] = act[w] ? keys[ix[w][r]] : kKeyPad;
       }
     }
 #pragma unroll
@@ -817,7 +822,7 @@ __device__ __forceinline__ void lds_stages(uint64_t* keys, int RS, int G, int lk
 #pragma unroll
         for (int r = 0; r < N; ++r)
           if ((r & (1 << k)) == 0) KeyMinMax()(v[w][r], v[w][r | (1 << k)]);
-      if (e0 + w * NT < total) {
+      if (act[w]) {
 #pragma unroll
         for (int r = 0; r < N; ++r) keys[ix[w][r]] = v[w][r];
       }
@@ -935,18 +940,20 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       uint64_t k[kBlk];
       uint64_t* r = keys + (b >> (lk - kBlkLog)) * RS;
       const int base = (b & ((1 << (lk - kBlkLog)) - 1)) * kBlk;
-      block_load(r, base, k);
-      sort_network<kBlk>(k, KeyMinMax());
-      block_store(r, base, k);
+      if (base < K) {
+        block_load(r, base, k);
+        sort_network<kBlk>(k, KeyMinMax());
+        block_store(r, base, k);
+      }
     }
     lds_barrier();
     for (int ls = kBlkLog + 1; ls <= lk; ++ls) {  // merge size 2^ls
       for (int lt = ls - 1; lt >= kBlkLog;) {     // strides >= kBlk through LDS
         const int m = lt - kBlkLog + 1 >= DFB_MAX_M ? DFB_MAX_M : lt - kBlkLog + 1;
-        if (m == 4) lds_stages<4>(keys, RS, G, lk, ls, lt, NT, tid);
-        else if (m == 3) lds_stages<3>(keys, RS, G, lk, ls, lt, NT, tid);
-        else if (m == 2) lds_stages<2>(keys, RS, G, lk, ls, lt, NT, tid);
-        else lds_stages<1>(keys, RS, G, lk, ls, lt, NT, tid);
+        if (m == 4) lds_stages<4>(keys, RS, G, lk, ls, lt, K, NT, tid);
+        else if (m == 3) lds_stages<3>(keys, RS, G, lk, ls, lt, K, NT, tid);
+        else if (m == 2) lds_stages<2>(keys, RS, G, lk, ls, lt, K, NT, tid);
+        else lds_stages<1>(keys, RS, G, lk, ls, lt, K, NT, tid);
         lt -= m;
         lds_barrier();
       }
@@ -954,9 +961,11 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         uint64_t k[kBlk];
         uint64_t* r = keys + (b >> (lk - kBlkLog)) * RS;
         const int base = (b & ((1 << (lk - kBlkLog)) - 1)) * kBlk;
-        block_load(r, base, k);
-        block_half_clean(k);
-        block_store(r, base, k);
+        if (base < K) {
+          block_load(r, base, k);
+          block_half_clean(k);
+          block_store(r, base, k);
+        }
       }
       lds_barrier();
     }
