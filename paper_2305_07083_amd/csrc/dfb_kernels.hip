@@ -102,25 +102,50 @@ __device__ __forceinline__ uint32_t half_depth_bits(uint16_t h) {
   return (h & 0x8000u) ? (~static_cast<uint32_t>(h) & 0xFFFFu) : (static_cast<uint32_t>(h) | 0x8000u);
 }
 
+// Keys of fp32 depths.  The sort order (ordered depth bits, then layer
+// index) is that of the 44-bit integer x = depth_bits << 12 | l (l < 4096).  Held as
+// the double 2^52 + x (bit pattern 0x433 << 52 | x), every key is a normal
+// double whose value orders like x, so a comparator is one v_min_f64 and one
+// v_max_f64 instead of two 64-bit integer compares and four selects.  The
+// layer index is the low 12 bits of the pattern.
+constexpr uint64_t kKeyBias = 0x4330000000000000ull;
+constexpr uint64_t kKeyPad = kKeyBias | 0x00000FFFFFFFFFFFull;  // not below any real key
+__device__ __forceinline__ uint64_t big_key(uint32_t dbits, int l) {
+  return kKeyBias | (static_cast<uint64_t>(dbits) << 12) | static_cast<uint32_t>(l);
+}
+__device__ __forceinline__ int key_layer(uint64_t k) { return static_cast<int>(k & 0xFFFu); }
+struct KeyMinMax {
+  __device__ __forceinline__ void operator()(uint64_t& a, uint64_t& b) const {
+    const double x = __builtin_bit_cast(double, a), y = __builtin_bit_cast(double, b);
+    double lo, hi;
+    asm("v_min_f64 %0, %1, %2" : "=v"(lo) : "v"(x), "v"(y));
+    asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(x), "v"(y));
+    a = __builtin_bit_cast(uint64_t, lo);
+    b = __builtin_bit_cast(uint64_t, hi);
+  }
+};
+
 // Sort keys of the register path: (ordered depth bits, layer index), as one
-// integer so that one compare orders by depth and breaks ties by index (the
-// layers of a tile are in source-id order).  fp32 depths need 64-bit keys;
-// fp16 depths and an index below 65536 fit 32 bits, which halves the
-// registers and the compare work of the sorting network.
+// number so that one comparison orders by depth and breaks ties by index (the
+// layers of a tile are in source-id order).  fp32 depths take the 64-bit
+// double-encoded key above; fp16 depths and an index below 65536 fit 32 bits
+// (v_min_u32 / v_max_u32), which also halves the registers.
 template <typename FT>
 struct SortKey;
 template <>
 struct SortKey<float> {
   using K = uint64_t;
-  static constexpr K kPad = ~0ull;
+  using CE = KeyMinMax;
+  static constexpr K kPad = kKeyPad;
   __device__ static __forceinline__ K make(const float* __restrict__ b, uint32_t i, int l) {
-    return (static_cast<uint64_t>(depth_bits(ldf<float>(b, i))) << 32) | static_cast<uint32_t>(l);
+    return big_key(depth_bits(ldf<float>(b, i)), l);
   }
-  __device__ static __forceinline__ int index(K k) { return static_cast<int>(static_cast<uint32_t>(k)); }
+  __device__ static __forceinline__ int index(K k) { return key_layer(k); }
 };
 template <>
 struct SortKey<_Float16> {
   using K = uint32_t;
+  using CE = CompareExchange<uint32_t>;
   static constexpr K kPad = ~0u;
   __device__ static __forceinline__ K make(const _Float16* __restrict__ b, uint32_t i, int l) {
 #if DFB_NT_LOADS
@@ -246,7 +271,7 @@ __device__ __forceinline__ float4 composite_px_upfront(float& Tout, const FrameA
 #pragma unroll
   for (int l = 0; l < KMAX; ++l)
     if (l < K) wl[l * NT] = alp[l];
-  sort_network<KMAX>(key);
+  sort_network<KMAX>(key, typename SK::CE());
   float T = 1.f, A = 0.f;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
@@ -297,7 +322,7 @@ __device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const Fram
       key[l] = SK::kPad;
     }
   }
-  sort_network<KMAX>(key);
+  sort_network<KMAX>(key, typename SK::CE());
   float T = 1.f, A = 0.f;
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) {
@@ -728,28 +753,6 @@ constexpr int kBigC = DFB_BIG_C;              // layers per lane whose colours a
 
 __device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
 
-// Keys of this path.  The sort order (ordered depth bits, then layer index)
-// is that of the 44-bit integer x = depth_bits << 12 | l (l < 4096).  Held as
-// the double 2^52 + x (bit pattern 0x433 << 52 | x), every key is a normal
-// double whose value orders like x, so a comparator is one v_min_f64 and one
-// v_max_f64 instead of two 64-bit integer compares and four selects.  The
-// layer index is the low 12 bits of the pattern.
-constexpr uint64_t kKeyBias = 0x4330000000000000ull;
-constexpr uint64_t kKeyPad = kKeyBias | 0x00000FFFFFFFFFFFull;  // not below any real key
-__device__ __forceinline__ uint64_t big_key(uint32_t dbits, int l) {
-  return kKeyBias | (static_cast<uint64_t>(dbits) << 12) | static_cast<uint32_t>(l);
-}
-__device__ __forceinline__ int key_layer(uint64_t k) { return static_cast<int>(k & 0xFFFu); }
-struct KeyMinMax {
-  __device__ __forceinline__ void operator()(uint64_t& a, uint64_t& b) const {
-    const double x = __builtin_bit_cast(double, a), y = __builtin_bit_cast(double, b);
-    double lo, hi;
-    asm("v_min_f64 %0, %1, %2" : "=v"(lo) : "v"(x), "v"(y));
-    asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(x), "v"(y));
-    a = __builtin_bit_cast(uint64_t, lo);
-    b = __builtin_bit_cast(uint64_t, hi);
-  }
-};
 
 // a block is read as runs of 16 keys, none of which straddles a pad slot
 __device__ __forceinline__ void block_load(const uint64_t* r, int base, uint64_t (&k)[kBlk]) {
