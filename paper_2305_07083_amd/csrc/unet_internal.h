@@ -38,7 +38,8 @@ hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, 
                          const Shape& s, hipStream_t st);
 // dw[9][ci][co] = sum_p x[p + tap] * bf16(dy[p] * (y[p] > 0)) for ci < ci_out
 // (ci_out < x.c when x carries zero padding channels); db[co] = sum_p dy*(y>0).
-// `partial` needs conv3x3_wgrad_scratch floats.
+// `partial` needs conv3x3_wgrad_scratch floats; dy and y row strides and
+// offsets are multiples of 4 elements.
 hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, float* db,
                          float* partial, const Shape& s, hipStream_t st, int ci_out);
 size_t conv3x3_wgrad_scratch(int ci, int co, const Shape& s);

@@ -6,12 +6,12 @@
 //
 // The three convolutions are one GEMM shape, D[M][N] += A[M][K] B[K][N],
 // read from LDS in 32-wide K slices:
-//   forward  M = pixels, N = c_out, K = (tap, c_in)   A = x[p + tap], B = W
+//   forward  M = c_out,  N = pixels, K = (tap, c_in)   A = W, B = x[p + tap]
 //   dgrad    M = pixels, N = c_in,  K = (tap, c_out)  A = dy[p - tap], B = W^T
 //   wgrad    M = c_in,   N = c_out, K = pixels (per tap, split over chunks)
-// A workgroup is 4 waves; wave w owns rows 16w..16w+15 of a 64-row tile and
-// every 16-column block of N, one v_mfma_f32_16x16x32_bf16 per block per K
-// slice.  Operand layout (checked on the device): lane l holds k =
+// A workgroup is 4 waves, one v_mfma_f32_16x16x32_bf16 per 16x16 block per K
+// slice.  In dgrad and wgrad wave w owns rows 16w..16w+15 of a 64-row tile
+// and every 16-column block of N; the forward kernel's tiling is below.  Operand layout (checked on the device): lane l holds k =
 // (l/16)*8 .. +7 of row/column l%16; the result element r of lane l is row
 // (l/16)*4 + r, column l%16.
 #include <hip/hip_runtime.h>
@@ -72,7 +72,8 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // flight during this tap's MFMAs (double-buffered in LDS where that does not
 // cost resident workgroups).  Wave w owns tile rows
 // w*TH/4 .. +TH/4-1 (TH/2 row blocks of 16 pixels) and every 16-column block
-// of BN.  K runs tap-major, then 32-channel slices.  Epilogue: bias, ReLU, bf16 into LDS, 16-byte
+// of BN; the MFMA takes the weights as its row operand, so each accumulator
+// holds 4 channels of one pixel.  K runs tap-major, then 32-channel slices.  Epilogue: bias, ReLU, bf16 into LDS, 16-byte
 // coalesced stores, and optionally the 2x2 average pool of the tile (the
 // tile origin and TH are even).
 constexpr int kTW = 32;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __
           const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
           const bf16x8 a = lds_frag(halo + ((row + dr) * C::HW + col + dc) * C::LDR + ks * 32 + (lane >> 4) * 8);
 #pragma unroll
-          for (int j = 0; j < NB; ++j) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf[j], acc[m][j], 0, 0, 0);
+          for (int j = 0; j < NB; ++j) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j], a, acc[m][j], 0, 0, 0);
         }
       }
       if (tap + 1 < 9) {
@@ -196,21 +197,26 @@ __global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __
       }
       __syncthreads();
     }
-    // epilogue: bias + ReLU + bf16 into the staging tile (the halo is no longer read)
+    // epilogue: bias + ReLU + bf16 into the staging tile (the halo is no
+    // longer read); a lane holds 4 consecutive channels of one pixel, written
+    // as one 8-byte store
     uint16_t* ot = smem;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int ch = j * 16 + (lane & 15);
-      const float bb = bias[ch];
+      const int ch = j * 16 + (lane >> 4) * 4;
+      float bb[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bb[r] = bias[ch + r];
 #pragma unroll
       for (int m = 0; m < MB; ++m) {
-        const int row = wave * WR + m / 2;
+        const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
+        uint32_t h[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int col = (m & 1) * 16 + (lane >> 4) * 4 + r;
-          const float v = acc[m][j][r] + bb;
-          ot[(row * kTW + col) * C::LDO + ch] = to_bf16(v > 0.f ? v : 0.f);
+          const float v = acc[m][j][r] + bb[r];
+          h[r] = to_bf16(v > 0.f ? v : 0.f);
         }
+        *reinterpret_cast<uint2*>(ot + (row * kTW + col) * C::LDO + ch) = uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
       }
     }
     __syncthreads();
@@ -351,27 +357,54 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, MapF dy, Map y, float
   const int a8 = (tid & 7) * 8;            // 8 c_in values
   constexpr int BPER = BN / 8;             // c_out values per thread
   const int b0 = (tid & 7) * BPER;
-  for (int k0 = 0; k0 < kWgradChunk; k0 += 32) {
+  // the next slice's x, dy and y are loaded into registers while this
+  // slice's MFMAs run
+  uint4 v;
+  float dv[BPER];
+  uint16_t yv[BPER];
+  auto load = [&](int k0) {
     const long long p = p_begin + k0 + px;
     const Pix q = pixel_of(p, s);
     bool in;
     const long long src = shifted(q, dr, dc, s, in);
-    uint4 v = {0u, 0u, 0u, 0u};
+    v = uint4{0u, 0u, 0u, 0u};
     if (in && ci0 + a8 < x.c) v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + ci0 + a8);
+#pragma unroll
+    for (int i = 0; i < BPER; ++i) {
+      dv[i] = 0.f;
+      yv[i] = 0;
+    }
+    if (q.ok) {  // 16-byte loads (dy rows and offsets are multiples of 4, y's of 8)
+      const float4* d4 = reinterpret_cast<const float4*>(dy.p + p * dy.ld + dy.off + b0);
+#pragma unroll
+      for (int i = 0; i < BPER / 4; ++i) {
+        const float4 t = d4[i];
+        dv[4 * i] = t.x;
+        dv[4 * i + 1] = t.y;
+        dv[4 * i + 2] = t.z;
+        dv[4 * i + 3] = t.w;
+      }
+      const uint16_t* yp = y.p + p * y.ld + y.off + b0;
+#pragma unroll
+      for (int i = 0; i < BPER / 4; ++i) {
+        const uint2 t = *reinterpret_cast<const uint2*>(yp + 4 * i);
+        yv[4 * i] = static_cast<uint16_t>(t.x);
+        yv[4 * i + 1] = static_cast<uint16_t>(t.x >> 16);
+        yv[4 * i + 2] = static_cast<uint16_t>(t.y);
+        yv[4 * i + 3] = static_cast<uint16_t>(t.y >> 16);
+      }
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < kWgradChunk; k0 += 32) {
     const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < 8; ++i) As[(a8 + i) * LDK + px] = static_cast<uint16_t>(vw[i >> 1] >> ((i & 1) * 16));
 #pragma unroll
-    for (int i = 0; i < BPER; ++i) {
-      float g = 0.f;
-      if (q.ok) {
-        const long long o = p * dy.ld + dy.off + b0 + i;
-        const uint16_t yh = y.p[p * y.ld + y.off + b0 + i];
-        g = from_bf16(yh) > 0.f ? dy.p[o] : 0.f;
-      }
-      Bs[(b0 + i) * LDK + px] = to_bf16(g);
-    }
+    for (int i = 0; i < BPER; ++i) Bs[(b0 + i) * LDK + px] = to_bf16(from_bf16(yv[i]) > 0.f ? dv[i] : 0.f);
     __syncthreads();
+    const bool more = k0 + 32 < kWgradChunk && p_begin + k0 + 32 < P;
+    if (more) load(k0 + 32);
     const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
 #pragma unroll
     for (int j = 0; j < BN / 16; ++j) {
@@ -379,7 +412,7 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, MapF dy, Map y, float
       acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
     }
     __syncthreads();
-    if (p_begin + k0 + 32 >= P) break;
+    if (!more) break;
   }
   const int ci_n = x.c;
 #pragma unroll
@@ -749,6 +782,7 @@ hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, 
                          const Shape& s, hipStream_t st, int ci_out) {
   const int chunks = static_cast<int>((s.pixels() + kWgradChunk - 1) / kWgradChunk);
   if (x.c % 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
+  if (dy.ld % 4 || dy.off % 4 || y.ld % 4 || y.off % 4) return hipErrorInvalidValue;
   dim3 grid(chunks, 9, (x.c + BM - 1) / BM);
   switch (dy.c) {
     case 32: conv_wgrad_k<32><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
