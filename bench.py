@@ -80,10 +80,10 @@ def measured_traffic(workload, accumulate):
     return (fetch + write) * 1024.0
 
 
-def measured_op_traffic(op):
-    """HBM bytes per launch of the list / average operation from the committed
-    counter summary of the tile-op legs (current kernel source only)."""
-    path = os.path.join(ROOT, "profiles", "frame_kernel_tile_ops_2048_counters.txt")
+def measured_leg_traffic(profile, leg):
+    """HBM bytes per launch of one leg's kernel (``leg``_fetch / _write keys)
+    from a committed counter summary (current kernel source only)."""
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -91,11 +91,17 @@ def measured_op_traffic(op):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash() or op + "_fetch_kib_per_dispatch" not in kv:
+    if kv.get("kernel_source_hash") != kernel_source_hash() or leg + "_fetch_kib_per_dispatch" not in kv:
         return None
-    fetch = float(kv[op + "_fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
-    write = float(kv[op + "_write_kib_per_dispatch"]) * float(kv["write_scale"])
+    fetch = float(kv[leg + "_fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+    write = float(kv[leg + "_write_kib_per_dispatch"]) * float(kv["write_scale"])
     return (fetch + write) * 1024.0
+
+
+def measured_op_traffic(op):
+    """The tile-op legs (list, average, and the per-pixel sort of the same
+    brick frame)."""
+    return measured_leg_traffic("frame_kernel_tile_ops_2048_counters.txt", op)
 
 
 BF16_PEAK_TFLOPS = 2500.0
@@ -270,7 +276,7 @@ def tile_ops_leg(dfb, torch, steps=30, warmup=5, copies=4):
                      "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
                      "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                   "frac": gbps / HBM_PEAK_GBPS,
-                                  "traffic": measured_op_traffic(name) if name in ("list", "average") else None,
+                                  "traffic": measured_op_traffic(name),
                                   "algorithmic_bytes_per_launch": alg}}
     return out
 
@@ -322,7 +328,8 @@ def other_workloads_leg(dfb, torch, steps=10, warmup=3):
                      "fragments_per_s": f.n_fragments / (kms * 1e-3),
                      "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
                      "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                                  "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
+                                  "frac": gbps / HBM_PEAK_GBPS,
+                                  "traffic": measured_leg_traffic("frame_kernel_other_workloads_counters.txt", name),
                                   "algorithmic_bytes_per_launch": alg}}
     return out
 

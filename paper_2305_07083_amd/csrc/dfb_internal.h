@@ -49,6 +49,7 @@ struct FrameArgs {
   uint32_t* queue;             // kQueues x kSlots counters, queues kQueueStride apart
   int32_t slot, clear_slot;    // this frame's counter slot; the slot it clears
   int32_t n_queues;            // counters in use: min(kQueues, grid)
+  int32_t queue_block;         // consecutive work-list positions per counter block (units per tile)
   int32_t n_work;
   int32_t width, height, tiles_x, n_tiles;
   int32_t tile_w, tile_h, P;

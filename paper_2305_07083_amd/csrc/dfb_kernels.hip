@@ -1072,28 +1072,42 @@ __device__ __forceinline__ float variance_of_mean(float sum, int inside_px, int 
                 static_cast<float>(n - 1));
 }
 
-// Work queue.  Counter s (of S = n_queues) holds the work-list positions
-// congruent to s, in order; workgroup b starts on counter b mod S, and its
-// first unit there is its rank r = b / S among those workgroups (no
-// atomic).  Each ticket c of a counter names its unit g + c, g being the
-// number of workgroups that start on it.  Lane 0 of wave 0 takes the next
-// ticket at the start of a unit and the result is read at its end, so the
-// atomic's latency hides behind the unit's work.  A drained counter sends
-// the workgroup on to the next one (s + 1, s + 2, ... mod S); a coherent
-// read skips counters that are already drained without an atomic.
+// Work queue.  The work list is cut into blocks of B = queue_block
+// consecutive positions (the units of one tile); counter s (of S = n_queues)
+// holds the blocks congruent to s, in order.  Workgroup b starts on counter
+// b mod S, and its first unit there is its rank r = b / S among those
+// workgroups (no atomic).  Each ticket c of a counter names its unit g + c,
+// g being the number of workgroups that start on it.  Lane 0 of wave 0
+// takes the next ticket at the start of a unit and the result is read at
+// its end, so the atomic's latency hides behind the unit's work.  A drained
+// counter sends the workgroup on to the next one (s + 1, s + 2, ... mod S);
+// a coherent read skips counters that are already drained without an
+// atomic.  Workgroups are dealt to the 8 XCDs in turn and S is a multiple of
+// 8 on every grid of 8 workgroups or more, so the units of one tile run at
+// about the same time under one XCD's L2: unit rows that share cache lines
+// (fp16 planes, units narrower than a line) are fetched from memory once.
 struct Queue {
   uint32_t* ctr;
-  int s, g, n;
+  int s, g, n;  // counter, workgroups starting on it, units it holds
 };
 
 __device__ __forceinline__ Queue queue_of(const FrameArgs& a, int s) {
-  const int S = a.n_queues;
+  const int S = a.n_queues, B = a.queue_block;
+  const int nb = (a.n_work + B - 1) / B;  // blocks
+  const int cnt = s < nb ? (nb - s + S - 1) / S : 0;
   Queue q;
   q.s = s;
   q.g = (static_cast<int>(gridDim.x) - s + S - 1) / S;
-  q.n = (a.n_work - s + S - 1) / S;
+  q.n = cnt * B;
+  if (cnt > 0 && s + (cnt - 1) * S == nb - 1 && a.n_work % B) q.n -= B - a.n_work % B;  // partial last block
   q.ctr = a.queue + static_cast<size_t>(s) * kQueueStride + a.slot;
   return q;
+}
+
+// Work-list position of the j-th unit of a counter (j < q.n).
+__device__ __forceinline__ int unit_at(const FrameArgs& a, const Queue& q, int j) {
+  const int B = a.queue_block;
+  return ((j / B) * a.n_queues + q.s) * B + j % B;
 }
 
 __device__ __forceinline__ uint32_t take_ticket(const Queue& q) {
@@ -1104,7 +1118,7 @@ __device__ __forceinline__ uint32_t take_ticket(const Queue& q) {
 
 __device__ __forceinline__ int ticket_to_unit(const FrameArgs& a, const Queue& q, uint32_t v) {
   const int64_t j = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(v)) + q.g;
-  return j < q.n ? static_cast<int>(j) * a.n_queues + q.s : a.n_work;
+  return j < q.n ? unit_at(a, q, static_cast<int>(j)) : a.n_work;
 }
 
 // Whether a counter may still hand out a unit (never wrong the other way:
@@ -1152,7 +1166,7 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
   Queue q = queue_of(a, home);
   int drained = 0;  // counters this workgroup has found empty
   const int r = static_cast<int>(blockIdx.x) / a.n_queues;
-  int it = r < q.n ? r * a.n_queues + home : a.n_work;  // the first unit is static
+  int it = r < q.n ? unit_at(a, q, r) : a.n_work;  // the first unit is static
   while (it < a.n_work) {
     // the next unit's ticket is taken now and read after this unit's work
     const uint32_t next = wave0 ? take_ticket(q) : 0u;

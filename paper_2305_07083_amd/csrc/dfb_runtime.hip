@@ -342,6 +342,7 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   a.slot = static_cast<int32_t>(h->frame_seq % dfb::kSlots);
   a.clear_slot = static_cast<int32_t>((h->frame_seq + dfb::kSlots / 2) % dfb::kSlots);
   a.n_queues = 1;  // set by launch_frame once the grid is known
+  a.queue_block = h->subs_per_tile;
   a.n_work = h->n_work;
   a.width = h->cfg.width;
   a.height = h->cfg.height;
