@@ -33,15 +33,19 @@ struct Shape {
 // also pool = bf16(2x2 average of y) at s/2.
 hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y,
                        const Shape& s, hipStream_t st, bool up = false, const Map* pool = nullptr);
-// dx = conv3x3^T(bf16(dy * (y > 0))) (overwrites dx).
-hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, const MapF& dx,
-                         const Shape& s, hipStream_t st);
-// dw[9][ci][co] = sum_p x[p + tap] * bf16(dy[p] * (y[p] > 0)) for ci < ci_out
-// (ci_out < x.c when x carries zero padding channels); db[co] = sum_p dy*(y>0).
-// `partial` needs conv3x3_wgrad_scratch floats; dy and y row strides and
-// offsets are multiples of 4 elements.
-hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, float* db,
-                         float* partial, const Shape& s, hipStream_t st, int ci_out);
+// g = bf16(dy * (y > 0)), the ReLU-gated output gradient (g.c == dy.c, a
+// multiple of 8 dividing 2048; rows and offsets of y and g multiples of 8),
+// and db[c] = sum_p dy*(y>0) in f32.  `partial` needs conv3x3_wgrad_scratch
+// floats.
+hipError_t conv3x3_gate(const MapF& dy, const Map& y, const Map& g, float* db, float* partial, const Shape& s,
+                        hipStream_t st);
+// dx = conv3x3^T(g) (overwrites dx).
+hipError_t conv3x3_dgrad(const Map& g, const uint16_t* w_dgrad, const MapF& dx, const Shape& s, hipStream_t st);
+// dw[9][ci][co] = sum_p x[p + tap] * g[p] for ci < ci_out (ci_out < x.c when
+// x carries zero padding channels).  `partial` needs conv3x3_wgrad_scratch
+// floats; g's row stride and offset are multiples of 4 elements.
+hipError_t conv3x3_wgrad(const Map& x, const Map& g, float* dw, float* partial, const Shape& s, hipStream_t st,
+                         int ci_out);
 size_t conv3x3_wgrad_scratch(int ci, int co, const Shape& s);
 
 hipError_t avgpool2(const Map& x, const Map& y, const Shape& s_in, hipStream_t st);

@@ -266,62 +266,56 @@ __global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __
 }
 
 // ------------------------------------------------------------- dgrad
-// A[p][(tap, co)] = bf16(dy[p - tap][co] * (y[p - tap][co] > 0)); B = W[tap][ci][co].
+// A[p][(tap, co)] = g[p - tap][co], g = bf16(dy * (y > 0)) (gate_k); B =
+// W[tap][ci][co].  The next (tap, slice)'s A chunk and weights are loaded
+// into registers while this slice's MFMAs run.
 template <int BN>
-__global__ void __launch_bounds__(256) conv_dgrad_k(MapF dy, Map y, const uint16_t* __restrict__ w,
-                                                    MapF dx, Shape s) {
+__global__ void __launch_bounds__(256) conv_dgrad_k(Map g, const uint16_t* __restrict__ w, MapF dx, Shape s) {
   __shared__ __align__(16) uint16_t As[BM * LDK];
   __shared__ __align__(16) uint16_t Bs[BN * LDK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long m0 = static_cast<long long>(blockIdx.x) * BM;
   const int ap = tid >> 2, ach = (tid & 3) * 8;
   const Pix q = pixel_of(m0 + ap, s);
-  const int co_n = dy.c;
+  const int co_n = g.c;
   f32x4 acc[BN / 16];
 #pragma unroll
   for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int nk = (co_n + 31) / 32;
-  for (int tap = 0; tap < 9; ++tap) {
+  constexpr int WPT = (BN * 4 + 255) / 256;  // 16-byte weight chunks per thread and slice
+  uint4 av, wv[WPT];
+  auto load = [&](int tap, int kc) {
     bool in;
     const long long src = shifted(q, 1 - tap / 3, 1 - tap % 3, s, in);
-    for (int kc = 0; kc < nk; ++kc) {
-      const int c0 = kc * 32 + ach;
-      uint16_t hv[8];
+    const int c0 = kc * 32 + ach;
+    av = uint4{0u, 0u, 0u, 0u};
+    if (in && c0 < co_n) av = *reinterpret_cast<const uint4*>(g.p + src * g.ld + g.off + c0);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) hv[i] = 0;
-      if (in && c0 < co_n) {
-        const float4 g0 = *reinterpret_cast<const float4*>(dy.p + src * dy.ld + dy.off + c0);
-        const float4 g1 = *reinterpret_cast<const float4*>(dy.p + src * dy.ld + dy.off + c0 + 4);
-        const uint4 mk = *reinterpret_cast<const uint4*>(y.p + src * y.ld + y.off + c0);
-        const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
-        const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint16_t yh = static_cast<uint16_t>(mw[i >> 1] >> ((i & 1) * 16));
-          hv[i] = to_bf16(from_bf16(yh) > 0.f ? gv[i] : 0.f);
-        }
-      }
-      uint4 pk;
-      pk.x = hv[0] | (static_cast<uint32_t>(hv[1]) << 16);
-      pk.y = hv[2] | (static_cast<uint32_t>(hv[3]) << 16);
-      pk.z = hv[4] | (static_cast<uint32_t>(hv[5]) << 16);
-      pk.w = hv[6] | (static_cast<uint32_t>(hv[7]) << 16);
-      *reinterpret_cast<uint4*>(As + ap * LDK + ach) = pk;
-      for (int e = tid; e < BN * 4; e += 256) {
-        const int ci = e >> 2, k0 = kc * 32 + (e & 3) * 8;
-        uint4 wv = {0u, 0u, 0u, 0u};
-        if (k0 < co_n) wv = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + ci) * co_n + k0);
-        *reinterpret_cast<uint4*>(Bs + ci * LDK + (e & 3) * 8) = wv;
-      }
-      __syncthreads();
-      const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
-#pragma unroll
-      for (int j = 0; j < BN / 16; ++j) {
-        const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-      }
-      __syncthreads();
+    for (int i = 0; i < WPT; ++i) {
+      const int e = tid + i * 256;
+      const int ci = e >> 2, k0 = kc * 32 + (e & 3) * 8;
+      wv[i] = uint4{0u, 0u, 0u, 0u};
+      if (e < BN * 4 && k0 < co_n)
+        wv[i] = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + ci) * co_n + k0);
     }
+  };
+  load(0, 0);
+  for (int it = 0; it < 9 * nk; ++it) {
+    *reinterpret_cast<uint4*>(As + ap * LDK + ach) = av;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      const int e = tid + i * 256;
+      if (e < BN * 4) *reinterpret_cast<uint4*>(Bs + (e >> 2) * LDK + (e & 3) * 8) = wv[i];
+    }
+    __syncthreads();
+    if (it + 1 < 9 * nk) load((it + 1) / nk, (it + 1) % nk);
+    const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+#pragma unroll
+    for (int j = 0; j < BN / 16; ++j) {
+      const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+    }
+    __syncthreads();
   }
   const long long P = s.pixels();
 #pragma unroll
@@ -335,16 +329,61 @@ __global__ void __launch_bounds__(256) conv_dgrad_k(MapF dy, Map y, const uint16
   }
 }
 
+// ------------------------------------------------------------- gate
+// g[p][c] = bf16(dy[p][c] * (y[p][c] > 0)), the ReLU-gated output gradient
+// that the data and weight gradients read (8 channels per thread); and the
+// bias-gradient partial of the workgroup's pixels, partial[block][c] = the
+// sum over its pixels, in pixel order, of dy * (y > 0) in f32.
+__global__ void __launch_bounds__(256) gate_k(MapF dy, Map y, Map g, float* __restrict__ partial, Shape s) {
+  __shared__ float red[256 * 9];  // [thread][8], one pad slot
+  const int t = threadIdx.x, cb = dy.c / 8;
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + t;
+  float gf[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) gf[i] = 0.f;
+  if (e < s.pixels() * cb) {
+    const long long p = e / cb;
+    const int c0 = static_cast<int>(e - p * cb) * 8;
+    const float4 g0 = *reinterpret_cast<const float4*>(dy.p + p * dy.ld + dy.off + c0);
+    const float4 g1 = *reinterpret_cast<const float4*>(dy.p + p * dy.ld + dy.off + c0 + 4);
+    const uint4 mk = *reinterpret_cast<const uint4*>(y.p + p * y.ld + y.off + c0);
+    const float gv[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+    const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+    uint32_t h[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint16_t yh = static_cast<uint16_t>(mw[i >> 1] >> ((i & 1) * 16));
+      gf[i] = from_bf16(yh) > 0.f ? gv[i] : 0.f;
+      h[i] = to_bf16(gf[i]);
+    }
+    *reinterpret_cast<uint4*>(g.p + p * g.ld + g.off + c0) =
+        uint4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) red[t * 9 + i] = gf[i];
+  __syncthreads();
+  if (t < dy.c) {  // channel t: thread (pixel k, chunk t/8) of the block holds it at slot t%8
+    float sum = 0.f;
+    for (int k = 0; k < 256 / cb; ++k) sum += red[(k * cb + t / 8) * 9 + (t & 7)];
+    partial[static_cast<size_t>(blockIdx.x) * dy.c + t] = sum;
+  }
+}
+
 // ------------------------------------------------------------- wgrad
 // Per tap and 64-wide c_in tile, over one chunk of pixels:
-// partial[chunk][tap][ci][co] = sum_p x[p + tap][ci] * bf16(dy[p][co] * (y > 0)).
+// partial[chunk][tap][ci][co] = sum_p x[p + tap][ci] * g[p][co], g = bf16(dy * (y > 0)).
 constexpr int kWgradChunk = 2048;
 
+// A stage is KS slices of 32 pixels (one barrier pair per stage); the
+// next stage's x and g are loaded into registers while this stage's MFMAs
+// run.  Slices past the image end stage zeros.
+constexpr int kWgradKS = 4;
+constexpr int LDW = 32 * kWgradKS + 8;  // LDS row: the stage's pixels + 8 padding
+
 template <int BN>
-__global__ void __launch_bounds__(256) conv_wgrad_k(Map x, MapF dy, Map y, float* __restrict__ partial,
-                                                    Shape s) {
-  __shared__ __align__(16) uint16_t As[BM * LDK];   // [ci][px]
-  __shared__ __align__(16) uint16_t Bs[BN * LDK];   // [co][px]
+__global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restrict__ partial, Shape s) {
+  __shared__ __align__(16) uint16_t As[BM * LDW];   // [ci][px]
+  __shared__ __align__(16) uint16_t Bs[BN * LDW];   // [co][px]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int chunk = blockIdx.x, tap = blockIdx.y, ci0 = blockIdx.z * BM;
   const int dr = tap / 3 - 1, dc = tap % 3 - 1;
@@ -353,63 +392,58 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, MapF dy, Map y, float
   f32x4 acc[BN / 16];
 #pragma unroll
   for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int px = tid >> 3;                 // 0..31: pixel of the K slice this thread stages
+  const int px = tid >> 3;                 // 0..31: pixel of each slice this thread stages
   const int a8 = (tid & 7) * 8;            // 8 c_in values
   constexpr int BPER = BN / 8;             // c_out values per thread
   const int b0 = (tid & 7) * BPER;
-  // the next slice's x, dy and y are loaded into registers while this
-  // slice's MFMAs run
-  uint4 v;
-  float dv[BPER];
-  uint16_t yv[BPER];
+  uint4 v[kWgradKS];
+  uint32_t gw[kWgradKS][BPER / 2];
   auto load = [&](int k0) {
-    const long long p = p_begin + k0 + px;
-    const Pix q = pixel_of(p, s);
-    bool in;
-    const long long src = shifted(q, dr, dc, s, in);
-    v = uint4{0u, 0u, 0u, 0u};
-    if (in && ci0 + a8 < x.c) v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + ci0 + a8);
 #pragma unroll
-    for (int i = 0; i < BPER; ++i) {
-      dv[i] = 0.f;
-      yv[i] = 0;
-    }
-    if (q.ok) {  // 16-byte loads (dy rows and offsets are multiples of 4, y's of 8)
-      const float4* d4 = reinterpret_cast<const float4*>(dy.p + p * dy.ld + dy.off + b0);
+    for (int sl = 0; sl < kWgradKS; ++sl) {
+      const long long p = p_begin + k0 + sl * 32 + px;
+      const Pix q = pixel_of(p, s);
+      bool in;
+      const long long src = shifted(q, dr, dc, s, in);
+      v[sl] = uint4{0u, 0u, 0u, 0u};
+      if (in && ci0 + a8 < x.c) v[sl] = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + ci0 + a8);
 #pragma unroll
-      for (int i = 0; i < BPER / 4; ++i) {
-        const float4 t = d4[i];
-        dv[4 * i] = t.x;
-        dv[4 * i + 1] = t.y;
-        dv[4 * i + 2] = t.z;
-        dv[4 * i + 3] = t.w;
-      }
-      const uint16_t* yp = y.p + p * y.ld + y.off + b0;
+      for (int i = 0; i < BPER / 2; ++i) gw[sl][i] = 0u;
+      if (q.ok) {  // 8-byte loads (g's row stride and offset are multiples of 4)
+        const uint16_t* gp = g.p + p * g.ld + g.off + b0;
 #pragma unroll
-      for (int i = 0; i < BPER / 4; ++i) {
-        const uint2 t = *reinterpret_cast<const uint2*>(yp + 4 * i);
-        yv[4 * i] = static_cast<uint16_t>(t.x);
-        yv[4 * i + 1] = static_cast<uint16_t>(t.x >> 16);
-        yv[4 * i + 2] = static_cast<uint16_t>(t.y);
-        yv[4 * i + 3] = static_cast<uint16_t>(t.y >> 16);
+        for (int i = 0; i < BPER / 4; ++i) {
+          const uint2 t = *reinterpret_cast<const uint2*>(gp + 4 * i);
+          gw[sl][2 * i] = t.x;
+          gw[sl][2 * i + 1] = t.y;
+        }
       }
     }
   };
   load(0);
-  for (int k0 = 0; k0 < kWgradChunk; k0 += 32) {
-    const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+  for (int k0 = 0; k0 < kWgradChunk; k0 += 32 * kWgradKS) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) As[(a8 + i) * LDK + px] = static_cast<uint16_t>(vw[i >> 1] >> ((i & 1) * 16));
+    for (int sl = 0; sl < kWgradKS; ++sl) {
+      const uint32_t vw[4] = {v[sl].x, v[sl].y, v[sl].z, v[sl].w};
 #pragma unroll
-    for (int i = 0; i < BPER; ++i) Bs[(b0 + i) * LDK + px] = to_bf16(from_bf16(yv[i]) > 0.f ? dv[i] : 0.f);
+      for (int i = 0; i < 8; ++i)
+        As[(a8 + i) * LDW + sl * 32 + px] = static_cast<uint16_t>(vw[i >> 1] >> ((i & 1) * 16));
+#pragma unroll
+      for (int i = 0; i < BPER; ++i)
+        Bs[(b0 + i) * LDW + sl * 32 + px] = static_cast<uint16_t>(gw[sl][i >> 1] >> ((i & 1) * 16));
+    }
     __syncthreads();
-    const bool more = k0 + 32 < kWgradChunk && p_begin + k0 + 32 < P;
-    if (more) load(k0 + 32);
-    const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+    const int k1 = k0 + 32 * kWgradKS;
+    const bool more = k1 < kWgradChunk && p_begin + k1 < P;
+    if (more) load(k1);
 #pragma unroll
-    for (int j = 0; j < BN / 16; ++j) {
-      const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+    for (int sl = 0; sl < kWgradKS; ++sl) {
+      const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDW + sl * 32 + (lane >> 4) * 8);
+#pragma unroll
+      for (int j = 0; j < BN / 16; ++j) {
+        const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDW + sl * 32 + (lane >> 4) * 8);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+      }
     }
     __syncthreads();
     if (!more) break;
@@ -441,37 +475,8 @@ __global__ void __launch_bounds__(256) wgrad_reduce_k(const float* __restrict__ 
   dw[e] = sum;
 }
 
-// db[co] partials per chunk of kBiasChunk pixels: thread (co, g) sums the
-// chunk's pixels g, g + G, ... in order (G = 256 / c_out groups, lanes of a
-// wave on consecutive channels of one pixel), then the groups are added in
-// group order: deterministic.
-constexpr int kBiasChunk = 256;
-__global__ void __launch_bounds__(256) bias_partial_k(MapF dy, Map y, float* __restrict__ partial, Shape s) {
-  __shared__ float red[256];
-  const int C = dy.c, G = 256 / C;
-  const int t = threadIdx.x, co = t % C, g = t / C;
-  const long long P = s.pixels();
-  const long long p0 = static_cast<long long>(blockIdx.x) * kBiasChunk;
-  const long long p1 = p0 + kBiasChunk < P ? p0 + kBiasChunk : P;
-  float sum = 0.f;
-  if (g < G) {
-    for (long long p = p0 + g; p < p1; p += G) {
-      const uint16_t yh = y.p[p * y.ld + y.off + co];
-      sum += from_bf16(yh) > 0.f ? dy.p[p * dy.ld + dy.off + co] : 0.f;
-    }
-  }
-  red[t] = sum;
-  __syncthreads();
-  if (t < C) {
-    float v = 0.f;
-    for (int k = 0; k < G; ++k) v += red[k * C + t];
-    partial[static_cast<size_t>(blockIdx.x) * C + t] = v;
-  }
-}
-
-// out[i] = sum over chunks of partial[chunk][i]: one workgroup per output;
-// thread t sums chunks t, t + 256, ... in order, then a fixed-shape tree
-// over the threads (deterministic).
+// out[i] = sum over chunks of partial[chunk][i]: a strided sum per thread, then a
+// fixed tree (one workgroup per output): deterministic.
 __global__ void __launch_bounds__(256) chunk_reduce_k(const float* __restrict__ partial, float* __restrict__ out,
                                                       int chunks, int n) {
   __shared__ float red[256];
@@ -758,14 +763,26 @@ hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, c
   return up ? conv_tile<true>(x, w_fwd, bias, y, pl, s, st) : conv_tile<false>(x, w_fwd, bias, y, pl, s, st);
 }
 
-hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, const MapF& dx, const Shape& s,
-                         hipStream_t st) {
-  const unsigned g = blocks(s.pixels(), BM);
-  if (dy.c % 8 || dy.ld % 4 || dy.off % 4 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
+hipError_t conv3x3_gate(const MapF& dy, const Map& y, const Map& g, float* db, float* partial, const Shape& s,
+                        hipStream_t st) {
+  if (dy.c % 8 || dy.ld % 4 || dy.off % 4 || y.ld % 8 || y.off % 8 || g.ld % 8 || g.off % 8 || g.c != dy.c ||
+      256 % (dy.c / 8))
+    return hipErrorInvalidValue;
+  const unsigned nb = blocks(s.pixels() * (dy.c / 8), 256);
+  gate_k<<<nb, 256, 0, st>>>(dy, y, g, partial, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  chunk_reduce_k<<<dy.c, 256, 0, st>>>(partial, db, static_cast<int>(nb), dy.c);
+  return hipGetLastError();
+}
+
+hipError_t conv3x3_dgrad(const Map& g, const uint16_t* w_dgrad, const MapF& dx, const Shape& s, hipStream_t st) {
+  const unsigned nb = blocks(s.pixels(), BM);
+  if (g.c % 8 || g.ld % 8 || g.off % 8) return hipErrorInvalidValue;
   switch (dx.c) {
-    case 32: conv_dgrad_k<32><<<g, 256, 0, st>>>(dy, y, w_dgrad, dx, s); break;
-    case 64: conv_dgrad_k<64><<<g, 256, 0, st>>>(dy, y, w_dgrad, dx, s); break;
-    case 128: conv_dgrad_k<128><<<g, 256, 0, st>>>(dy, y, w_dgrad, dx, s); break;
+    case 32: conv_dgrad_k<32><<<nb, 256, 0, st>>>(g, w_dgrad, dx, s); break;
+    case 64: conv_dgrad_k<64><<<nb, 256, 0, st>>>(g, w_dgrad, dx, s); break;
+    case 128: conv_dgrad_k<128><<<nb, 256, 0, st>>>(g, w_dgrad, dx, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -773,32 +790,26 @@ hipError_t conv3x3_dgrad(const MapF& dy, const Map& y, const uint16_t* w_dgrad, 
 
 size_t conv3x3_wgrad_scratch(int ci, int co, const Shape& s) {
   const long long chunks = (s.pixels() + kWgradChunk - 1) / kWgradChunk;
-  const long long bchunks = (s.pixels() + kBiasChunk - 1) / kBiasChunk;
+  const long long bchunks = (s.pixels() * (co / 8) + 255) / 256;  // gate_k's blocks
   const size_t wsum = static_cast<size_t>(chunks) * 9 * ci * co, bsum = static_cast<size_t>(bchunks) * co;
   return wsum > bsum ? wsum : bsum;
 }
 
-hipError_t conv3x3_wgrad(const Map& x, const MapF& dy, const Map& y, float* dw, float* db, float* partial,
-                         const Shape& s, hipStream_t st, int ci_out) {
+hipError_t conv3x3_wgrad(const Map& x, const Map& g, float* dw, float* partial, const Shape& s, hipStream_t st,
+                         int ci_out) {
   const int chunks = static_cast<int>((s.pixels() + kWgradChunk - 1) / kWgradChunk);
   if (x.c % 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
-  if (dy.ld % 4 || dy.off % 4 || y.ld % 4 || y.off % 4) return hipErrorInvalidValue;
+  if (g.ld % 4 || g.off % 4) return hipErrorInvalidValue;
   dim3 grid(chunks, 9, (x.c + BM - 1) / BM);
-  switch (dy.c) {
-    case 32: conv_wgrad_k<32><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
-    case 64: conv_wgrad_k<64><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
-    case 128: conv_wgrad_k<128><<<grid, 256, 0, st>>>(x, dy, y, partial, s); break;
+  switch (g.c) {
+    case 32: conv_wgrad_k<32><<<grid, 256, 0, st>>>(x, g, partial, s); break;
+    case 64: conv_wgrad_k<64><<<grid, 256, 0, st>>>(x, g, partial, s); break;
+    case 128: conv_wgrad_k<128><<<grid, 256, 0, st>>>(x, g, partial, s); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  wgrad_reduce_k<<<blocks(9LL * ci_out * dy.c, 256), 256, 0, st>>>(partial, dw, chunks, x.c, ci_out, dy.c);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // bias partials reuse the front of the scratch (the weight sums are done)
-  const int bchunks = static_cast<int>((s.pixels() + kBiasChunk - 1) / kBiasChunk);
-  bias_partial_k<<<bchunks, 256, 0, st>>>(dy, y, partial, s);
-  chunk_reduce_k<<<dy.c, 256, 0, st>>>(partial, db, bchunks, dy.c);
+  wgrad_reduce_k<<<blocks(9LL * ci_out * g.c, 256), 256, 0, st>>>(partial, dw, chunks, x.c, ci_out, g.c);
   return hipGetLastError();
 }
 

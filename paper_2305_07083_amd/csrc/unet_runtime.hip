@@ -79,6 +79,7 @@ struct dfb_denoiser_ctx {
         *g_pool2 = nullptr, *g_e2a = nullptr, *g_pool1 = nullptr, *g_e1a = nullptr;
   float* scratch = nullptr;
   size_t scratch_n = 0;
+  uint16_t* gate = nullptr;  // gated output gradient of the layer in the backward pass (bf16)
   float* loss_dev = nullptr;
   // frame inference buffers (dfb_denoise)
   float* frame_in = nullptr;
@@ -174,40 +175,43 @@ dfb_status backward(dfb_denoiser_ctx* n, const float* target, const Shape& s0) {
   using namespace dfb::unet;
   NHIP(n, out_conv_backward(mp(n->d1b, 32, 0, 32), n->out, target, n->w + n->off_ow, mf(n->g_d1b, 32, 0, 32),
                             G + n->off_ow, G + n->off_ob, n->loss_dev, S, s0, st));
+  // one conv layer: gate its output gradient dy (output y) once, with the
+  // bias gradient, then the data gradient into dx (unless null) and the
+  // weight gradient
+  auto layer = [&](int L, const MapF& dy, const Map& y, const Map& x, const MapF* dx, const Shape& sh, int ci_out) {
+    const Map gm{n->gate, dy.c, 0, dy.c};
+    hipError_t e = conv3x3_gate(dy, y, gm, gb(L), S, sh, st);
+    if (e == hipSuccess && dx) e = conv3x3_dgrad(gm, n->wd[L], *dx, sh, st);
+    if (e == hipSuccess) e = conv3x3_wgrad(x, gm, gw(L), S, sh, st, ci_out);
+    return e;
+  };
+  const MapF dx_d1a = mf(n->g_d1a, 32, 0, 32), dx_cat1 = mf(n->g_cat1, 64, 0, 64), dx_upd2 = mf(n->g_upd2, 64, 0, 64);
+  const MapF dx_d2a = mf(n->g_d2a, 64, 0, 64), dx_cat2 = mf(n->g_cat2, 128, 0, 128), dx_up3 = mf(n->g_up3, 128, 0, 128);
+  const MapF dx_e3a = mf(n->g_e3a, 128, 0, 128), dx_pool2 = mf(n->g_pool2, 64, 0, 64), dx_e2a = mf(n->g_e2a, 64, 0, 64);
+  const MapF dx_pool1 = mf(n->g_pool1, 32, 0, 32), dx_e1a = mf(n->g_e1a, 32, 0, 32);
   // dec1b, dec1a
-  NHIP(n, conv3x3_dgrad(mf(n->g_d1b, 32, 0, 32), mp(n->d1b, 32, 0, 32), n->wd[DEC1B], mf(n->g_d1a, 32, 0, 32), s0, st));
-  NHIP(n, conv3x3_wgrad(mp(n->d1a, 32, 0, 32), mf(n->g_d1b, 32, 0, 32), mp(n->d1b, 32, 0, 32), gw(DEC1B), gb(DEC1B), S, s0, st, 32));
-  NHIP(n, conv3x3_dgrad(mf(n->g_d1a, 32, 0, 32), mp(n->d1a, 32, 0, 32), n->wd[DEC1A], mf(n->g_cat1, 64, 0, 64), s0, st));
-  NHIP(n, conv3x3_wgrad(mp(n->cat1, 64, 0, 64), mf(n->g_d1a, 32, 0, 32), mp(n->d1a, 32, 0, 32), gw(DEC1A), gb(DEC1A), S, s0, st, 64));
+  NHIP(n, layer(DEC1B, mf(n->g_d1b, 32, 0, 32), mp(n->d1b, 32, 0, 32), mp(n->d1a, 32, 0, 32), &dx_d1a, s0, 32));
+  NHIP(n, layer(DEC1A, mf(n->g_d1a, 32, 0, 32), mp(n->d1a, 32, 0, 32), mp(n->cat1, 64, 0, 64), &dx_cat1, s0, 64));
   // up1 (input: upsampled dec2b), output cat1[0:32]
-  NHIP(n, conv3x3_dgrad(mf(n->g_cat1, 64, 0, 32), mp(n->cat1, 64, 0, 32), n->wd[UP1], mf(n->g_upd2, 64, 0, 64), s0, st));
-  NHIP(n, conv3x3_wgrad(mp(n->upd2, 64, 0, 64), mf(n->g_cat1, 64, 0, 32), mp(n->cat1, 64, 0, 32), gw(UP1), gb(UP1), S, s0, st, 64));
+  NHIP(n, layer(UP1, mf(n->g_cat1, 64, 0, 32), mp(n->cat1, 64, 0, 32), mp(n->upd2, 64, 0, 64), &dx_upd2, s0, 64));
   NHIP(n, upsample2_backward(mf(n->g_upd2, 64, 0, 64), mf(n->g_d2b, 64, 0, 64), s1, st));
   // dec2b, dec2a
-  NHIP(n, conv3x3_dgrad(mf(n->g_d2b, 64, 0, 64), mp(n->d2b, 64, 0, 64), n->wd[DEC2B], mf(n->g_d2a, 64, 0, 64), s1, st));
-  NHIP(n, conv3x3_wgrad(mp(n->d2a, 64, 0, 64), mf(n->g_d2b, 64, 0, 64), mp(n->d2b, 64, 0, 64), gw(DEC2B), gb(DEC2B), S, s1, st, 64));
-  NHIP(n, conv3x3_dgrad(mf(n->g_d2a, 64, 0, 64), mp(n->d2a, 64, 0, 64), n->wd[DEC2A], mf(n->g_cat2, 128, 0, 128), s1, st));
-  NHIP(n, conv3x3_wgrad(mp(n->cat2, 128, 0, 128), mf(n->g_d2a, 64, 0, 64), mp(n->d2a, 64, 0, 64), gw(DEC2A), gb(DEC2A), S, s1, st, 128));
+  NHIP(n, layer(DEC2B, mf(n->g_d2b, 64, 0, 64), mp(n->d2b, 64, 0, 64), mp(n->d2a, 64, 0, 64), &dx_d2a, s1, 64));
+  NHIP(n, layer(DEC2A, mf(n->g_d2a, 64, 0, 64), mp(n->d2a, 64, 0, 64), mp(n->cat2, 128, 0, 128), &dx_cat2, s1, 128));
   // up2 (input: upsampled enc3b), output cat2[0:64]
-  NHIP(n, conv3x3_dgrad(mf(n->g_cat2, 128, 0, 64), mp(n->cat2, 128, 0, 64), n->wd[UP2], mf(n->g_up3, 128, 0, 128), s1, st));
-  NHIP(n, conv3x3_wgrad(mp(n->up3, 128, 0, 128), mf(n->g_cat2, 128, 0, 64), mp(n->cat2, 128, 0, 64), gw(UP2), gb(UP2), S, s1, st, 128));
+  NHIP(n, layer(UP2, mf(n->g_cat2, 128, 0, 64), mp(n->cat2, 128, 0, 64), mp(n->up3, 128, 0, 128), &dx_up3, s1, 128));
   NHIP(n, upsample2_backward(mf(n->g_up3, 128, 0, 128), mf(n->g_e3b, 128, 0, 128), s2, st));
   // enc3b, enc3a
-  NHIP(n, conv3x3_dgrad(mf(n->g_e3b, 128, 0, 128), mp(n->e3b, 128, 0, 128), n->wd[ENC3B], mf(n->g_e3a, 128, 0, 128), s2, st));
-  NHIP(n, conv3x3_wgrad(mp(n->e3a, 128, 0, 128), mf(n->g_e3b, 128, 0, 128), mp(n->e3b, 128, 0, 128), gw(ENC3B), gb(ENC3B), S, s2, st, 128));
-  NHIP(n, conv3x3_dgrad(mf(n->g_e3a, 128, 0, 128), mp(n->e3a, 128, 0, 128), n->wd[ENC3A], mf(n->g_pool2, 64, 0, 64), s2, st));
-  NHIP(n, conv3x3_wgrad(mp(n->pool2, 64, 0, 64), mf(n->g_e3a, 128, 0, 128), mp(n->e3a, 128, 0, 128), gw(ENC3A), gb(ENC3A), S, s2, st, 64));
+  NHIP(n, layer(ENC3B, mf(n->g_e3b, 128, 0, 128), mp(n->e3b, 128, 0, 128), mp(n->e3a, 128, 0, 128), &dx_e3a, s2, 128));
+  NHIP(n, layer(ENC3A, mf(n->g_e3a, 128, 0, 128), mp(n->e3a, 128, 0, 128), mp(n->pool2, 64, 0, 64), &dx_pool2, s2, 64));
   // skip 2: the enc2b output also fed pool2
   NHIP(n, avgpool2_backward_add(mf(n->g_pool2, 64, 0, 64), mf(n->g_cat2, 128, 64, 64), s1, st));
-  NHIP(n, conv3x3_dgrad(mf(n->g_cat2, 128, 64, 64), mp(n->cat2, 128, 64, 64), n->wd[ENC2B], mf(n->g_e2a, 64, 0, 64), s1, st));
-  NHIP(n, conv3x3_wgrad(mp(n->e2a, 64, 0, 64), mf(n->g_cat2, 128, 64, 64), mp(n->cat2, 128, 64, 64), gw(ENC2B), gb(ENC2B), S, s1, st, 64));
-  NHIP(n, conv3x3_dgrad(mf(n->g_e2a, 64, 0, 64), mp(n->e2a, 64, 0, 64), n->wd[ENC2A], mf(n->g_pool1, 32, 0, 32), s1, st));
-  NHIP(n, conv3x3_wgrad(mp(n->pool1, 32, 0, 32), mf(n->g_e2a, 64, 0, 64), mp(n->e2a, 64, 0, 64), gw(ENC2A), gb(ENC2A), S, s1, st, 32));
+  NHIP(n, layer(ENC2B, mf(n->g_cat2, 128, 64, 64), mp(n->cat2, 128, 64, 64), mp(n->e2a, 64, 0, 64), &dx_e2a, s1, 64));
+  NHIP(n, layer(ENC2A, mf(n->g_e2a, 64, 0, 64), mp(n->e2a, 64, 0, 64), mp(n->pool1, 32, 0, 32), &dx_pool1, s1, 32));
   // skip 1: the enc1b output also fed pool1
   NHIP(n, avgpool2_backward_add(mf(n->g_pool1, 32, 0, 32), mf(n->g_cat1, 64, 32, 32), s0, st));
-  NHIP(n, conv3x3_dgrad(mf(n->g_cat1, 64, 32, 32), mp(n->cat1, 64, 32, 32), n->wd[ENC1B], mf(n->g_e1a, 32, 0, 32), s0, st));
-  NHIP(n, conv3x3_wgrad(mp(n->e1a, 32, 0, 32), mf(n->g_cat1, 64, 32, 32), mp(n->cat1, 64, 32, 32), gw(ENC1B), gb(ENC1B), S, s0, st, 32));
-  NHIP(n, conv3x3_wgrad(mp(n->xin, 8, 0, 8), mf(n->g_e1a, 32, 0, 32), mp(n->e1a, 32, 0, 32), gw(ENC1A), gb(ENC1A), S, s0, st, 6));
+  NHIP(n, layer(ENC1B, mf(n->g_cat1, 64, 32, 32), mp(n->cat1, 64, 32, 32), mp(n->e1a, 32, 0, 32), &dx_e1a, s0, 32));
+  NHIP(n, layer(ENC1A, mf(n->g_e1a, 32, 0, 32), mp(n->e1a, 32, 0, 32), mp(n->xin, 8, 0, 8), nullptr, s0, 6));
   return DFB_OK;
 }
 
@@ -298,6 +302,7 @@ dfb_status dfb_denoiser_create(const dfb_unet_config* cfg, void* hip_stream, dfb
   }
   n->scratch_n = sc;
   if ((s = dalloc(n, &n->scratch, sc)) || (s = dalloc(n, &n->loss_dev, 4))) return bail(s);
+  if ((s = dalloc(n, &n->gate, static_cast<size_t>(std::max(P0 * 32, std::max(P1 * 64, P2 * 128)))))) return bail(s);
   // initial parameters: He-normal conv3x3 weights, zero biases, N(0, 0.01) output weights
   std::vector<float> h(np, 0.f);
   uint64_t st = 0x5DEECE66Dull ^ cfg->seed;
