@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(256) gate_k(MapF dy, Map y, Map g, float* __re
 // ------------------------------------------------------------- wgrad
 // Per tap and 64-wide c_in tile, over one chunk of pixels:
 // partial[chunk][tap][ci][co] = sum_p x[p + tap][ci] * g[p][co], g = bf16(dy * (y > 0)).
-constexpr int kWgradChunk = 2048;
+constexpr int kWgradChunk = 1024;
 
 // A stage is KS slices of 32 pixels (one barrier pair per stage); the
 // next stage's x and g are loaded into registers while this stage's MFMAs
