@@ -634,12 +634,15 @@ __global__ void __launch_bounds__(256) out_bwd_k(Map x, const float* __restrict_
   }
 }
 
+// one thread per pixel: 6 f32 in, one 16-byte store of 8 bf16 (channels 6, 7 zero)
 __global__ void pack_input_k(const float* __restrict__ in, int in_ld, uint16_t* __restrict__ x, long long P) {
-  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= P * 8) return;
-  const long long p = e >> 3;
-  const int ch = static_cast<int>(e & 7);
-  x[e] = ch < 6 ? to_bf16(in[p * in_ld + ch]) : static_cast<uint16_t>(0);
+  const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const float* q = in + p * in_ld;
+  uint32_t h[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) h[c] = to_bf16(q[c]);
+  *reinterpret_cast<uint4*>(x + p * 8) = uint4{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), 0u};
 }
 
 __global__ void adam_k(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
@@ -868,7 +871,8 @@ hipError_t out_conv_backward(const Map& x, const float* out, const float* target
 }
 
 hipError_t pack_input(const float* in, int in_ld, uint16_t* x, const Shape& s, hipStream_t st) {
-  pack_input_k<<<blocks(s.pixels() * 8, 256), 256, 0, st>>>(in, in_ld, x, s.pixels());
+  if (reinterpret_cast<uintptr_t>(x) % 16) return hipErrorInvalidValue;
+  pack_input_k<<<blocks(s.pixels(), 256), 256, 0, st>>>(in, in_ld, x, s.pixels());
   return hipGetLastError();
 }
 
