@@ -743,13 +743,16 @@ __device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* 
 #endif
 constexpr int kBlkLog = DFB_BLK_LOG;   // keys sorted per lane in registers: 2^kBlkLog
 constexpr int kBlk = 1 << kBlkLog;
+// Layers per lane whose colours are loaded with the keys (held in registers
+// through the sort; past 8 the capacity-32 kernel loses its second wave per
+// SIMD), and the most merge stages one LDS pass runs.
 #ifndef DFB_BIG_C
 #define DFB_BIG_C 8
 #endif
 #ifndef DFB_MAX_M
 #define DFB_MAX_M 4
 #endif
-constexpr int kBigC = DFB_BIG_C;              // layers per lane whose colours are loaded with the keys
+constexpr int kBigC = DFB_BIG_C;
 
 __device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
 

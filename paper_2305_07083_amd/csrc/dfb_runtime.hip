@@ -275,16 +275,24 @@ dfb_status check_usable(dfb_ctx* h) {
 int kcap_for(int max_k) { return max_k <= 8 ? 8 : (max_k <= 16 ? 16 : 32); }
 
 // Candidate launch shapes: square work units of 16/32/64/128 that divide the
-// tile (else the whole tile), times 1/2/4 waves, times (frames with tiles of
-// more than 128 layers) a small or a large LDS budget for the K > 32 path --
-// two workgroups per CU, or one with twice the pixels per sorting group.
+// tile (else the whole tile), and full-width strips of the same pixel count
+// (a strip row is a whole tile row, so a unit's plane rows are contiguous in
+// memory and fp16 rows fill whole cache lines), times 1/2/4 waves, times
+// (frames with tiles of more than 128 layers) a small or a large LDS budget
+// for the K > 32 path -- two workgroups per CU, or one with twice the pixels
+// per sorting group.
 std::vector<Shape> candidates(const dfb_config& c, int max_k) {
   std::vector<std::pair<int, int>> sizes;
   if (c.work_w) {
     sizes.push_back({c.work_w, c.work_h});
   } else {
     for (int s : {16, 32, 64, 128})
-      if (c.tile_w % s == 0 && c.tile_h % s == 0) sizes.push_back({s, s});
+      if (c.tile_w % s == 0 && c.tile_h % s == 0) {
+        sizes.push_back({s, s});
+        const int h = s * s / c.tile_w;
+        if (s < c.tile_w && (s * s) % c.tile_w == 0 && h >= 1 && c.tile_h % h == 0)
+          sizes.push_back({c.tile_w, h});
+      }
     if (sizes.empty()) sizes.push_back({c.tile_w, c.tile_h});
   }
   std::vector<int> waves;
