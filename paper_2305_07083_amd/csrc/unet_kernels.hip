@@ -461,18 +461,25 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restr
   }
 }
 
-// dw[tap][ci][co] (ci < ci_out) = sum over chunks, in chunk order.
+// dw[tap][ci][co] (ci < ci_out) = sum over chunks: a workgroup takes 64
+// outputs; wave g sums chunks g, g + 4, g + 8, ... in order, then the four
+// wave sums are added in wave order (deterministic).
 __global__ void __launch_bounds__(256) wgrad_reduce_k(const float* __restrict__ partial, float* __restrict__ dw,
                                                       int chunks, int ci_n, int ci_out, int co_n) {
-  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  __shared__ float red[4][64];
+  const int t = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const long long e = static_cast<long long>(blockIdx.x) * 64 + t;
   const long long total = 9LL * ci_out * co_n;
-  if (e >= total) return;
-  const int co = static_cast<int>(e % co_n);
-  const int ci = static_cast<int>((e / co_n) % ci_out);
-  const int tap = static_cast<int>(e / (static_cast<long long>(co_n) * ci_out));
   float sum = 0.f;
-  for (int c = 0; c < chunks; ++c) sum += partial[((static_cast<size_t>(c) * 9 + tap) * ci_n + ci) * co_n + co];
-  dw[e] = sum;
+  if (e < total) {
+    const int co = static_cast<int>(e % co_n);
+    const int ci = static_cast<int>((e / co_n) % ci_out);
+    const int tap = static_cast<int>(e / (static_cast<long long>(co_n) * ci_out));
+    for (int c = g; c < chunks; c += 4) sum += partial[((static_cast<size_t>(c) * 9 + tap) * ci_n + ci) * co_n + co];
+  }
+  red[g][t] = sum;
+  __syncthreads();
+  if (g == 0 && e < total) dw[e] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
 }
 
 // out[i] = sum over chunks of partial[chunk][i]: a strided sum per thread, then a
@@ -812,7 +819,7 @@ hipError_t conv3x3_wgrad(const Map& x, const Map& g, float* dw, float* partial, 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  wgrad_reduce_k<<<blocks(9LL * ci_out * g.c, 256), 256, 0, st>>>(partial, dw, chunks, x.c, ci_out, g.c);
+  wgrad_reduce_k<<<blocks(9LL * ci_out * g.c, 64), 256, 0, st>>>(partial, dw, chunks, x.c, ci_out, g.c);
   return hipGetLastError();
 }
 
