@@ -392,45 +392,59 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restr
   f32x4 acc[BN / 16];
 #pragma unroll
   for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int px = tid >> 3;                 // 0..31: pixel of each slice this thread stages
+  // thread (q, cg) stages the 4 consecutive pixels 4q..4q+3 of the stage
+  // (q < 32) for channel group cg: 4 loads of x and of g, then one 8-byte
+  // LDS store per channel (4 pixels of one channel, transposed in registers)
+  const int q4 = (tid >> 3) * 4;
   const int a8 = (tid & 7) * 8;            // 8 c_in values
   constexpr int BPER = BN / 8;             // c_out values per thread
   const int b0 = (tid & 7) * BPER;
-  uint4 v[kWgradKS];
-  uint32_t gw[kWgradKS][BPER / 2];
+  uint4 v[4];
+  uint32_t gw[4][BPER / 2];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int sl = 0; sl < kWgradKS; ++sl) {
-      const long long p = p_begin + k0 + sl * 32 + px;
+    for (int i = 0; i < 4; ++i) {
+      const long long p = p_begin + k0 + q4 + i;
       const Pix q = pixel_of(p, s);
       bool in;
       const long long src = shifted(q, dr, dc, s, in);
-      v[sl] = uint4{0u, 0u, 0u, 0u};
-      if (in && ci0 + a8 < x.c) v[sl] = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + ci0 + a8);
+      v[i] = uint4{0u, 0u, 0u, 0u};
+      if (in && ci0 + a8 < x.c) v[i] = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + ci0 + a8);
 #pragma unroll
-      for (int i = 0; i < BPER / 2; ++i) gw[sl][i] = 0u;
+      for (int k = 0; k < BPER / 2; ++k) gw[i][k] = 0u;
       if (q.ok) {  // 8-byte loads (g's row stride and offset are multiples of 4)
         const uint16_t* gp = g.p + p * g.ld + g.off + b0;
 #pragma unroll
-        for (int i = 0; i < BPER / 4; ++i) {
-          const uint2 t = *reinterpret_cast<const uint2*>(gp + 4 * i);
-          gw[sl][2 * i] = t.x;
-          gw[sl][2 * i + 1] = t.y;
+        for (int k = 0; k < BPER / 4; ++k) {
+          const uint2 t = *reinterpret_cast<const uint2*>(gp + 4 * k);
+          gw[i][2 * k] = t.x;
+          gw[i][2 * k + 1] = t.y;
         }
       }
     }
   };
+  // channel c of 4 pixels' packed words w[i] (2 channels per word) as 4 bf16
+  auto column = [](const uint32_t (&w)[4], int c) {
+    const int sh = (c & 1) * 16;
+    const uint32_t e0 = (w[0] >> sh) & 0xFFFFu, e1 = (w[1] >> sh) & 0xFFFFu, e2 = (w[2] >> sh) & 0xFFFFu,
+                   e3 = (w[3] >> sh) & 0xFFFFu;
+    return uint2{e0 | (e1 << 16), e2 | (e3 << 16)};
+  };
   load(0);
   for (int k0 = 0; k0 < kWgradChunk; k0 += 32 * kWgradKS) {
 #pragma unroll
-    for (int sl = 0; sl < kWgradKS; ++sl) {
-      const uint32_t vw[4] = {v[sl].x, v[sl].y, v[sl].z, v[sl].w};
+    for (int c = 0; c < 8; ++c) {
+      const int wi = c >> 1;
+      const uint32_t w[4] = {wi == 0 ? v[0].x : wi == 1 ? v[0].y : wi == 2 ? v[0].z : v[0].w,
+                             wi == 0 ? v[1].x : wi == 1 ? v[1].y : wi == 2 ? v[1].z : v[1].w,
+                             wi == 0 ? v[2].x : wi == 1 ? v[2].y : wi == 2 ? v[2].z : v[2].w,
+                             wi == 0 ? v[3].x : wi == 1 ? v[3].y : wi == 2 ? v[3].z : v[3].w};
+      *reinterpret_cast<uint2*>(As + (a8 + c) * LDW + q4) = column(w, c);
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i)
-        As[(a8 + i) * LDW + sl * 32 + px] = static_cast<uint16_t>(vw[i >> 1] >> ((i & 1) * 16));
-#pragma unroll
-      for (int i = 0; i < BPER; ++i)
-        Bs[(b0 + i) * LDW + sl * 32 + px] = static_cast<uint16_t>(gw[sl][i >> 1] >> ((i & 1) * 16));
+    for (int c = 0; c < BPER; ++c) {
+      const uint32_t w[4] = {gw[0][c >> 1], gw[1][c >> 1], gw[2][c >> 1], gw[3][c >> 1]};
+      *reinterpret_cast<uint2*>(Bs + (b0 + c) * LDW + q4) = column(w, c);
     }
     __syncthreads();
     const int k1 = k0 + 32 * kWgradKS;
