@@ -133,7 +133,20 @@ def test_thousands_of_layers(dfb, ranks):
     check_frame(dfb, f, work=0, waves=0, bg=(0.1, 0.1, 0.1, 1.0))
 
 
-@pytest.mark.parametrize("work", [16, 32, 64])
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+@pytest.mark.parametrize("work", [(64, 16), (64, 4)])
+def test_strip_work_units(dfb, dtype, work):
+    """Full-width strip work units (the autotuner's other shape family):
+    against the oracle, and the same finished colour and order as square
+    units (a pixel's arithmetic does not depend on the unit's shape)."""
+    f = workloads.brick_frame(512, 256, (4, 4, 4), 64, seed=7, name="strips").as_dtype(dtype)
+    g, _ = check_frame(dfb, f, work=work, waves=4)
+    sq = composite_gpu(dfb, f, work=32, waves=4)
+    assert np.array_equal(g["finished"], sq["finished"])
+    assert np.array_equal(g["order"], sq["order"])
+
+
+@pytest.mark.parametrize("work", [16, 32, 64, (64, 16)])
 def test_work_units_identical_for_many_layers(dfb, work):
     """With the waves per unit fixed, the LDS path splits each pixel's
     colour sum over the same lanes for every work-unit size: identical

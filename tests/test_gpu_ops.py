@@ -62,7 +62,7 @@ def check_order(g, ref, f):
 
 # ------------------------------------------------------------------ list
 @pytest.mark.parametrize("dtype", [np.float32, np.float16])
-@pytest.mark.parametrize("work,waves", [(32, 1), (64, 4), (16, 2)])
+@pytest.mark.parametrize("work,waves", [(32, 1), (64, 4), (16, 2), ((64, 16), 4), ((64, 4), 2)])
 def test_list_parity(dfb, dtype, work, waves):
     counts = workloads.ragged_counts(20, 40, 21)              # 0..40 generations, K > 32 too
     f = workloads.generation_frame(300, 250, 64, counts, 22, depth_by_generation=False).as_dtype(dtype)
@@ -86,7 +86,7 @@ def test_list_equals_blend_when_rank_order_is_correct(dfb):
 
 # ------------------------------------------------------------------ average
 @pytest.mark.parametrize("dtype", [np.float32, np.float16])
-@pytest.mark.parametrize("work,waves", [(32, 2), (64, 1)])
+@pytest.mark.parametrize("work,waves", [(32, 2), (64, 1), ((64, 16), 4)])
 def test_average_parity(dfb, dtype, work, waves):
     counts = workloads.ragged_counts(20, 70, 23, p_empty=0.15)
     f, _ = workloads.redundant_frame(300, 250, 64, counts, 0.2, 24)
