@@ -96,7 +96,8 @@ typedef struct {
                               are stored whole, pixels past the image edge are composited but
                               excluded from the variance. */
   int32_t work_w, work_h;  /* GPU scheduling unit inside a tile; must divide tile_w / tile_h.
-                              0,0 = autotune over {16,32,64,128}^2 (those that divide the tile). */
+                              0,0 = autotune over the squares {16,32,64,128}^2 that divide the
+                              tile and full-width strips tile_w x (s*s/tile_w) of the same sizes. */
   int32_t waves_per_tile;  /* 64-lane waves per work unit: 1, 2 or 4; 0 = autotune */
   int32_t frag_dtype;      /* dfb_dtype */
   int32_t format;          /* dfb_format */
