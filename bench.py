@@ -334,6 +334,18 @@ def other_workloads_leg(dfb, torch, steps=10, warmup=3):
     return out
 
 
+def assign_samples_ms(dfb, n_tiles=4096, extra=16384, reps=20):
+    """Host time of one variance-driven assignment of extra renders over
+    n_tiles tiles (the library's host routine, seeded variances)."""
+    import numpy as np
+    v = np.random.default_rng(5).gamma(2.0, 1e-3, n_tiles).astype(np.float32)
+    dfb.dfb_assign_samples_host(v, extra)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dfb.dfb_assign_samples_host(v, extra)
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
 def cpu_baseline(f, accumulate, budget_s=12.0):
     """The FP64 oracle as it stands, on whole frames, repeated for about
     ``budget_s`` seconds on this host's cores."""
@@ -392,9 +404,14 @@ def main():
     accumulate = not args.plain
     n_blocks = copies[0].shape[0]
     with dfb.Compositor(cfg, stream) as c:
-        c.set_fragments(copies[0], n_blocks, f.layers, f.expected)
+        t_in = time.perf_counter()
+        c.set_fragments(copies[0], n_blocks, f.layers, f.expected)   # a new layout: host ingest
+        ingest_ms = (time.perf_counter() - t_in) * 1e3
         c.composite(accumulate=False)     # first frame of a new layout: autotunes the launch shape
         torch.cuda.synchronize()
+        t_in = time.perf_counter()
+        c.set_fragments(copies[1 % len(copies)], n_blocks, f.layers, f.expected)  # same layout
+        same_layout_ms = (time.perf_counter() - t_in) * 1e3
         for i in range(args.warmup):
             c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
             c.composite(accumulate=accumulate)
@@ -435,6 +452,8 @@ def main():
                    "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
                    "grid": info.grid_size},
         "kernel_ms": kernel_ms,
+        "host_ms": {"ingest_new_layout": ingest_ms, "set_fragments_same_layout": same_layout_ms,
+                    "assign_samples_4096_tiles": assign_samples_ms(dfb)},
         "hbm_gbps_algorithmic": achieved,
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBPS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
