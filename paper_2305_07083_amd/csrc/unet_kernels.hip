@@ -267,12 +267,17 @@ __global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __
 
 // ------------------------------------------------------------- dgrad
 // A[p][(tap, co)] = g[p - tap][co], g = bf16(dy * (y > 0)) (gate_k); B =
-// W[tap][ci][co].  The next (tap, slice)'s A chunk and weights are loaded
-// into registers while this slice's MFMAs run.
+// W[tap][ci][co].  K runs over (tap, 32-wide c_out slice) in stages of
+// kDgradKS slices (one barrier pair per stage; slots past the last slice
+// stage zeros); the next stage's A chunks and weights are loaded into
+// registers while this stage's MFMAs run.
+constexpr int kDgradKS = 4;
+constexpr int LDD = 32 * kDgradKS + 8;  // LDS row: the stage's K + 8 padding
+
 template <int BN>
 __global__ void __launch_bounds__(256) conv_dgrad_k(Map g, const uint16_t* __restrict__ w, MapF dx, Shape s) {
-  __shared__ __align__(16) uint16_t As[BM * LDK];
-  __shared__ __align__(16) uint16_t Bs[BN * LDK];
+  __shared__ __align__(16) uint16_t As[BM * LDD];
+  __shared__ __align__(16) uint16_t Bs[BN * LDD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long m0 = static_cast<long long>(blockIdx.x) * BM;
   const int ap = tid >> 2, ach = (tid & 3) * 8;
@@ -281,39 +286,55 @@ __global__ void __launch_bounds__(256) conv_dgrad_k(Map g, const uint16_t* __res
   f32x4 acc[BN / 16];
 #pragma unroll
   for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int nk = (co_n + 31) / 32;
+  const int nk = (co_n + 31) / 32, n_it = 9 * nk;
   constexpr int WPT = (BN * 4 + 255) / 256;  // 16-byte weight chunks per thread and slice
-  uint4 av, wv[WPT];
-  auto load = [&](int tap, int kc) {
-    bool in;
-    const long long src = shifted(q, 1 - tap / 3, 1 - tap % 3, s, in);
-    const int c0 = kc * 32 + ach;
-    av = uint4{0u, 0u, 0u, 0u};
-    if (in && c0 < co_n) av = *reinterpret_cast<const uint4*>(g.p + src * g.ld + g.off + c0);
+  uint4 av[kDgradKS], wv[kDgradKS][WPT];
+  auto load = [&](int it0) {
 #pragma unroll
-    for (int i = 0; i < WPT; ++i) {
-      const int e = tid + i * 256;
-      const int ci = e >> 2, k0 = kc * 32 + (e & 3) * 8;
-      wv[i] = uint4{0u, 0u, 0u, 0u};
-      if (e < BN * 4 && k0 < co_n)
-        wv[i] = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + ci) * co_n + k0);
+    for (int sl = 0; sl < kDgradKS; ++sl) {
+      const int it = it0 + sl;
+      const int tap = it / nk, kc = it - (it / nk) * nk;
+      av[sl] = uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int i = 0; i < WPT; ++i) wv[sl][i] = uint4{0u, 0u, 0u, 0u};
+      if (it < n_it) {
+        bool in;
+        const long long src = shifted(q, 1 - tap / 3, 1 - tap % 3, s, in);
+        const int c0 = kc * 32 + ach;
+        if (in && c0 < co_n) av[sl] = *reinterpret_cast<const uint4*>(g.p + src * g.ld + g.off + c0);
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+          const int e = tid + i * 256;
+          const int ci = e >> 2, k0 = kc * 32 + (e & 3) * 8;
+          if (e < BN * 4 && k0 < co_n)
+            wv[sl][i] = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + ci) * co_n + k0);
+        }
+      }
     }
   };
-  load(0, 0);
-  for (int it = 0; it < 9 * nk; ++it) {
-    *reinterpret_cast<uint4*>(As + ap * LDK + ach) = av;
+  load(0);
+  for (int it0 = 0; it0 < n_it; it0 += kDgradKS) {
 #pragma unroll
-    for (int i = 0; i < WPT; ++i) {
-      const int e = tid + i * 256;
-      if (e < BN * 4) *reinterpret_cast<uint4*>(Bs + (e >> 2) * LDK + (e & 3) * 8) = wv[i];
+    for (int sl = 0; sl < kDgradKS; ++sl) {
+      *reinterpret_cast<uint4*>(As + ap * LDD + sl * 32 + ach) = av[sl];
+#pragma unroll
+      for (int i = 0; i < WPT; ++i) {
+        const int e = tid + i * 256;
+        if (e < BN * 4) *reinterpret_cast<uint4*>(Bs + (e >> 2) * LDD + sl * 32 + (e & 3) * 8) = wv[sl][i];
+      }
     }
     __syncthreads();
-    if (it + 1 < 9 * nk) load((it + 1) / nk, (it + 1) % nk);
-    const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
+    if (it0 + kDgradKS < n_it) load(it0 + kDgradKS);
 #pragma unroll
-    for (int j = 0; j < BN / 16; ++j) {
-      const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8);
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+    for (int sl = 0; sl < kDgradKS; ++sl) {
+      if (it0 + sl < n_it) {  // uniform
+        const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDD + sl * 32 + (lane >> 4) * 8);
+#pragma unroll
+        for (int j = 0; j < BN / 16; ++j) {
+          const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDD + sl * 32 + (lane >> 4) * 8);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+      }
     }
     __syncthreads();
   }
