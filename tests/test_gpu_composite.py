@@ -125,9 +125,10 @@ def test_layer_counts_across_register_and_lds_paths(dfb, ranks):
     check_frame(dfb, f, bg=(0.3, 0.2, 0.1, 0.9))
 
 
-@pytest.mark.parametrize("ranks", [1500, 2048, 2100])
+@pytest.mark.parametrize("ranks", [1500, 2048, 2100, 4096])
 def test_thousands_of_layers(dfb, ranks):
-    """Padded layer counts of 2048 and 4096 in the LDS sort: against the
+    """Padded layer counts of 2048 and 4096 in the LDS sort, up to the
+    largest tile the library takes (4096 layers, no padding): against the
     oracle, order bit-exact."""
     f = workloads.uniform_frame(16, 16, 16, ranks=ranks, seed=ranks)
     check_frame(dfb, f, work=0, waves=0, bg=(0.1, 0.1, 0.1, 1.0))
