@@ -1,7 +1,7 @@
 """Throughput of the per-tile sort-last compositing path on one MI355X.
 
 One step = one frame of the 2048x2048, 64x64-tile, 4x4x4-brick (64 ranks)
-fragment set through the whole path in one persistent graph launch: per-pixel
+fragment set through the whole path in one persistent launch: per-pixel
 depth sort, front-to-back over with the background, Welford accumulation,
 per-tile variance and RGBA8 tonemapping.  Inputs are resident in HBM before
 the timed region; four copies rotate so the 555 MB working set cannot stay in
@@ -225,7 +225,7 @@ def make_frame(name):
 
 def time_frames(dfb, torch, f, op, copies, steps, warmup):
     """Plain frames (composite + RGBA8) of ``f`` with tile operation ``op``,
-    autotuned; returns (kernel ms from the graph's events, wall ms per frame,
+    autotuned; returns (kernel ms from the HIP events around the frame kernel, wall ms per frame,
     launch info)."""
     cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=0, waves=0, op=op)
     n_blocks = copies[0].shape[0]

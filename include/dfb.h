@@ -157,14 +157,15 @@ dfb_status dfb_destroy(dfb_handle h);
 dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_blocks,
                              const dfb_layer* layers, int32_t n_layers, const int32_t* expected);
 
-/* Composite every tile of the frame in one persistent launch (a one-node HIP
- * graph, replayed each frame) that takes tiles from a device work queue in
- * longest-first order: per pixel, sort the layers by (depth with NaN last and
- * -0 == +0, source_id), blend front to back with premultiplied "over", put
- * the background colour behind (Sec. 4.2, Listing 4).  With DFB_ACCUMULATE
- * the same launch folds the frame into the running mean (Welford), reduces
- * the per-tile variance of the mean and writes the display pixels of the
- * mean; without it the display pixels are those of this frame.
+/* Composite every tile of the frame in one persistent launch on the handle's
+ * stream that takes tiles from a device work queue in longest-first order:
+ * per pixel, sort the layers by (depth with NaN last and -0 == +0,
+ * source_id), blend front to back with premultiplied "over", put the
+ * background colour behind (Sec. 4.2, Listing 4).  With DFB_ACCUMULATE the
+ * same launch folds the frame into the running mean (Welford) and writes the
+ * display pixels of the mean, and a second, small launch combines its
+ * per-unit sums into the per-tile variance of the mean; without it the
+ * display pixels are those of this frame.
  * Tonemap: y = clamp(x,0,1) (NaN -> 0), colour ^ (1/gamma), code
  * floor(255 y + 0.5).  If work_w/waves_per_tile are 0, the first frame of a
  * new layer layout first autotunes them (synchronously). */
@@ -273,9 +274,9 @@ dfb_status dfb_synchronize(dfb_handle h);
 dfb_status dfb_get_info(dfb_handle h, dfb_info* out);
 
 /* Average device time (ms) of the frame kernel over the composites since
- * timing was enabled (dfb_set_timing(h, 1)), measured with HIP events that
- * the frame's graph records right before and after the frame kernel on the
- * handle's stream; -1 if none were timed. */
+ * timing was enabled (dfb_set_timing(h, 1)), measured with HIP events
+ * recorded right before and after the frame kernel on the handle's stream;
+ * -1 if none were timed. */
 dfb_status dfb_set_timing(dfb_handle h, int enable);
 double dfb_kernel_ms(dfb_handle h);
 

@@ -43,7 +43,7 @@ enum ModeBits : uint32_t {
 //   layer_off  [n_layers] element offset of each layer's block (block*5*P);
 //              per tile ordered by source id
 //   work_list  [n_work] work-unit ids, longest tile first
-// Passed by value (a graph node's parameters are updated per frame).
+// Passed by value, built anew for every launch.
 struct FrameArgs {
   const void* frag;            // fragment blocks (caller's buffer)
   uint32_t* queue;             // kQueues x kSlots counters, queues kQueueStride apart
