@@ -168,7 +168,10 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
  * display pixels are those of this frame.
  * Tonemap: y = clamp(x,0,1) (NaN -> 0), colour ^ (1/gamma), code
  * floor(255 y + 0.5).  If work_w/waves_per_tile are 0, the first frame of a
- * new layer layout first autotunes them (synchronously). */
+ * new layer layout first autotunes them (synchronously).
+ * Each call fixes its frame's state in the launch arguments (the work-queue
+ * counter slot, the accumulation count), so a stream capture of one call
+ * holds one frame: a graph made from it may be replayed once, not per frame. */
 dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags);
 
 /* Replace the background texture (NULL: back to cfg.background) for the
