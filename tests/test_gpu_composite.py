@@ -302,6 +302,35 @@ def test_reset_restarts_the_mean(dfb):
         assert np.all(np.isinf(c.read(dfb.DFB_BUF_TILE_VARIANCE)))
 
 
+def test_kernel_timing_leaves_results_unchanged(dfb):
+    """Event timing of the frame kernel (a ring of 64 event pairs, each read
+    back when its slot comes round again): accumulated results are
+    bit-identical with and without it, and the average time is reported only
+    while timing is on."""
+    f = workloads.brick_frame(256, 256, (4, 4, 4), 64, seed=11)
+    xs = [upload(workloads.noisy_colour(f, 0.1, 6, k)) for k in range(4)]
+    bufs = (dfb.DFB_BUF_ACCUM_F32, dfb.DFB_BUF_M2_F32, dfb.DFB_BUF_TILE_VARIANCE, dfb.DFB_BUF_FINAL)
+    res = []
+    for timing in (False, True):
+        cfg = dfb.make_config(256, 256, 64, work=64, waves=2, flags=dfb.DFB_KEEP_FINISHED)
+        with dfb.Compositor(cfg, stream_handle()) as c:
+            assert dfb.dfb_kernel_ms(c.h) == -1.0
+            dfb.dfb_set_timing(c.h, timing)
+            for k in range(70):  # more frames than event pairs in the ring
+                c.set_fragments(xs[k % 4], xs[0].shape[0], f.layers, f.expected)
+                c.composite(accumulate=True)
+            ms = dfb.dfb_kernel_ms(c.h)
+            if timing:
+                assert 0.0 < ms < 100.0
+            else:
+                assert ms == -1.0
+            res.append([c.read(b) for b in bufs])
+            dfb.dfb_set_timing(c.h, False)
+            assert dfb.dfb_kernel_ms(c.h) == -1.0
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
 # ------------------------------------------------------------------ errors
 def test_errors_are_reported(dfb):
     f = workloads.c1()
