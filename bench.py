@@ -43,6 +43,9 @@ def parse():
                     help="skip the list / average tile-operation legs")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the 4096x1024 (fp32, fp16) and 8192x8192 sort-path legs")
+    ap.add_argument("--time-every", type=int, default=5,
+                    help="HIP events around the frame kernel of every n-th timed headline frame "
+                         "(each timed frame carries two event records, ~3.5 us each)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 1 GiB device to device (the reference kernel for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -416,7 +419,7 @@ def main():
             c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
             c.composite(accumulate=accumulate)
         torch.cuda.synchronize()
-        dfb.dfb_set_timing(c.h, True)
+        dfb.dfb_set_timing(c.h, max(1, args.time_every))
         t0 = time.perf_counter()
         for i in range(args.steps):
             c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
@@ -452,6 +455,8 @@ def main():
                    "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
                    "grid": info.grid_size},
         "kernel_ms": kernel_ms,
+        "kernel_timing": "HIP events around the frame kernel of 1 in every %d of the %d timed frames"
+                         % (max(1, args.time_every), args.steps),
         "host_ms": {"ingest_new_layout": ingest_ms, "set_fragments_same_layout": same_layout_ms,
                     "assign_samples_4096_tiles": assign_samples_ms(dfb)},
         "hbm_gbps_algorithmic": achieved,

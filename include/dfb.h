@@ -276,11 +276,13 @@ dfb_status dfb_synchronize(dfb_handle h);
 /* Shape of the current frame and launch. */
 dfb_status dfb_get_info(dfb_handle h, dfb_info* out);
 
-/* Average device time (ms) of the frame kernel over the composites since
- * timing was enabled (dfb_set_timing(h, 1)), measured with HIP events
- * recorded right before and after the frame kernel on the handle's stream;
- * -1 if none were timed. */
-dfb_status dfb_set_timing(dfb_handle h, int enable);
+/* Average device time (ms) of the frame kernel over the timed composites
+ * since the last dfb_set_timing call, measured with HIP events recorded right
+ * before and after the frame kernel on the handle's stream; -1 if none were
+ * timed.  dfb_set_timing(h, n): time the first composite after the call and
+ * every n-th one after it (n = 1: every composite; n <= 0: none).  Each timed
+ * composite adds the two event records to the stream (a few microseconds). */
+dfb_status dfb_set_timing(dfb_handle h, int every);
 double dfb_kernel_ms(dfb_handle h);
 
 /* Host-only check of one frame's layer list against a config, without a GPU:

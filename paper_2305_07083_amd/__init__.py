@@ -242,8 +242,9 @@ def dfb_get_info(h) -> Info:
     return info
 
 
-def dfb_set_timing(h, enable=True):
-    _check(load().dfb_set_timing(h, int(bool(enable))), h)
+def dfb_set_timing(h, every=1):
+    """Time every ``every``-th composite (True: each one; False or 0: none)."""
+    _check(load().dfb_set_timing(h, int(every)), h)
 
 
 def dfb_kernel_ms(h) -> float:

@@ -94,9 +94,11 @@ struct dfb_ctx {
   int subs_x = 1, subs_per_tile = 1;
   bool work_valid = false;  // d_work matches shape + layer table
 
-  // timing: a ring of event pairs, harvested when a slot is reused
+  // timing: a ring of event pairs, harvested when a slot is reused; every
+  // timing_every-th composite is timed (0: none)
   static constexpr int kRing = 64;
-  bool timing = false;
+  int timing_every = 0;
+  int64_t timing_seq = 0;
   hipEvent_t ev0[kRing] = {}, ev1[kRing] = {};
   bool pending[kRing] = {};
   int ring_pos = 0;
@@ -837,7 +839,8 @@ dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
   }
   const int slot = h->ring_pos;
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (h->timing) {
+  const bool timed = h->timing_every > 0 && h->timing_seq++ % h->timing_every == 0;
+  if (timed) {
     if (!h->ev0[slot]) {
       DFB_HIP(h, hipEventCreate(&h->ev0[slot]));
       DFB_HIP(h, hipEventCreate(&h->ev1[slot]));
@@ -851,7 +854,7 @@ dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
   }
   s = launch_frame(h, mode, t0, t1);
   if (s != DFB_OK) return s;
-  if (h->timing) {
+  if (timed) {
     h->pending[slot] = true;
     h->ring_pos = (slot + 1) % dfb_ctx::kRing;
   }
@@ -966,9 +969,10 @@ dfb_status dfb_get_info(dfb_handle h, dfb_info* out) {
   return DFB_OK;
 }
 
-dfb_status dfb_set_timing(dfb_handle h, int enable) {
+dfb_status dfb_set_timing(dfb_handle h, int every) {
   if (!h) return DFB_ERR_INVALID_ARG;
-  h->timing = enable != 0;
+  h->timing_every = every > 0 ? every : 0;
+  h->timing_seq = 0;
   h->time_sum_ms = 0.0;
   h->time_n = 0;
   for (int i = 0; i < dfb_ctx::kRing; ++i) h->pending[i] = false;
