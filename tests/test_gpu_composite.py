@@ -332,6 +332,27 @@ def test_kernel_timing_leaves_results_unchanged(dfb):
             assert np.array_equal(a, b)
 
 
+def test_side_stream_gives_same_results(dfb):
+    """Every launch and copy of a handle goes to the stream it was created
+    with: accumulated frames on a second (default-priority) stream equal
+    those on the current one bit for bit."""
+    torch = torch_dev()
+    f = workloads.brick_frame(256, 256, (4, 4, 4), 64, seed=13)
+    xs = [upload(workloads.noisy_colour(f, 0.1, 7, k)) for k in range(3)]
+    torch.cuda.synchronize()
+    bufs = (dfb.DFB_BUF_ACCUM_F32, dfb.DFB_BUF_M2_F32, dfb.DFB_BUF_TILE_VARIANCE, dfb.DFB_BUF_FINAL)
+    res = []
+    for stream in (torch.cuda.current_stream(), torch.cuda.Stream()):
+        cfg = dfb.make_config(256, 256, 64, work=32, waves=2, flags=dfb.DFB_KEEP_FINISHED)
+        with dfb.Compositor(cfg, stream.cuda_stream) as c:
+            for x in xs:
+                c.set_fragments(x, x.shape[0], f.layers, f.expected)
+                c.composite(accumulate=True)
+            res.append([c.read(b) for b in bufs])
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
 # ------------------------------------------------------------------ errors
 def test_errors_are_reported(dfb):
     f = workloads.c1()
