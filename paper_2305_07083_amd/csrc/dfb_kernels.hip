@@ -351,19 +351,23 @@ __device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const Fram
   return make_float4(R, G, B, A);
 }
 
-// Up-front loads for buckets up to upfront_max(KCAP): the kernel's register
-// allocation follows its largest bucket, so a kernel for tiles of at most 16
-// layers keeps more waves resident when its 12/16 buckets load in two phases;
-// the 32-layer kernel is bound by its 24/32 buckets either way.
+// Up-front loads for buckets up to upfront_max(KCAP): one memory round trip
+// per pixel instead of two, at the cost of registers.  The fp32 16-layer
+// kernel stays at 3 waves per SIMD with all its buckets up front (2048^2
+// bricks: 139 against 144 us); the fp16 one would drop from 4 to 3, so its
+// 12/16 buckets load in two phases.  The 32-layer kernels stay at 2 waves
+// with the 24 bucket up front (4096x1024: 225 against 232 us fp32, 186
+// against 193 us fp16); their 32 bucket loads in two phases.
+template <typename FT>
 constexpr int upfront_max(int kcap) {
-  return DFB_UPFRONT_MAX > 0 ? DFB_UPFRONT_MAX : (kcap <= 16 ? 8 : 16);
+  return DFB_UPFRONT_MAX > 0 ? DFB_UPFRONT_MAX : (kcap <= 16 ? (sizeof(FT) == 4 ? 16 : 8) : 24);
 }
 
 template <typename FT, int KMAX, int KCAP>
 __device__ __forceinline__ float4 composite_px(float& T, const FrameArgs& a, const int64_t* __restrict__ loff,
                                                int K, int off, int p, float* __restrict__ wl,
                                                int NT) {
-  if constexpr (KMAX <= upfront_max(KCAP)) return composite_px_upfront<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
+  if constexpr (KMAX <= upfront_max<FT>(KCAP)) return composite_px_upfront<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
   else return composite_px_two_phase<FT, KMAX>(T, a, loff, K, off, p, wl, NT);
 }
 
