@@ -64,41 +64,41 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def read_counter_profile(path):
+    """The ``key: value`` lines of a committed rocprofv3 counter summary
+    (comment lines skipped), or None if the file is missing or its counters
+    were taken on another kernel source than the current one."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv if kv.get("kernel_source_hash") == kernel_source_hash() else None
+
+
+def counter_bytes(kv, prefix):
+    """HBM bytes per launch: scaled FETCH_SIZE + WRITE_SIZE (KiB per dispatch)."""
+    if kv is None or prefix + "fetch_kib_per_dispatch" not in kv:
+        return None
+    fetch = float(kv[prefix + "fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+    write = float(kv[prefix + "write_kib_per_dispatch"]) * float(kv["write_scale"])
+    return (fetch + write) * 1024.0
+
+
 def measured_traffic(workload, accumulate):
     """HBM bytes per frame-kernel launch from the committed rocprofv3 counter
     summary of this workload, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "frame_kernel_%s_%s_counters.txt"
                         % (workload, "acc" if accumulate else "plain"))
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
-    write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
-    return (fetch + write) * 1024.0
+    return counter_bytes(read_counter_profile(path), "")
 
 
 def measured_leg_traffic(profile, leg):
     """HBM bytes per launch of one leg's kernel (``leg``_fetch / _write keys)
     from a committed counter summary (current kernel source only)."""
-    path = os.path.join(ROOT, "profiles", profile)
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    for line in open(path):
-        if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash() or leg + "_fetch_kib_per_dispatch" not in kv:
-        return None
-    fetch = float(kv[leg + "_fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
-    write = float(kv[leg + "_write_kib_per_dispatch"]) * float(kv["write_scale"])
-    return (fetch + write) * 1024.0
+    return counter_bytes(read_counter_profile(os.path.join(ROOT, "profiles", profile)), leg + "_")
 
 
 def measured_op_traffic(op):
