@@ -88,6 +88,7 @@ typedef enum {
 
 /* dfb_composite_frame frame_flags */
 #define DFB_ACCUMULATE 0x1u      /* fold this frame into the running mean (fused) */
+#define DFB_REPLAY 0x2u          /* launch the frame as a replay of a HIP graph the handle keeps */
 
 typedef struct {
   int32_t width, height;   /* framebuffer, pixels */
@@ -129,17 +130,26 @@ typedef struct {
   int32_t n_tiles, tiles_x, tiles_y;
   int32_t n_layers, max_layers_per_tile;
   int32_t work_w, work_h, waves_per_tile;  /* the launch shape in use (after autotune) */
-  int32_t accumulation_id;                 /* frames folded in since the last reset */
+  int32_t accumulation_id;                 /* frames folded in since the last reset (read from
+                                              the device: counts graph replays too) */
   int32_t grid_size;                       /* persistent workgroups per frame */
   int64_t n_fragments;                     /* sum over tiles of layers * P */
 } dfb_info;
 
-/* Create a compositor.  Validates cfg, allocates the device buffers for the
- * finished / accumulation / variance / display tiles on the current device.
- * hip_stream: a hipStream_t (may be 0).  On success *out is a new handle. */
+/* Create a compositor: the tile owner's state of Sec. 3 and the buffers of
+ * Listing 1's tile operation (finished, accumulation and variance tiles,
+ * final pixels in the display format of Sec. 3.1).  Validates cfg and
+ * allocates those device buffers on the current device; the accumulation
+ * buffers are allocated by the first accumulating frame.
+ * hip_stream: a hipStream_t (may be 0); every call of the handle enqueues
+ * on it.  On success *out is a new handle owned by the caller; errors leave
+ * *out NULL and the reason in dfb_last_error(NULL). */
 dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out);
 
-/* Free every device buffer and the handle; waits for pending work. */
+/* End of the DFB instance (Sec. 3; Listing 1's buffers): waits for pending
+ * work on the handle's stream, then frees every device buffer, the frame
+ * graphs and the handle.  Device buffers the caller lent (fragments,
+ * background texture) are not touched.  NULL -> DFB_ERR_INVALID_ARG. */
 dfb_status dfb_destroy(dfb_handle h);
 
 /* Hand over one frame's generation-1 tiles (Sec. 3.1 setTile; Sec. 3.1.1).
@@ -169,9 +179,23 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
  * Tonemap: y = clamp(x,0,1) (NaN -> 0), colour ^ (1/gamma), code
  * floor(255 y + 0.5).  If work_w/waves_per_tile are 0, the first frame of a
  * new layer layout first autotunes them (synchronously).
- * Each call fixes its frame's state in the launch arguments (the work-queue
- * counter slot, the accumulation count), so a stream capture of one call
- * holds one frame: a graph made from it may be replayed once, not per frame. */
+ * Per-frame state (the work queue's counter slot, the accumulation count)
+ * lives in device memory and is advanced by the frame's own kernels, so the
+ * launches of one call are the same for every frame of a layer table:
+ *  - DFB_REPLAY launches the frame as a replay of a HIP graph (frame kernel,
+ *    then the variance combine of an accumulating frame) that the handle
+ *    builds on first use for the current layer table, launch shape,
+ *    fragment buffer and flags, and keeps (up to 8 buffers and flag sets)
+ *    until the layer layout, the shape or the background texture changes.
+ *  - The caller may also capture a call on the handle's stream into a graph
+ *    of its own and replay that graph once per frame.  Under capture the
+ *    call fails with DFB_ERR_STATE if the layout's launch shape is not
+ *    chosen yet (composite one frame first) or, with DFB_ACCUMULATE, if no
+ *    frame was accumulated yet; it does no timing.  The graph holds the
+ *    fragment buffer given to the last dfb_set_fragments and the layer
+ *    table: replays see what those hold when they run.
+ * Errors: before any dfb_set_fragments -> DFB_ERR_STATE; unknown flags ->
+ * DFB_ERR_INVALID_ARG. */
 dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags);
 
 /* Replace the background texture (NULL: back to cfg.background) for the
@@ -251,16 +275,28 @@ dfb_status dfb_assign_samples_host(const float* variance, int32_t n_tiles, int64
  * Synchronises the handle's stream. */
 dfb_status dfb_assign_samples(dfb_handle h, int64_t extra, int32_t* counts);
 
-/* Unfused accumulation of the last finished frame (needs DFB_KEEP_FINISHED):
- * the same Welford update, variance and display conversion as
- * DFB_ACCUMULATE, as a separate pass. */
+/* Progressive refinement (Listing 1: accumulationID and the accumulation
+ * and variance tiles), unfused: fold the last finished frame into the
+ * running mean as frame n = accumulationID + 1, with the same Welford
+ * update, per-tile variance of the mean and display conversion as
+ * DFB_ACCUMULATE, in a separate pass.  Needs a frame composited with
+ * DFB_KEEP_FINISHED and without DFB_ACCUMULATE that was not accumulated
+ * yet, else DFB_ERR_STATE (a frame is never folded in twice). */
 dfb_status dfb_accumulate(dfb_handle h);
 
-/* Start progressive refinement over: the next accumulated frame is n = 1. */
+/* Restart progressive refinement (Listing 1: accumulationID := 0, as when
+ * the camera moves): the next accumulated frame is n = 1 and replaces the
+ * mean.  Stream-ordered: frames enqueued before it still accumulate. */
 dfb_status dfb_reset_accumulation(dfb_handle h);
 
-/* Copy tiles [first_tile, first_tile + n_tiles) of one buffer to dst (host, or
- * device if dst_is_device), stream-ordered.  DFB_BUF_SORT_ORDER holds, for
+/* Read out finished pixels (Listing 1: finalPixels, in the display format
+ * of Sec. 3.1) or another of the tile operation's buffers.
+ * Copy tiles [first_tile, first_tile + n_tiles) of one buffer to dst (host, or
+ * device if dst_is_device; the caller owns dst, which must hold
+ * dfb_buffer_bytes for the range), stream-ordered: a host dst is complete
+ * after dfb_synchronize.  Bad range or NULL dst -> DFB_ERR_INVALID_ARG; no
+ * composited frame, or a buffer its flag or format did not enable ->
+ * DFB_ERR_STATE.  DFB_BUF_SORT_ORDER holds, for
  * each tile in id order, uint16[K_t][P]: entry (i, p) is the index, among the
  * tile's layers ordered by ascending source_id, of the i-th nearest fragment
  * of pixel p; it is only kept for the last composited frame. */
@@ -270,10 +306,13 @@ dfb_status dfb_read_tiles(dfb_handle h, dfb_buffer which, int32_t first_tile, in
 /* Bytes dfb_read_tiles would copy for that range (0 if not available). */
 int64_t dfb_buffer_bytes(dfb_handle h, dfb_buffer which, int32_t first_tile, int32_t n_tiles);
 
-/* Wait for everything enqueued on the handle's stream. */
+/* Plumbing, no paper counterpart: wait for everything enqueued on the
+ * handle's stream; a device fault is returned here (and stays sticky). */
 dfb_status dfb_synchronize(dfb_handle h);
 
-/* Shape of the current frame and launch. */
+/* Shape of the current frame and launch (plumbing).  Reads the
+ * accumulation count from the device: synchronises the stream, so not
+ * during a capture. */
 dfb_status dfb_get_info(dfb_handle h, dfb_info* out);
 
 /* Average device time (ms) of the frame kernel over the timed composites

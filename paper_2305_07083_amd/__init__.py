@@ -35,6 +35,7 @@ DFB_FMT_RGBA8, DFB_FMT_RGBAF32, DFB_FMT_NONE = 0, 1, 2
  DFB_BUF_TILE_VARIANCE, DFB_BUF_SORT_ORDER, DFB_BUF_DENOISED_F32) = range(7)
 DFB_VALIDATE, DFB_KEEP_SORT_ORDER, DFB_KEEP_FINISHED = 0x1, 0x2, 0x4
 DFB_ACCUMULATE = 0x1
+DFB_REPLAY = 0x2
 
 # every symbol include/dfb.h declares
 EXPORTED = (
@@ -374,8 +375,8 @@ class Compositor:
     def assign_samples(self, extra):
         return dfb_assign_samples(self.h, extra, self.n_tiles)
 
-    def composite(self, accumulate=False):
-        dfb_composite_frame(self.h, DFB_ACCUMULATE if accumulate else 0)
+    def composite(self, accumulate=False, replay=False):
+        dfb_composite_frame(self.h, (DFB_ACCUMULATE if accumulate else 0) | (DFB_REPLAY if replay else 0))
 
     def accumulate(self):
         dfb_accumulate(self.h)

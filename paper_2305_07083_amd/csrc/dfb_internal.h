@@ -18,10 +18,22 @@ constexpr int kRegMax = 32;
 // mod kQueues, so same-address atomics do not serialise the whole chip.
 // Each counter has kSlots per-frame slots used as a ring: frame f counts in
 // slot f mod kSlots and clears slot (f + kSlots/2) mod kSlots, which no
-// frame in flight uses, so nothing is reset between frames.
+// frame in flight uses, so nothing is reset between frames.  After the
+// kQueues counter pages come one page of per-slot "workgroups finished"
+// counters and one page holding the FrameState below.
 constexpr int kQueues = 16;
 constexpr int kQueueStride = 1024;  // 4-byte counters between queues
 constexpr int kSlots = 64;
+constexpr int kQueueWords = (kQueues + 2) * kQueueStride;  // the whole allocation, in u32
+
+// Per-handle frame state in device memory.  Kernels read it at their start
+// and the last workgroup of a frame advances it, so a launch carries no
+// per-frame value in its arguments and one captured frame can be replayed
+// as every later frame.
+struct FrameState {
+  uint32_t seq;    // frame launches so far: selects the counter slot
+  int32_t n_acc;   // frames folded into the running mean since the reset
+};
 constexpr int kMaxLayers = 4096;
 // Largest LDS budget of the large-K path for keys (u64) and weights (f32);
 // the host passes 64, 96 or 112 KB depending on the frame's largest tile.
@@ -43,11 +55,13 @@ enum ModeBits : uint32_t {
 //   layer_off  [n_layers] element offset of each layer's block (block*5*P);
 //              per tile ordered by source id
 //   work_list  [n_work] work-unit ids, longest tile first
-// Passed by value, built anew for every launch.
+// Passed by value; nothing in it changes from frame to frame while the layer
+// table, the fragment buffer and the launch shape stay the same.
 struct FrameArgs {
   const void* frag;            // fragment blocks (caller's buffer)
-  uint32_t* queue;             // kQueues x kSlots counters, queues kQueueStride apart
-  int32_t slot, clear_slot;    // this frame's counter slot; the slot it clears
+  uint32_t* queue;             // kQueues x kSlots counters, queues kQueueStride apart,
+                               // then the kSlots finish counters, then the FrameState
+  int32_t slot, clear_slot;    // set by the kernel from FrameState::seq
   int32_t n_queues;            // counters in use: min(kQueues, grid)
   int32_t queue_block;         // consecutive work-list positions per counter block (units per tile)
   int32_t n_work;
@@ -61,8 +75,8 @@ struct FrameArgs {
   const float* bg_image;       // [n_tiles][P][4] per-pixel background, or null
   float inv_gamma;
   uint32_t mode;
-  int32_t n_acc;               // accumulation id after this frame (>= 1)
-  float inv_n;                 // 1 / n_acc
+  int32_t n_acc;               // set by the kernel: accumulation id after this frame
+  float inv_n;                 // set by the kernel: 1 / n_acc
   float* finished;             // [n_tiles][P][4]
   float* accum;                // [n_tiles][P][4]
   float* m2;                   // [n_tiles][3][P]
@@ -81,14 +95,14 @@ struct AccumArgs {
   int32_t width, height, tiles_x, n_tiles, tile_w, tile_h, P;
   float inv_gamma;
   uint32_t mode;
-  int32_t n_acc;
-  float inv_n;
+  const FrameState* state;     // n = state->n_acc + 1 (advanced by a separate launch)
 };
 
 struct VarianceArgs {
   const float* var_partial;    // [n_tiles * subs_per_tile]
   float* tile_var;             // [n_tiles]
-  int32_t n_tiles, subs_per_tile, tiles_x, width, height, tile_w, tile_h, n_acc;
+  int32_t n_tiles, subs_per_tile, tiles_x, width, height, tile_w, tile_h;
+  const FrameState* state;     // n = state->n_acc (already advanced by the frame kernel)
 };
 
 struct ValidateArgs {
@@ -102,7 +116,8 @@ struct ValidateArgs {
 struct FrameGlue {
   const float* accum;      // [T][P][4] running mean
   const float* tile_var;   // [T]
-  int width, height, tiles_x, tile_w, tile_h, P, n_acc;
+  const FrameState* state; // n = state->n_acc
+  int width, height, tiles_x, tile_w, tile_h, P;
 };
 struct FrameView {
   FrameGlue glue;
@@ -124,6 +139,8 @@ const void* frame_kernel(int dtype, int kcap, int op);
 dfb_status assign_samples(const float* variance, int32_t n_tiles, int64_t extra, int32_t* counts);
 const void* accumulate_kernel();
 const void* tile_variance_kernel();
+// One thread: state->n_acc = value (value >= 0), or += 1 (value < 0).
+const void* state_kernel();
 const void* validate_kernel(int dtype);
 
 // LDS budget of the K > 32 path for a frame whose largest tile has

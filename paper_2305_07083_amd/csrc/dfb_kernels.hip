@@ -1156,17 +1156,49 @@ constexpr int min_waves(int kcap) {
                                 : (DFB_WAVES_K32 > 0 ? DFB_WAVES_K32 : 1);
 }
 
+__device__ __forceinline__ uint32_t* finish_counters(const FrameArgs& a) {
+  return a.queue + static_cast<size_t>(kQueues) * kQueueStride;
+}
+__device__ __forceinline__ FrameState* frame_state(const FrameArgs& a) {
+  return reinterpret_cast<FrameState*>(a.queue + static_cast<size_t>(kQueues + 1) * kQueueStride);
+}
+
+// The frame's sequence number and accumulation count, read once per
+// workgroup from the device state and shared through LDS.  The load's value
+// is stored to LDS before the barrier, so it has returned before anything
+// else of the workgroup runs; the last workgroup to finish advances the
+// state only after every workgroup has counted itself finished, hence after
+// every read of this frame.
+__device__ __forceinline__ uint32_t read_frame_state(FrameArgs& a, uint32_t* s_state) {
+  if (threadIdx.x == 0) {
+    const FrameState* st = frame_state(a);
+    s_state[0] = __hip_atomic_load(&st->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_state[1] = static_cast<uint32_t>(__hip_atomic_load(&st->n_acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+  lds_barrier();
+  const uint32_t seq = __builtin_amdgcn_readfirstlane(s_state[0]);
+  const int n_prev = static_cast<int>(__builtin_amdgcn_readfirstlane(s_state[1]));
+  a.slot = static_cast<int32_t>(seq % kSlots);
+  a.clear_slot = static_cast<int32_t>((seq + kSlots / 2) % kSlots);
+  a.n_acc = (a.mode & kModeAccumulate) ? n_prev + 1 : n_prev;
+  a.inv_n = a.n_acc > 0 ? 1.f / static_cast<float>(a.n_acc) : 1.f;
+  return seq;
+}
+
 template <typename FT, int KCAP, int OP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(KCAP))))
-frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
+frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
                const int64_t* __restrict__ layer_off, const int32_t* __restrict__ work_list) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_item;
   __shared__ float s_red[4];
+  __shared__ uint32_t s_state[2];
   const int tid = threadIdx.x;
   const int n_waves = static_cast<int>(blockDim.x >> 6);
   const bool wave0 = __builtin_amdgcn_readfirstlane(tid) < 64;  // uniform per wave
-  if (blockIdx.x == 0 && tid < kQueues)  // recycle the slot of the frame kSlots/2 ahead
+  FrameArgs a = args;
+  const uint32_t seq = read_frame_state(a, s_state);
+  if (blockIdx.x == 0 && tid <= kQueues)  // recycle the slot of the frame kSlots/2 ahead (counters, finish count)
     __hip_atomic_store(a.queue + static_cast<size_t>(tid) * kQueueStride + a.clear_slot, 0u, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   const int home = static_cast<int>(blockIdx.x) % a.n_queues;
@@ -1234,6 +1266,19 @@ frame_kernel_t(FrameArgs a, const int32_t* __restrict__ tile_off,
     lds_barrier();
     it = __builtin_amdgcn_readfirstlane(s_item);
   }
+  // Count this workgroup finished; the last one advances the frame state
+  // for the next launch (sequence number, and the accumulation count of an
+  // accumulating frame).  Every queue access of this workgroup has returned
+  // its value before this point.
+  uint32_t done = 0;
+  if (tid == 0)
+    done = __hip_atomic_fetch_add(finish_counters(a) + a.slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  done = __builtin_amdgcn_readfirstlane(done);
+  const bool last = wave0 && done == gridDim.x - 1;
+  if (last && tid == 0)
+    __hip_atomic_store(&frame_state(a)->seq, seq + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (last && tid == 0 && (a.mode & kModeAccumulate))
+    __hip_atomic_store(&frame_state(a)->n_acc, a.n_acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-tile variance of the mean from the units' partial M2 sums, added in
@@ -1246,13 +1291,15 @@ __global__ void __launch_bounds__(256) tile_variance_kernel_t(VarianceArgs a) {
   const int x0 = (t % a.tiles_x) * a.tile_w, y0 = (t / a.tiles_x) * a.tile_h;
   const int wx = a.width - x0, wy = a.height - y0;
   const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
-  a.tile_var[t] = variance_of_mean(sum, inside, a.n_acc);
+  a.tile_var[t] = variance_of_mean(sum, inside, a.state->n_acc);
 }
 
 // Unfused accumulation of the stored finished tiles: one workgroup per tile.
 __global__ void __launch_bounds__(256) accumulate_kernel_t(AccumArgs a) {
   __shared__ float s_red[4];
   const int t = blockIdx.x, tid = threadIdx.x;
+  const int n_acc = a.state->n_acc + 1;  // the state kernel after this launch advances it
+  const float inv_n = 1.f / static_cast<float>(n_acc);
   const int x0 = (t % a.tiles_x) * a.tile_w, y0 = (t / a.tiles_x) * a.tile_h;
   float vs = 0.f;
   for (int p = tid; p < a.P; p += blockDim.x) {
@@ -1261,7 +1308,7 @@ __global__ void __launch_bounds__(256) accumulate_kernel_t(AccumArgs a) {
     const size_t px = static_cast<size_t>(t) * a.P + p;
     const float4 x = reinterpret_cast<const float4*>(a.finished)[px];
     vs += store_pixel(x, px, static_cast<size_t>(t) * 3 * a.P + p, a.P, inside,
-                      (a.mode & ~kModeKeepFinished) | kModeAccumulate, a.n_acc, a.inv_n,
+                      (a.mode & ~kModeKeepFinished) | kModeAccumulate, n_acc, inv_n,
                       a.inv_gamma, nullptr, a.accum, a.m2, a.final_out);
   }
   vs = wave_sum(vs);
@@ -1274,8 +1321,14 @@ __global__ void __launch_bounds__(256) accumulate_kernel_t(AccumArgs a) {
       if (i < n_waves) sum += s_red[i];
     const int wx = a.width - x0, wy = a.height - y0;
     const int inside = (wx < a.tile_w ? wx : a.tile_w) * (wy < a.tile_h ? wy : a.tile_h);
-    if (__lane_id() == 0) a.tile_var[t] = variance_of_mean(sum, inside, a.n_acc);
+    if (__lane_id() == 0) a.tile_var[t] = variance_of_mean(sum, inside, n_acc);
   }
+}
+
+// Accumulation count of a handle's frame state, set (value >= 0) or advanced
+// by one (value < 0), stream-ordered with the frames around it.
+__global__ void state_kernel_t(FrameState* st, int32_t value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->n_acc = value >= 0 ? value : st->n_acc + 1;
 }
 
 // NaN scan of every layer's depth plane: one workgroup per layer.
@@ -1312,6 +1365,8 @@ const void* frame_kernel(int dtype, int kcap, int op) {
 const void* accumulate_kernel() { return reinterpret_cast<const void*>(&accumulate_kernel_t); }
 
 const void* tile_variance_kernel() { return reinterpret_cast<const void*>(&tile_variance_kernel_t); }
+
+const void* state_kernel() { return reinterpret_cast<const void*>(&state_kernel_t); }
 
 const void* validate_kernel(int dtype) {
   return dtype == 0 ? reinterpret_cast<const void*>(&validate_kernel_t<float>)

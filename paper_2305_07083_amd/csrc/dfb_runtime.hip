@@ -82,8 +82,19 @@ struct dfb_ctx {
   float* d_var_partial = nullptr;
   size_t partial_cap = 0;
   uint32_t* d_flag = nullptr;
-  uint32_t* d_queue_ring = nullptr;  // kQueues x kSlots counters
-  unsigned long long frame_seq = 0;  // frame launches so far (selects the counter slot)
+  uint32_t* d_queue_ring = nullptr;  // kQueues x kSlots counters, finish counters, FrameState
+  dfb::FrameState* d_state = nullptr;  // inside d_queue_ring
+
+  // Frame graphs for DFB_REPLAY: one per (fragment buffer, frame mode) of the
+  // current layer table and launch shape; dropped when either changes.
+  struct GraphEntry {
+    const void* frag;
+    uint32_t mode;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  static constexpr int kMaxGraphs = 8;
+  std::vector<GraphEntry> graphs;
 
   // launch shape
   Shape shape{0, 0, 0, 64 * 1024};
@@ -292,9 +303,12 @@ std::vector<Shape> candidates(const dfb_config& c, int max_k) {
   return out;
 }
 
+void drop_graphs(dfb_ctx* h);
+
 // Work list for a shape: every (tile, unit) pair, tiles with more layers
 // first (longest-processing-time order), ties by tile id.
 dfb_status build_work(dfb_ctx* h, const Shape& s) {
+  drop_graphs(h);
   const int sx = h->cfg.tile_w / s.work_w, sy = h->cfg.tile_h / s.work_h;
   h->subs_x = sx;
   h->subs_per_tile = sx * sy;
@@ -332,8 +346,7 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   FrameArgs a{};
   a.frag = h->frag;
   a.queue = h->d_queue_ring;
-  a.slot = static_cast<int32_t>(h->frame_seq % dfb::kSlots);
-  a.clear_slot = static_cast<int32_t>((h->frame_seq + dfb::kSlots / 2) % dfb::kSlots);
+  a.slot = a.clear_slot = 0;  // the kernel takes both from the device frame state
   a.n_queues = 1;  // set by launch_frame once the grid is known
   a.queue_block = h->subs_per_tile;
   a.n_work = h->n_work;
@@ -362,8 +375,8 @@ FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   a.bg_image = h->bg_image;
   a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
   a.mode = mode;
-  a.n_acc = h->acc_n;
-  a.inv_n = h->acc_n > 0 ? 1.f / static_cast<float>(h->acc_n) : 1.f;
+  a.n_acc = 0;    // the kernel takes it from the device frame state
+  a.inv_n = 1.f;
   a.finished = h->finished;
   a.accum = h->accum;
   a.m2 = h->m2;
@@ -401,43 +414,158 @@ dfb::VarianceArgs make_var_args(dfb_ctx* h) {
   v.height = h->cfg.height;
   v.tile_w = h->cfg.tile_w;
   v.tile_h = h->cfg.tile_h;
-  v.n_acc = h->acc_n;
+  v.state = h->d_state;
   return v;
 }
 
-// Launch one frame with the current shape on the caller's stream: the
-// persistent frame kernel, then (accumulating frames) the per-tile variance
-// combine.  With t0/t1 given, the two events bracket the frame kernel alone.
-// Plain launches: a HIP graph of the same two kernels, replayed per frame,
-// took ~14 us more per frame on the 2048^2 frame (157 against 143 us).
-dfb_status launch_frame(dfb_ctx* h, uint32_t mode, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
-  const int threads = 64 * h->shape.waves;
+// Everything one frame's launches take: the persistent frame kernel and,
+// for accumulating frames, the per-tile variance combine.  Nothing in it
+// changes from frame to frame (the frame's counter slot and accumulation
+// count live in the device frame state), so the same launches serve as a
+// graph replayed every frame.
+struct FrameLaunch {
+  const void* func;
+  int grid, threads;
+  size_t lds;
+  bool acc;
+  FrameArgs fa;
+  dfb::VarianceArgs va;
+  const int32_t* tab_off;
+  const int64_t* tab_layer;
+  const int32_t* tab_work;
+  void* fparams[4];
+  void* vparams[1];
+  void bind() {
+    fparams[0] = &fa;
+    fparams[1] = &tab_off;
+    fparams[2] = &tab_layer;
+    fparams[3] = &tab_work;
+    vparams[0] = &va;
+  }
+};
+
+dfb_status prepare_launch(dfb_ctx* h, uint32_t mode, FrameLaunch& L) {
+  L.threads = 64 * h->shape.waves;
   const bool sorting = h->cfg.tile_op == DFB_OP_ALPHA_BLEND;
-  const void* func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap, h->cfg.tile_op);
+  L.func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap, h->cfg.tile_op);
   // the list and averaging operations keep nothing in LDS
-  const size_t lds = sorting ? dfb::frame_lds_bytes(h->kcap, threads, h->max_k, h->shape.big_lds) : 0;
-  const bool acc = (mode & dfb::kModeAccumulate) != 0;
-  int grid = 0;
-  dfb_status st = grid_for(h, func, threads, lds, grid);
+  L.lds = sorting ? dfb::frame_lds_bytes(h->kcap, L.threads, h->max_k, h->shape.big_lds) : 0;
+  L.acc = (mode & dfb::kModeAccumulate) != 0;
+  dfb_status st = grid_for(h, L.func, L.threads, L.lds, L.grid);
   if (st != DFB_OK) return st;
-  if (lds > 64 * 1024) DFB_HIP(h, hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  FrameArgs fa = make_args(h, mode);
-  fa.n_queues = std::min(dfb::kQueues, grid);
-  dfb::VarianceArgs va = make_var_args(h);
-  const int32_t* tab_off = h->d_off;
-  const int64_t* tab_layer = h->d_block;
-  const int32_t* tab_work = h->d_work;
-  void* fparams[] = {&fa, &tab_off, &tab_layer, &tab_work};
-  void* vparams[] = {&va};
+  if (L.lds > 64 * 1024)
+    DFB_HIP(h, hipFuncSetAttribute(L.func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(L.lds)));
+  L.fa = make_args(h, mode);
+  L.fa.n_queues = std::min(dfb::kQueues, L.grid);
+  L.va = make_var_args(h);
+  L.tab_off = h->d_off;
+  L.tab_layer = h->d_block;
+  L.tab_work = h->d_work;
+  L.bind();
+  return DFB_OK;
+}
+
+// Launch one frame with the current shape on the caller's stream.  With
+// t0/t1 given, the two events bracket the frame kernel alone.
+dfb_status launch_frame(dfb_ctx* h, uint32_t mode, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
+  FrameLaunch L;
+  dfb_status st = prepare_launch(h, mode, L);
+  if (st != DFB_OK) return st;
   if (t0) DFB_HIP(h, hipEventRecord(t0, h->stream));
-  DFB_HIP(h, hipLaunchKernel(func, dim3(grid), dim3(threads), fparams, lds, h->stream));
+  DFB_HIP(h, hipLaunchKernel(L.func, dim3(L.grid), dim3(L.threads), L.fparams, L.lds, h->stream));
   if (t1) DFB_HIP(h, hipEventRecord(t1, h->stream));
-  if (acc)
-    DFB_HIP(h, hipLaunchKernel(dfb::tile_variance_kernel(), dim3((h->n_tiles + 255) / 256), dim3(256), vparams, 0,
+  if (L.acc)
+    DFB_HIP(h, hipLaunchKernel(dfb::tile_variance_kernel(), dim3((h->n_tiles + 255) / 256), dim3(256), L.vparams, 0,
                                h->stream));
   DFB_HIP(h, hipGetLastError());
-  h->grid = grid;
-  h->frame_seq += 1;
+  h->grid = L.grid;
+  return DFB_OK;
+}
+
+void drop_graphs(dfb_ctx* h) {
+  for (auto& g : h->graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  h->graphs.clear();
+}
+
+// The frame graph for the current fragment buffer and mode (built on first
+// use): the frame kernel node, then the variance node of an accumulating
+// frame.  Built node by node, not by stream capture, so the handle's stream
+// may be the null stream.
+dfb_status frame_graph(dfb_ctx* h, uint32_t mode, hipGraphExec_t& exec) {
+  for (auto& g : h->graphs)
+    if (g.frag == h->frag && g.mode == mode) {
+      exec = g.exec;
+      return DFB_OK;
+    }
+  FrameLaunch L;
+  dfb_status st = prepare_launch(h, mode, L);
+  if (st != DFB_OK) return st;
+  if (static_cast<int>(h->graphs.size()) >= dfb_ctx::kMaxGraphs) {
+    (void)hipGraphExecDestroy(h->graphs.front().exec);
+    (void)hipGraphDestroy(h->graphs.front().graph);
+    h->graphs.erase(h->graphs.begin());
+  }
+  dfb_ctx::GraphEntry e{h->frag, mode, nullptr, nullptr};
+  DFB_HIP(h, hipGraphCreate(&e.graph, 0));
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(L.func);
+  kp.gridDim = dim3(L.grid);
+  kp.blockDim = dim3(L.threads);
+  kp.sharedMemBytes = static_cast<unsigned>(L.lds);
+  kp.kernelParams = L.fparams;
+  kp.extra = nullptr;
+  hipGraphNode_t fnode = nullptr, vnode = nullptr;
+  hipError_t err = hipGraphAddKernelNode(&fnode, e.graph, nullptr, 0, &kp);
+  if (err == hipSuccess && L.acc) {
+    hipKernelNodeParams vp{};
+    vp.func = const_cast<void*>(dfb::tile_variance_kernel());
+    vp.gridDim = dim3((h->n_tiles + 255) / 256);
+    vp.blockDim = dim3(256);
+    vp.sharedMemBytes = 0;
+    vp.kernelParams = L.vparams;
+    vp.extra = nullptr;
+    err = hipGraphAddKernelNode(&vnode, e.graph, &fnode, 1, &vp);
+  }
+  if (err == hipSuccess) err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+  if (err != hipSuccess) {
+    (void)hipGraphDestroy(e.graph);
+    return hip_fail(h, err, "building the frame graph");
+  }
+  h->graphs.push_back(e);
+  h->grid = L.grid;
+  exec = e.exec;
+  return DFB_OK;
+}
+
+// Whether the handle's stream is being captured into a graph by the caller.
+bool capturing(dfb_ctx* h) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
+// The device accumulation count after everything enqueued so far
+// (synchronises the stream).  Graph replays of a captured accumulating frame
+// advance it without the host seeing each one.
+dfb_status read_acc_count(dfb_ctx* h, int32_t& n) {
+  DFB_HIP(h, hipMemcpyAsync(&n, &h->d_state->n_acc, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+  DFB_HIP(h, hipStreamSynchronize(h->stream));
+  return DFB_OK;
+}
+
+// Stream-ordered update of the device accumulation count (value >= 0: set;
+// < 0: add one).
+dfb_status set_acc_count(dfb_ctx* h, int32_t value) {
+  dfb::FrameState* st = h->d_state;
+  void* params[] = {&st, &value};
+  DFB_HIP(h, hipLaunchKernel(dfb::state_kernel(), dim3(1), dim3(64), params, 0, h->stream));
+  DFB_HIP(h, hipGetLastError());
   return DFB_OK;
 }
 
@@ -545,7 +673,7 @@ dfb_status frame_view(dfb_ctx* h, FrameView* v, bool want_denoised) {
   v->glue.tile_w = h->cfg.tile_w;
   v->glue.tile_h = h->cfg.tile_h;
   v->glue.P = h->P;
-  v->glue.n_acc = h->acc_n;
+  v->glue.state = h->d_state;
   v->final_out = h->final_out;
   v->denoised = h->denoised;
   v->display_mode = display_mode(h->cfg);
@@ -633,9 +761,10 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
     if ((s = alloc_plain(h, &h->final_out, px * 16)) != DFB_OK) return bail(s);
   }
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->tile_var), h->n_tiles * sizeof(float))) != DFB_OK) return bail(s);
-  const size_t queue_bytes = sizeof(uint32_t) * dfb::kQueues * dfb::kQueueStride;
+  const size_t queue_bytes = sizeof(uint32_t) * dfb::kQueueWords;
   static_assert(dfb::kSlots <= dfb::kQueueStride, "a queue's slots fit in its stride");
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_queue_ring), queue_bytes)) != DFB_OK) return bail(s);
+  h->d_state = reinterpret_cast<dfb::FrameState*>(h->d_queue_ring + (dfb::kQueues + 1) * dfb::kQueueStride);
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_flag), 64)) != DFB_OK) return bail(s);
   e = hipMemsetAsync(h->d_queue_ring, 0, queue_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->tile_var, 0, h->n_tiles * sizeof(float), h->stream);
@@ -648,6 +777,7 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
 dfb_status dfb_destroy(dfb_handle h) {
   if (!h) return DFB_ERR_INVALID_ARG;
   (void)hipStreamSynchronize(h->stream);
+  drop_graphs(h);
   for (int i = 0; i < dfb_ctx::kRing; ++i) {
     if (h->ev0[i]) (void)hipEventDestroy(h->ev0[i]);
     if (h->ev1[i]) (void)hipEventDestroy(h->ev1[i]);
@@ -730,6 +860,7 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
   uint64_t dg = fnv1a(counts.data(), counts.size() * sizeof(int32_t));
   if (dg != h->digest || max_k != h->max_k || h->state == State::kEmpty) h->shape_valid = false;
   h->digest = dg;
+  drop_graphs(h);
   h->h_off.swap(off);
   h->h_block.swap(block);
   h->n_layers = n_layers;
@@ -804,6 +935,7 @@ dfb_status dfb_set_background_image(dfb_handle h, const float* image_dev) {
     return fail(h, DFB_ERR_INVALID_ARG, "background image must be 16-byte aligned");
   h->bg_image = image_dev;
   h->cfg.background_image = image_dev;
+  drop_graphs(h);
   return DFB_OK;
 }
 
@@ -812,7 +944,10 @@ dfb_status dfb_assign_samples(dfb_handle h, int64_t extra, int32_t* counts) {
   if (s != DFB_OK) return s;
   if (!counts || extra < 0 || extra > INT32_MAX) return fail(h, DFB_ERR_INVALID_ARG, "bad extra or counts");
   std::vector<float> v(h->n_tiles, INFINITY);  // uniform before two accumulated frames
-  if (h->acc_n >= 2) {
+  int32_t n_acc = 0;
+  s = read_acc_count(h, n_acc);
+  if (s != DFB_OK) return s;
+  if (n_acc >= 2) {
     DFB_HIP(h, hipMemcpyAsync(v.data(), h->tile_var, v.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
     DFB_HIP(h, hipStreamSynchronize(h->stream));
   }
@@ -825,21 +960,38 @@ dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
   dfb_status s = check_usable(h);
   if (s != DFB_OK) return s;
   if (h->state == State::kEmpty) return fail(h, DFB_ERR_STATE, "dfb_set_fragments must come first");
-  if (frame_flags & ~DFB_ACCUMULATE) return fail(h, DFB_ERR_INVALID_ARG, "unknown frame flag");
+  if (frame_flags & ~(DFB_ACCUMULATE | DFB_REPLAY)) return fail(h, DFB_ERR_INVALID_ARG, "unknown frame flag");
+  const bool acc = (frame_flags & DFB_ACCUMULATE) != 0;
+  const bool replay = (frame_flags & DFB_REPLAY) != 0;
+  // Under the caller's stream capture nothing may synchronise or allocate:
+  // the launch shape and the accumulation buffers must already exist.
+  const bool captured = capturing(h);
+  if (captured) {
+    if (!(h->shape_valid && h->work_valid))
+      return fail(h, DFB_ERR_STATE, "the first frame of a new layer layout chooses the launch shape "
+                                    "(synchronously): composite it before capturing");
+    if (acc && !h->accum)
+      return fail(h, DFB_ERR_STATE, "accumulate one frame before capturing an accumulating frame");
+    if (replay) return fail(h, DFB_ERR_INVALID_ARG, "DFB_REPLAY cannot be captured");
+  }
   s = prepare_shape(h);
   if (s != DFB_OK) return s;
   uint32_t mode = display_mode(h->cfg);
   if (h->cfg.flags & DFB_KEEP_FINISHED) mode |= dfb::kModeKeepFinished;
   if (h->cfg.flags & DFB_KEEP_SORT_ORDER) mode |= dfb::kModeKeepOrder;
-  if (frame_flags & DFB_ACCUMULATE) {
+  if (acc) {
     s = ensure_accum(h);
     if (s != DFB_OK) return s;
     mode |= dfb::kModeAccumulate;
-    h->acc_n += 1;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (replay) {
+    s = frame_graph(h, mode, exec);
+    if (s != DFB_OK) return s;
   }
   const int slot = h->ring_pos;
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  const bool timed = h->timing_every > 0 && h->timing_seq++ % h->timing_every == 0;
+  const bool timed = !captured && h->timing_every > 0 && h->timing_seq++ % h->timing_every == 0;
   if (timed) {
     if (!h->ev0[slot]) {
       DFB_HIP(h, hipEventCreate(&h->ev0[slot]));
@@ -852,13 +1004,22 @@ dfb_status dfb_composite_frame(dfb_handle h, uint32_t frame_flags) {
     t0 = h->ev0[slot];
     t1 = h->ev1[slot];
   }
-  s = launch_frame(h, mode, t0, t1);
-  if (s != DFB_OK) return s;
+  if (replay) {
+    // the events bracket the whole graph (frame kernel and variance combine)
+    if (t0) DFB_HIP(h, hipEventRecord(t0, h->stream));
+    DFB_HIP(h, hipGraphLaunch(exec, h->stream));
+    if (t1) DFB_HIP(h, hipEventRecord(t1, h->stream));
+  } else {
+    s = launch_frame(h, mode, t0, t1);
+    if (s != DFB_OK) return s;
+  }
   if (timed) {
     h->pending[slot] = true;
     h->ring_pos = (slot + 1) % dfb_ctx::kRing;
   }
-  h->have_finished = (h->cfg.flags & DFB_KEEP_FINISHED) != 0;
+  if (acc) h->acc_n += 1;
+  // a frame folded into the accumulation already must not be folded again
+  h->have_finished = (h->cfg.flags & DFB_KEEP_FINISHED) != 0 && !acc;
   h->state = State::kComposited;
   return DFB_OK;
 }
@@ -867,10 +1028,12 @@ dfb_status dfb_accumulate(dfb_handle h) {
   dfb_status s = check_usable(h);
   if (s != DFB_OK) return s;
   if (h->state != State::kComposited || !h->have_finished)
-    return fail(h, DFB_ERR_STATE, "dfb_accumulate needs a composited frame with DFB_KEEP_FINISHED");
+    return fail(h, DFB_ERR_STATE, "dfb_accumulate needs a frame composited with DFB_KEEP_FINISHED and without "
+                                  "DFB_ACCUMULATE, not accumulated yet");
+  if (capturing(h) && !h->accum)
+    return fail(h, DFB_ERR_STATE, "accumulate one frame before capturing dfb_accumulate");
   s = ensure_accum(h);
   if (s != DFB_OK) return s;
-  h->acc_n += 1;
   dfb::AccumArgs a{};
   a.finished = h->finished;
   a.accum = h->accum;
@@ -886,17 +1049,21 @@ dfb_status dfb_accumulate(dfb_handle h) {
   a.P = h->P;
   a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
   a.mode = display_mode(h->cfg);
-  a.n_acc = h->acc_n;
-  a.inv_n = 1.f / static_cast<float>(h->acc_n);
+  a.state = h->d_state;
   void* params[] = {&a};
   DFB_HIP(h, hipLaunchKernel(dfb::accumulate_kernel(), dim3(h->n_tiles), dim3(256), params, 0, h->stream));
   DFB_HIP(h, hipGetLastError());
+  s = set_acc_count(h, -1);
+  if (s != DFB_OK) return s;
+  h->acc_n += 1;
   h->have_finished = false;  // one accumulation per finished frame
   return DFB_OK;
 }
 
 dfb_status dfb_reset_accumulation(dfb_handle h) {
   dfb_status s = check_usable(h);
+  if (s != DFB_OK) return s;
+  s = set_acc_count(h, 0);
   if (s != DFB_OK) return s;
   h->acc_n = 0;
   return DFB_OK;
@@ -955,6 +1122,11 @@ dfb_status dfb_synchronize(dfb_handle h) {
 
 dfb_status dfb_get_info(dfb_handle h, dfb_info* out) {
   if (!h || !out) return DFB_ERR_INVALID_ARG;
+  int32_t n_acc = h->acc_n;
+  if (!h->sticky_hip) {
+    dfb_status s = read_acc_count(h, n_acc);
+    if (s != DFB_OK) return s;
+  }
   out->n_tiles = h->n_tiles;
   out->tiles_x = h->tiles_x;
   out->tiles_y = h->tiles_y;
@@ -963,7 +1135,7 @@ dfb_status dfb_get_info(dfb_handle h, dfb_info* out) {
   out->work_w = h->shape.work_w;
   out->work_h = h->shape.work_h;
   out->waves_per_tile = h->shape.waves;
-  out->accumulation_id = h->acc_n;
+  out->accumulation_id = n_acc;
   out->grid_size = h->grid;
   out->n_fragments = static_cast<int64_t>(out->n_layers) * h->P;
   return DFB_OK;

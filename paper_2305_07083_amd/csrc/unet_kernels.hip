@@ -727,8 +727,9 @@ __global__ void frame_to_input_k(FrameGlue g, float* __restrict__ in6) {
   o[1] = mu.y;
   o[2] = mu.z;
   o[3] = mu.w;
-  o[4] = g.n_acc >= 2 ? logf(v > 1e-12f ? v : 1e-12f) : 0.f;
-  o[5] = 1.f / static_cast<float>(g.n_acc);
+  const int n_acc = g.state->n_acc;
+  o[4] = n_acc >= 2 ? logf(v > 1e-12f ? v : 1e-12f) : 0.f;
+  o[5] = 1.f / static_cast<float>(n_acc);
 }
 
 __device__ __forceinline__ uint32_t q8(float x, bool gamma, float inv_gamma) {
@@ -748,7 +749,7 @@ __global__ void frame_from_output_k(FrameGlue g, const float* __restrict__ out3,
   const int y = (t / g.tiles_x) * g.tile_h + q / g.tile_w;
   float4 v = reinterpret_cast<const float4*>(g.accum)[e];
   const float var = g.tile_var[t];
-  const bool fallback = g.n_acc >= 2 && var > tau;   // measured and too noisy: plain mean
+  const bool fallback = g.state->n_acc >= 2 && var > tau;   // measured and too noisy: plain mean
   if (!fallback && x < g.width && y < g.height) {
     const long long p = static_cast<long long>(y) * g.width + x;
     v.x = out3[p * 3];
