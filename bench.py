@@ -26,6 +26,39 @@ METRIC = "composited fragments/s + HBM GB/s % peak; frames-to-PSNR denoised vs p
 HBM_PEAK_GBPS = 8000.0
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def median_mad(xs):
+    """Median and median absolute deviation (unscaled), the statistics the
+    paper reports its timings with."""
+    import numpy as np
+    a = np.asarray(xs, dtype=np.float64)
+    med = float(np.median(a))
+    return med, float(np.median(np.abs(a - med)))
+
+
+def cpu_model():
+    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,12 +70,14 @@ def parse():
     ap.add_argument("--plain", action="store_true", help="composite only (no accumulation)")
     ap.add_argument("--no-denoise", action="store_true",
                     help="skip training / evaluating the denoiser (frames-to-PSNR part of the metric)")
-    ap.add_argument("--denoise-scenes", type=int, default=8)
+    ap.add_argument("--denoise-scenes", type=int, default=16)
     ap.add_argument("--denoise-steps", type=int, default=1000)
     ap.add_argument("--no-ops", action="store_true",
                     help="skip the list / average tile-operation legs")
     ap.add_argument("--no-other", action="store_true",
                     help="skip the 4096x1024 (fp32, fp16) and 8192x8192 sort-path legs")
+    ap.add_argument("--event-frames", type=int, default=30,
+                    help="frames of the separate timing pass with HIP events around every frame kernel")
     ap.add_argument("--time-every", type=int, default=5,
                     help="HIP events around the frame kernel of every n-th timed headline frame "
                          "(each timed frame carries two event records, ~3.5 us each)")
@@ -168,6 +203,11 @@ def denoise_leg(scenes, steps):
         "target": "denoised PSNR >= plain PSNR after 64 frames",
         "ms_64_plain_frames": res["ms_plain"],
         "ms_n_frames_plus_denoise": {int(k): v for k, v in res["ms_denoised"].items()},
+        "timing_note": "ms_64_plain_frames and ms_n_frames_plus_denoise include this harness's device "
+                       "noise draw per frame; the *_compositor_only figures rotate 4 frames drawn up front",
+        "ms_64_plain_frames_compositor_only": res["ms_plain_compositor_only"],
+        "ms_n_frames_plus_denoise_compositor_only": {int(k): v for k, v in
+                                                     res["ms_denoised_compositor_only"].items()},
         "ms_denoise_forward": res["ms_denoise_only"],
         "denoise_roofline": {"bound": "per layer: mfma (bf16) or hbm, whichever is slower",
                              "roofline_ms": roof_us * 1e-3, "achieved_ms": res["ms_denoise_only"],
@@ -284,7 +324,7 @@ def tile_ops_leg(dfb, torch, steps=30, warmup=5, copies=4):
     return out
 
 
-def other_workloads_leg(dfb, torch, steps=10, warmup=3):
+def other_workloads_leg(dfb, torch, steps=10, warmup=3, with_cpu=True):
     """The sort path on the other frame shapes, accumulating frames (the
     4096x1024 progressive case, fp32 and fp16) and plain frames (the 8192x8192
     heavy-tailed case), autotuned, 2 rotating copies (1 for the device-drawn
@@ -294,6 +334,7 @@ def other_workloads_leg(dfb, torch, steps=10, warmup=3):
     out = {}
     dev = torch.device("cuda:0")
     for name, accumulate in (("c3", True), ("c3f16", True), ("c4", False)):
+        log("other workloads: " + name)
         f, desc = make_frame(name)
         if name == "c4":
             copies = [workloads.uniform_values_torch(len(f.layers), f.P, seed=0, device=dev)]
@@ -317,8 +358,10 @@ def other_workloads_leg(dfb, torch, steps=10, warmup=3):
                 c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
                 c.composite(accumulate=accumulate)
             torch.cuda.synchronize()
+            times = dfb.dfb_kernel_times(c.h)
             kms = dfb.dfb_kernel_ms(c.h)
             info = c.info()
+        cpu = oracle_subset_baseline(f, copies[0], torch) if (name == "c4" and with_cpu) else None
         del copies
         torch.cuda.empty_cache()
         px = f.n_tiles * f.P
@@ -328,12 +371,16 @@ def other_workloads_leg(dfb, torch, steps=10, warmup=3):
         out[name] = {"workload": desc + (", composite + accumulate + per-tile variance + RGBA8" if accumulate
                                          else ", composite + RGBA8"),
                      "fragments_per_frame": f.n_fragments, "kernel_ms": kms,
+                     "kernel_ms_median": median_mad(times)[0], "kernel_ms_mad": median_mad(times)[1],
+                     "timed_frames": len(times),
                      "fragments_per_s": f.n_fragments / (kms * 1e-3),
                      "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
                      "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                   "frac": gbps / HBM_PEAK_GBPS,
                                   "traffic": measured_leg_traffic("frame_kernel_other_workloads_counters.txt", name),
                                   "algorithmic_bytes_per_launch": alg}}
+        if cpu is not None:
+            out[name]["cpu_baseline"] = cpu
     return out
 
 
@@ -349,34 +396,123 @@ def assign_samples_ms(dfb, n_tiles=4096, extra=16384, reps=20):
     return (time.perf_counter() - t0) / reps * 1e3
 
 
-def cpu_baseline(f, accumulate, budget_s=12.0):
-    """The FP64 oracle as it stands, on whole frames, repeated for about
-    ``budget_s`` seconds on this host's cores."""
+def cpu_baseline(f, accumulate, runs=3, run_s=3.0):
+    """The FP64 oracle as it stands, on whole frames of the same fragment set
+    (composite, then accumulate + variance + tonemap when accumulating):
+    ``runs`` runs of at least ``run_s`` seconds on all host cores, and
+    ``runs`` single-frame runs on one thread.  Median and MAD of the runs."""
     import numpy as np
     import oracle
     threads = len(os.sched_getaffinity(0))
     mu = np.zeros((f.n_tiles, f.P, 4))
     m2 = np.zeros((f.n_tiles, f.P, 3))
-    frames = 0
-    t0 = time.perf_counter()
-    while True:
-        r = oracle.composite(f.frag, f.layers, f.width, f.height, f.tile_w, f.tile_h,
-                             expected=f.expected, threads=threads)
-        if accumulate:
-            oracle.accumulate(mu, m2, r["rgba"], frames + 1)
-            oracle.tile_variance(m2, np.arange(f.n_tiles), f.width, f.height, f.tile_w, f.tile_h, frames + 1)
-            oracle.tonemap(mu)
-        else:
-            oracle.tonemap(r["rgba"])
-        frames += 1
-        dt = time.perf_counter() - t0
-        if dt >= budget_s:
-            break
-    return {"value": f.n_fragments * frames / dt, "unit": "fragments/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d whole frames of the same fragment set (%d fragments each), %s, %.1f s"
-                      % (frames, f.n_fragments,
-                         "composite+accumulate+variance+tonemap" if accumulate else "composite+tonemap", dt)}
+
+    def one_run(n_threads, min_s):
+        mu[...] = 0.0
+        m2[...] = 0.0
+        frames = 0
+        t0 = time.perf_counter()
+        while True:
+            r = oracle.composite(f.frag, f.layers, f.width, f.height, f.tile_w, f.tile_h,
+                                 expected=f.expected, threads=n_threads)
+            if accumulate:
+                oracle.accumulate(mu, m2, r["rgba"], frames + 1)
+                oracle.tile_variance(m2, np.arange(f.n_tiles), f.width, f.height, f.tile_w, f.tile_h, frames + 1)
+                oracle.tonemap(mu)
+            else:
+                oracle.tonemap(r["rgba"])
+            frames += 1
+            dt = time.perf_counter() - t0
+            if dt >= min_s:
+                return f.n_fragments * frames / dt, frames, dt
+
+    multi = [one_run(threads, run_s) for _ in range(runs)]
+    single = [one_run(1, 0.0) for _ in range(runs)]
+    med, mad = median_mad([r[0] for r in multi])
+    med1, mad1 = median_mad([r[0] for r in single])
+    what = "composite+accumulate+variance+tonemap" if accumulate else "composite+tonemap"
+    return {"value": med, "unit": "fragments/s", "cores": threads, "kind": "oracle",
+            "sample": "%d runs of %s whole frames of the same fragment set (%d fragments each), %s, on %d "
+                      "threads; median of the runs"
+                      % (runs, "/".join(str(r[1]) for r in multi), f.n_fragments, what, threads),
+            "mad": mad, "runs": [r[0] for r in multi],
+            "single_thread": {"value": med1, "mad": mad1, "runs": [r[0] for r in single],
+                              "sample": "%d runs of 1 whole frame on 1 thread" % runs},
+            "cpu_model": cpu_model()}
+
+
+def oracle_subset_baseline(f, dev_frag, torch, every=50, runs=3):
+    """The FP64 oracle on a K-stratified sample of the 8192x8192 frame's
+    tiles: the tiles sorted by layer count, every ``every``-th taken, so the
+    sample's layer-count mix follows the frame's.  Their blocks are copied
+    from the device (the full 57.6 GB set does not fit host memory) and
+    composited + tonemapped on all host cores; fragments/s of the sample
+    stands for the whole frame (the oracle's cost per fragment depends on K,
+    which the sample spans in proportion)."""
+    import numpy as np
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    counts = np.asarray(f.expected)
+    order = np.argsort(counts, kind="stable")
+    tiles = np.sort(order[every // 2::every]).astype(np.int32)
+    sel = np.isin(f.layers["tile_id"], tiles)
+    sub = f.layers[sel].copy()
+    idx = torch.from_numpy(sub["block"].astype(np.int64)).to(dev_frag.device)
+    host = dev_frag.index_select(0, idx).cpu().numpy()
+    del idx
+    sub["block"] = np.arange(len(sub))
+    n_frag = len(sub) * f.P
+    rates = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        r = oracle.composite(host, sub, f.width, f.height, f.tile_w, f.tile_h, tiles=tiles, threads=threads)
+        oracle.tonemap(r["rgba"])
+        rates.append(n_frag / (time.perf_counter() - t0))
+    med, mad = median_mad(rates)
+    return {"value": med, "unit": "fragments/s", "cores": threads, "kind": "oracle", "mad": mad, "runs": rates,
+            "sample": "%d of %d tiles (every %dth by layer count: K %d..%d), %d fragments = %.2f%% of the frame's; "
+                      "composite + tonemap, median of %d runs; the whole frame at this rate: %.0f s"
+                      % (len(tiles), f.n_tiles, every, int(counts[tiles].min()), int(counts[tiles].max()), n_frag,
+                         100.0 * n_frag / f.n_fragments, runs, f.n_fragments / med),
+            "cpu_model": cpu_model()}
+
+
+def c1_latency_leg(dfb, torch, frames=30, warmup=10):
+    """The 256x256 uniform frame (4 ranks on every tile, 5.2 MB: cache
+    resident, so latency rather than a roofline): per-frame kernel time from
+    HIP events on every frame, and the end-to-end latency of one
+    dfb_set_fragments + dfb_composite_frame + synchronise from the host."""
+    import workloads
+    f = workloads.c1()
+    buf = torch.from_numpy(f.frag).to("cuda:0")
+    cfg = dfb.make_config(f.width, f.height, f.tile_w, f.tile_h, work=0, waves=0)
+    with dfb.Compositor(cfg, torch.cuda.current_stream().cuda_stream) as c:
+        c.set_fragments(buf, f.frag.shape[0], f.layers, f.expected)
+        c.composite()
+        for _ in range(warmup):
+            c.composite()
+        torch.cuda.synchronize()
+        dfb.dfb_set_timing(c.h, 1)
+        for _ in range(frames):
+            c.set_fragments(buf, f.frag.shape[0], f.layers, f.expected)
+            c.composite()
+        k_med, k_mad = median_mad(dfb.dfb_kernel_times(c.h) * 1e3)
+        dfb.dfb_set_timing(c.h, 0)
+        lat = []
+        for _ in range(frames):
+            t0 = time.perf_counter()
+            c.set_fragments(buf, f.frag.shape[0], f.layers, f.expected)
+            c.composite()
+            dfb.dfb_synchronize(c.h)
+            lat.append((time.perf_counter() - t0) * 1e6)
+        info = c.info()
+    l_med, l_mad = median_mad(lat)
+    return {"workload": "256x256 frame, 64x64 tiles, 4 ranks on every tile, fp32, composite + RGBA8",
+            "fragments_per_frame": f.n_fragments, "kernel_us_median": k_med, "kernel_us_mad": k_mad,
+            "end_to_end_us_median": l_med, "end_to_end_us_mad": l_mad, "frames": frames,
+            "fragments_per_s": f.n_fragments / (k_med * 1e-6),
+            "work_tile": [info.work_w, info.work_h], "waves_per_tile": info.waves_per_tile,
+            "note": "5.2 MB working set, cache resident: a latency figure, no roofline claim"}
 
 
 def main():
@@ -428,6 +564,32 @@ def main():
         wall = time.perf_counter() - t0
         kernel_ms = dfb.dfb_kernel_ms(c.h)
         info = c.info()
+        # a separate timing pass: HIP events around every frame kernel
+        dfb.dfb_set_timing(c.h, 1)
+        for i in range(args.event_frames):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite(accumulate=accumulate)
+        ev_ms = dfb.dfb_kernel_times(c.h)
+        dfb.dfb_set_timing(c.h, 0)
+        # the same frames launched as replays of the handle's frame graphs
+        # (one per input copy): wall time per frame, then events around every
+        # replay (frame kernel + variance combine)
+        for i in range(max(len(copies), 3)):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite(accumulate=accumulate, replay=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite(accumulate=accumulate, replay=True)
+        torch.cuda.synchronize()
+        graph_wall = time.perf_counter() - t0
+        dfb.dfb_set_timing(c.h, 1)
+        for i in range(args.event_frames):
+            c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
+            c.composite(accumulate=accumulate, replay=True)
+        graph_ms = dfb.dfb_kernel_times(c.h)
+        dfb.dfb_set_timing(c.h, 0)
     frag_bytes = 10 if f16 else 20
     px = f.n_tiles * f.P
     per_px = 4 + (56 if accumulate else 0)       # RGBA8 out (+ mean and M2 read and written)
@@ -457,6 +619,17 @@ def main():
         "kernel_ms": kernel_ms,
         "kernel_timing": "HIP events around the frame kernel of 1 in every %d of the %d timed frames"
                          % (max(1, args.time_every), args.steps),
+        "kernel_timing_every_frame": {
+            "frames": int(len(ev_ms)), "median_ms": median_mad(ev_ms)[0], "mad_ms": median_mad(ev_ms)[1],
+            "mean_ms": float(np.mean(ev_ms)),
+            "achieved_gbps_median": alg_bytes / (median_mad(ev_ms)[0] * 1e-3) / 1e9,
+            "how": "a separate pass after the timed one: HIP events around every frame kernel"},
+        "graph_replay": {
+            "wall_ms_per_frame": graph_wall / args.steps * 1e3,
+            "stream_launch_wall_ms_per_frame": wall / args.steps * 1e3,
+            "events_median_ms": median_mad(graph_ms)[0], "events_mad_ms": median_mad(graph_ms)[1],
+            "how": "DFB_REPLAY: each frame a hipGraphLaunch of the handle's graph (frame kernel + variance "
+                   "combine, one graph per input copy); events bracket the whole graph"},
         "host_ms": {"ingest_new_layout": ingest_ms, "set_fragments_same_layout": same_layout_ms,
                     "assign_samples_4096_tiles": assign_samples_ms(dfb)},
         "hbm_gbps_algorithmic": achieved,
@@ -471,16 +644,24 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+    log("headline done: %.4f ms per frame, kernel %.4f ms" % (ms_per_step, kernel_ms))
     if not args.no_cpu and args.workload != "c4":
         out["cpu_baseline"] = cpu_baseline(f, accumulate)
+        log("cpu baseline done")
+    if args.workload == "c2":
+        out["c1_latency"] = c1_latency_leg(dfb, torch)
+        log("c1 latency done")
     if not args.no_ops and args.workload == "c2":
         out["tile_ops"] = tile_ops_leg(dfb, torch)
+        log("tile ops done")
     if not args.no_other and args.workload == "c2":
         del copies
         torch.cuda.empty_cache()
-        out["other_workloads"] = other_workloads_leg(dfb, torch)
+        out["other_workloads"] = other_workloads_leg(dfb, torch, with_cpu=not args.no_cpu)
+        log("other workloads done")
     if not args.no_denoise and args.workload == "c2":
         out["denoise"] = denoise_leg(args.denoise_scenes, args.denoise_steps)
+        log("denoise done")
     print(json.dumps(out), flush=True)
 
 

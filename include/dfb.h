@@ -324,6 +324,12 @@ dfb_status dfb_get_info(dfb_handle h, dfb_info* out);
 dfb_status dfb_set_timing(dfb_handle h, int every);
 double dfb_kernel_ms(dfb_handle h);
 
+/* The individual timings behind dfb_kernel_ms (plumbing): copies the first
+ * min(cap, count) per-frame times (ms, frame order) to ms (host float[cap])
+ * and returns count, the number timed since dfb_set_timing; -1 on a bad
+ * argument or HIP error.  Waits for the timed frames to finish. */
+int32_t dfb_kernel_times(dfb_handle h, float* ms, int32_t cap);
+
 /* Host-only check of one frame's layer list against a config, without a GPU:
  * the same validation dfb_set_fragments does.  counts: nullable int32[n_tiles]
  * that receives each tile's layer count. */

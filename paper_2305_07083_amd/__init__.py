@@ -41,7 +41,7 @@ DFB_REPLAY = 0x2
 EXPORTED = (
     "dfb_create", "dfb_destroy", "dfb_set_fragments", "dfb_composite_frame", "dfb_accumulate",
     "dfb_reset_accumulation", "dfb_read_tiles", "dfb_buffer_bytes", "dfb_synchronize",
-    "dfb_get_info", "dfb_set_timing", "dfb_kernel_ms", "dfb_validate_layers", "dfb_last_error",
+    "dfb_get_info", "dfb_set_timing", "dfb_kernel_ms", "dfb_kernel_times", "dfb_validate_layers", "dfb_last_error",
     "dfb_status_string", "dfb_set_background_image", "dfb_set_fragments_tree", "dfb_tree_create",
     "dfb_tree_destroy", "dfb_tree_new_frame", "dfb_tree_add", "dfb_tree_query",
     "dfb_assign_samples_host", "dfb_assign_samples",
@@ -121,6 +121,7 @@ def load():
         "dfb_get_info": ([P, ctypes.POINTER(Info)], I32),
         "dfb_set_timing": ([P, ctypes.c_int], I32),
         "dfb_kernel_ms": ([P], ctypes.c_double),
+        "dfb_kernel_times": ([P, P, I32], I32),
         "dfb_validate_layers": ([ctypes.POINTER(Config), I64, P, I32, P, P], I32),
         "dfb_last_error": ([P], ctypes.c_char_p),
         "dfb_status_string": ([I32], ctypes.c_char_p),
@@ -250,6 +251,18 @@ def dfb_set_timing(h, every=1):
 
 def dfb_kernel_ms(h) -> float:
     return float(load().dfb_kernel_ms(h))
+
+
+def dfb_kernel_times(h):
+    """Every per-frame timing (ms) since dfb_set_timing, in frame order."""
+    lib = load()
+    n = lib.dfb_kernel_times(h, None, 0)
+    if n < 0:
+        raise DfbError(DFB_ERR_HIP, "dfb_kernel_times")
+    out = np.zeros(n, dtype=np.float32)
+    if n:
+        lib.dfb_kernel_times(h, out.ctypes.data, n)
+    return out
 
 
 def dfb_validate_layers(cfg: Config, n_blocks, layers, expected=None):

@@ -115,6 +115,7 @@ struct dfb_ctx {
   int ring_pos = 0;
   double time_sum_ms = 0.0;
   int time_n = 0;
+  std::vector<float> times_ms;  // every harvested timing since dfb_set_timing, in frame order
 };
 
 namespace {
@@ -628,6 +629,7 @@ dfb_status harvest(dfb_ctx* h, int slot) {
   DFB_HIP(h, hipEventElapsedTime(&ms, h->ev0[slot], h->ev1[slot]));
   h->time_sum_ms += ms;
   h->time_n += 1;
+  h->times_ms.push_back(ms);
   h->pending[slot] = false;
   return DFB_OK;
 }
@@ -1147,15 +1149,36 @@ dfb_status dfb_set_timing(dfb_handle h, int every) {
   h->timing_seq = 0;
   h->time_sum_ms = 0.0;
   h->time_n = 0;
+  h->times_ms.clear();
   for (int i = 0; i < dfb_ctx::kRing; ++i) h->pending[i] = false;
+  return DFB_OK;
+}
+
+// Harvest the pending timings oldest first (the ring is filled in order
+// from ring_pos), so times_ms stays in frame order.
+dfb_status harvest_all(dfb_ctx* h) {
+  for (int k = 0; k < dfb_ctx::kRing; ++k) {
+    const int i = (h->ring_pos + k) % dfb_ctx::kRing;
+    if (h->pending[i]) {
+      dfb_status s = harvest(h, i);
+      if (s != DFB_OK) return s;
+    }
+  }
   return DFB_OK;
 }
 
 double dfb_kernel_ms(dfb_handle h) {
   if (!h) return -1.0;
-  for (int i = 0; i < dfb_ctx::kRing; ++i)
-    if (h->pending[i] && harvest(h, i) != DFB_OK) return -1.0;
+  if (harvest_all(h) != DFB_OK) return -1.0;
   return h->time_n ? h->time_sum_ms / h->time_n : -1.0;
+}
+
+int32_t dfb_kernel_times(dfb_handle h, float* ms, int32_t cap) {
+  if (!h || cap < 0 || (cap > 0 && !ms)) return -1;
+  if (harvest_all(h) != DFB_OK) return -1;
+  const int32_t n = static_cast<int32_t>(std::min<size_t>(h->times_ms.size(), static_cast<size_t>(cap)));
+  std::copy(h->times_ms.begin(), h->times_ms.begin() + n, ms);
+  return static_cast<int32_t>(h->times_ms.size());
 }
 
 }  // extern "C"

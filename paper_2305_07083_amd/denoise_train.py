@@ -196,6 +196,36 @@ def evaluate(net, frame, vmax, ref, n_plain=64, seed=12345, tau_factor=2.0):
         ev1.record()
         torch.cuda.synchronize()
         res["ms_denoised"][n] = ev0.elapsed_time(ev1)
+    # the same without the per-frame noise draw of this harness: four noisy
+    # frames drawn up front and rotated, so only the compositor (and the
+    # denoiser) run in the timed region
+    frames = [acc.noise.next().clone() for _ in range(4)]
+
+    def composite_only(n):
+        for i in range(n):
+            x = frames[i % 4]
+            acc.c.set_fragments(x, x.shape[0], acc.f.layers, acc.f.expected)
+            acc.c.composite(accumulate=True)
+
+    acc.c.reset()
+    composite_only(2)
+    torch.cuda.synchronize()
+    ev0.record()
+    composite_only(n_plain)
+    ev1.record()
+    torch.cuda.synchronize()
+    res["ms_plain_compositor_only"] = ev0.elapsed_time(ev1)
+    res["ms_denoised_compositor_only"] = {}
+    for n in N_INPUTS:
+        acc.c.reset()
+        torch.cuda.synchronize()
+        ev0.record()
+        composite_only(n)
+        dfb.dfb_denoise(acc.c.h, net, float("inf"))
+        ev1.record()
+        torch.cuda.synchronize()
+        res["ms_denoised_compositor_only"][n] = ev0.elapsed_time(ev1)
+    del frames
     # denoise alone
     ev0.record()
     for _ in range(5):
@@ -207,7 +237,7 @@ def evaluate(net, frame, vmax, ref, n_plain=64, seed=12345, tau_factor=2.0):
     return res
 
 
-def run(scenes=12, steps=1500, batch=8, crop=128, size=2048, log=print):
+def run(scenes=16, steps=1500, batch=8, crop=128, size=2048, log=print):
     # scenes first: the worker processes start before this process touches the GPU
     t0 = time.perf_counter()
     train_frames = make_scenes(range(1, scenes + 1), size=size)
@@ -271,7 +301,7 @@ def time_kernels(size=2048, passes=5, steps=10, batch=8, crop=128, log=print):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--scenes", type=int, default=12)
+    ap.add_argument("--scenes", type=int, default=16)
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--crop", type=int, default=128)
