@@ -336,6 +336,40 @@ int32_t dfb_kernel_times(dfb_handle h, float* ms, int32_t cap);
 dfb_status dfb_validate_layers(const dfb_config* cfg, int64_t n_blocks, const dfb_layer* layers,
                                int32_t n_layers, const int32_t* expected, int32_t* counts);
 
+/* Entry point for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): one plain frame -- the same frame kernel as
+ * dfb_composite_frame, without accumulation -- into caller-owned outputs.
+ * It calls no allocator: its work queue's counters, the frame state and the
+ * longest-first work list (built on the device from tile_off_dev) live in a
+ * static device array of DFB_NOALLOC_MAX_WORK work units plus 72 KiB, one
+ * per GPU, held until the process ends; the first call on a device clears
+ * it (a fill kernel on hip_stream).  All calls on one GPU share that array:
+ * calls that overlap in time on one GPU (different streams or threads)
+ * race and give wrong results; calls ordered on one stream are safe.
+ *   cfg           as for dfb_create; work_w, work_h and waves_per_tile must
+ *                 be set (no autotuning); DFB_VALIDATE and
+ *                 DFB_KEEP_SORT_ORDER -> DFB_ERR_UNSUPPORTED.
+ *   frag_dev      fragment blocks (layout of dfb_layer), cfg.frag_dtype.
+ *   tile_off_dev  device int32[n_tiles + 1]: tile t's layers are entries
+ *                 tile_off[t] .. tile_off[t+1]-1 of layer_off_dev.
+ *   layer_off_dev device int64[n_layers]: element offset block * 5 * P of
+ *                 each layer's block in frag_dev; a tile's layers ordered by
+ *                 ascending source_id (depth ties go to the earlier one).
+ *   max_layers    at least the largest layer count of any tile (<= 4096):
+ *                 it picks the kernel; a tile with more layers is not
+ *                 composited correctly.
+ *   final_dev     display pixels per cfg.format (NULL for DFB_FMT_NONE).
+ *   finished_dev  float[n_tiles][P][4] with DFB_KEEP_FINISHED, else NULL.
+ *   hip_stream    every launch is enqueued on it; nothing synchronises.
+ * A frame of more than DFB_NOALLOC_MAX_WORK work units (n_tiles * units per
+ * tile) -> DFB_ERR_UNSUPPORTED before any GPU work.  Errors are reported in
+ * dfb_last_error(NULL). */
+#define DFB_NOALLOC_MAX_WORK 1048576
+dfb_status dfb_composite_noalloc(const dfb_config* cfg, const void* frag_dev, const int32_t* tile_off_dev,
+                                 const int64_t* layer_off_dev, int32_t max_layers, void* final_dev,
+                                 float* finished_dev, void* hip_stream);
+
 /* Human-readable last error of the handle (or of the last failed create when
  * h is NULL). */
 const char* dfb_last_error(dfb_handle h);

@@ -44,7 +44,7 @@ EXPORTED = (
     "dfb_get_info", "dfb_set_timing", "dfb_kernel_ms", "dfb_kernel_times", "dfb_validate_layers", "dfb_last_error",
     "dfb_status_string", "dfb_set_background_image", "dfb_set_fragments_tree", "dfb_tree_create",
     "dfb_tree_destroy", "dfb_tree_new_frame", "dfb_tree_add", "dfb_tree_query",
-    "dfb_assign_samples_host", "dfb_assign_samples",
+    "dfb_assign_samples_host", "dfb_assign_samples", "dfb_composite_noalloc",
     # dfb_denoise.h
     "dfb_denoiser_param_count", "dfb_denoiser_create", "dfb_denoiser_destroy", "dfb_denoiser_set_params",
     "dfb_denoiser_get_params", "dfb_denoiser_forward", "dfb_denoiser_train_step",
@@ -134,6 +134,7 @@ def load():
         "dfb_tree_query": ([P, I32, P, P, P], I32),
         "dfb_assign_samples_host": ([P, I32, I64, P], I32),
         "dfb_assign_samples": ([P, I64, P], I32),
+        "dfb_composite_noalloc": ([ctypes.POINTER(Config), P, P, P, I32, P, P, P], I32),
         "dfb_denoiser_param_count": ([], I64),
         "dfb_denoiser_create": ([ctypes.POINTER(UnetConfig), P, ctypes.POINTER(P)], I32),
         "dfb_denoiser_destroy": ([P], I32),
@@ -308,6 +309,32 @@ def dfb_assign_samples_host(variance, extra):
     if st != DFB_OK:
         raise DfbError(st, load().dfb_status_string(st).decode())
     return counts
+
+
+NOALLOC_MAX_WORK = 1048576
+
+
+def dfb_composite_noalloc(cfg: Config, frag_dev, tile_off_dev, layer_off_dev, max_layers, final_dev,
+                          finished_dev=None, stream=0):
+    """One plain frame into caller-owned device outputs, with no allocation
+    (device CSR tables: tile_off int32[n_tiles + 1], layer_off int64 element
+    offsets block * 5 * P, each tile's layers by ascending source id)."""
+    st = load().dfb_composite_noalloc(ctypes.byref(cfg), _ptr(frag_dev), _ptr(tile_off_dev), _ptr(layer_off_dev),
+                                      int(max_layers), _ptr(final_dev), _ptr(finished_dev), stream)
+    _check(st)
+
+
+def layer_tables(layers, n_tiles, P):
+    """The per-tile layer table of a layer list, as dfb_composite_noalloc
+    takes it (host arrays): tile_off int32[n_tiles + 1], layer_off int64
+    (block * 5 * P, per tile by ascending source id) and the largest count."""
+    lay = np.asarray(layers)
+    counts = np.bincount(lay["tile_id"], minlength=n_tiles).astype(np.int64)
+    off = np.zeros(n_tiles + 1, dtype=np.int32)
+    off[1:] = np.cumsum(counts)
+    order = np.lexsort((lay["source_id"], lay["tile_id"]))
+    layer_off = lay["block"][order].astype(np.int64) * 5 * P
+    return off, layer_off, int(counts.max()) if n_tiles else 0
 
 
 def dfb_assign_samples(h, extra, n_tiles):

@@ -141,6 +141,12 @@ const void* accumulate_kernel();
 const void* tile_variance_kernel();
 // One thread: state->n_acc = value (value >= 0), or += 1 (value < 0).
 const void* state_kernel();
+// (uint32_t* p, uint32_t v, int64_t n): p[0..n) = v, any grid.
+const void* fill_u32_kernel();
+// (const int32_t* tile_off, int32_t n_tiles, int32_t subs, int32_t* work):
+// the longest-first work list, one workgroup of kLptThreads lanes.
+const void* lpt_work_kernel();
+constexpr int kLptThreads = 1024;
 const void* validate_kernel(int dtype);
 
 // LDS budget of the K > 32 path for a frame whose largest tile has

@@ -1209,7 +1209,7 @@ frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
   while (it < a.n_work) {
     // the next unit's ticket is taken now and read after this unit's work
     const uint32_t next = wave0 ? take_ticket(q) : 0u;
-    const int w = work_list[it];
+    const int w = work_list ? work_list[it] : it;
     Unit u;
     u.t = w / a.subs_per_tile;
     const int s = w - u.t * a.subs_per_tile;
@@ -1331,6 +1331,72 @@ __global__ void state_kernel_t(FrameState* st, int32_t value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) st->n_acc = value >= 0 ? value : st->n_acc + 1;
 }
 
+// n words of p set to v (grid-stride).
+__global__ void fill_u32_kernel_t(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// Longest-first work list on the device, from the per-tile CSR offsets:
+// a counting sort of the tiles by layer count, descending (one workgroup of
+// kLptThreads lanes; equal counts in any order, which changes only the
+// order units are taken in, never a result), then every tile's units in
+// order.  work[pos * subs + u] = t * subs + u for the tile t at sorted
+// position pos.
+constexpr int kLptBins = kMaxLayers + 1;                                // K = 0 .. kMaxLayers
+constexpr int kLptPer = (kLptBins + kLptThreads - 1) / kLptThreads;    // bins per lane in the scan
+__global__ void __launch_bounds__(kLptThreads) lpt_work_kernel_t(const int32_t* __restrict__ tile_off,
+                                                                 int32_t n_tiles, int32_t subs,
+                                                                 int32_t* __restrict__ work) {
+  __shared__ int32_t cnt[kLptBins];     // bin j holds layer count K = kMaxLayers - j
+  __shared__ int32_t wave_tot[kLptThreads / 64];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < kLptBins; j += kLptThreads) cnt[j] = 0;
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += kLptThreads) {
+    int K = tile_off[t + 1] - tile_off[t];
+    K = K < 0 ? 0 : (K > kMaxLayers ? kMaxLayers : K);
+    atomicAdd(&cnt[kMaxLayers - K], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the bins: each lane sums kLptPer consecutive bins,
+  // the lane sums are scanned within waves and across the waves
+  int local[kLptPer];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < kLptPer; ++i) {
+    const int j = tid * kLptPer + i;
+    local[i] = j < kLptBins ? cnt[j] : 0;
+    sum += local[i];
+  }
+  int incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if ((tid & 63) >= o) incl += v;
+  }
+  if ((tid & 63) == 63) wave_tot[tid >> 6] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < (tid >> 6); ++w) base += wave_tot[w];
+  int run = base + incl - sum;   // exclusive prefix of this lane's first bin
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kLptPer; ++i) {
+    const int j = tid * kLptPer + i;
+    if (j < kLptBins) cnt[j] = run;
+    run += local[i];
+  }
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += kLptThreads) {
+    int K = tile_off[t + 1] - tile_off[t];
+    K = K < 0 ? 0 : (K > kMaxLayers ? kMaxLayers : K);
+    const int pos = atomicAdd(&cnt[kMaxLayers - K], 1);
+    for (int u = 0; u < subs; ++u) work[static_cast<int64_t>(pos) * subs + u] = t * subs + u;
+  }
+}
+
 // NaN scan of every layer's depth plane: one workgroup per layer.
 template <typename FT>
 __global__ void __launch_bounds__(256) validate_kernel_t(ValidateArgs a) {
@@ -1367,6 +1433,10 @@ const void* accumulate_kernel() { return reinterpret_cast<const void*>(&accumula
 const void* tile_variance_kernel() { return reinterpret_cast<const void*>(&tile_variance_kernel_t); }
 
 const void* state_kernel() { return reinterpret_cast<const void*>(&state_kernel_t); }
+
+const void* fill_u32_kernel() { return reinterpret_cast<const void*>(&fill_u32_kernel_t); }
+
+const void* lpt_work_kernel() { return reinterpret_cast<const void*>(&lpt_work_kernel_t); }
 
 const void* validate_kernel(int dtype) {
   return dtype == 0 ? reinterpret_cast<const void*>(&validate_kernel_t<float>)

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -343,41 +344,50 @@ dfb_status ensure_accum(dfb_ctx* h) {
   return DFB_OK;
 }
 
-FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
+// Launch arguments of a frame from the geometry alone: the buffers are
+// filled in by the caller.
+FrameArgs base_args(const dfb_config& c, int tiles_x, int n_tiles, const Shape& sh, const void* frag,
+                    uint32_t mode) {
   FrameArgs a{};
-  a.frag = h->frag;
-  a.queue = h->d_queue_ring;
+  a.frag = frag;
   a.slot = a.clear_slot = 0;  // the kernel takes both from the device frame state
-  a.n_queues = 1;  // set by launch_frame once the grid is known
-  a.queue_block = h->subs_per_tile;
-  a.n_work = h->n_work;
-  a.width = h->cfg.width;
-  a.height = h->cfg.height;
-  a.tiles_x = h->tiles_x;
-  a.n_tiles = h->n_tiles;
-  a.tile_w = h->cfg.tile_w;
-  a.tile_h = h->cfg.tile_h;
-  a.P = h->P;
-  a.work_w = h->shape.work_w;
-  a.work_h = h->shape.work_h;
-  a.subs_x = h->subs_x;
-  a.subs_per_tile = h->subs_per_tile;
-  a.work_px = h->shape.work_w * h->shape.work_h;
-  a.big_lds = h->shape.big_lds;
+  a.n_queues = 1;             // set once the grid is known
+  const int sx = c.tile_w / sh.work_w, sy = c.tile_h / sh.work_h;
+  a.subs_x = sx;
+  a.subs_per_tile = sx * sy;
+  a.queue_block = a.subs_per_tile;
+  a.n_work = n_tiles * a.subs_per_tile;
+  a.width = c.width;
+  a.height = c.height;
+  a.tiles_x = tiles_x;
+  a.n_tiles = n_tiles;
+  a.tile_w = c.tile_w;
+  a.tile_h = c.tile_h;
+  a.P = c.tile_w * c.tile_h;
+  a.work_w = sh.work_w;
+  a.work_h = sh.work_h;
+  a.work_px = sh.work_w * sh.work_h;
+  a.big_lds = sh.big_lds;
   a.work_shift = -1;
   for (int k = 0; k < 16; ++k)
-    if ((1 << k) == h->shape.work_w) a.work_shift = k;
+    if ((1 << k) == sh.work_w) a.work_shift = k;
   // 16-byte plane loads of V = 16 / sizeof(element) pixels need aligned
   // blocks (P % V == 0 follows from tile_w % V == 0) and rows of whole vectors
-  const int V = h->cfg.frag_dtype == DFB_F16 ? 8 : 4;
-  a.vec_ok = (reinterpret_cast<uintptr_t>(h->frag) % 16 == 0) && h->cfg.tile_w % V == 0 &&
-             h->shape.work_w % V == 0;
-  for (int c = 0; c < 4; ++c) a.bg[c] = h->cfg.background[c];
-  a.bg_image = h->bg_image;
-  a.inv_gamma = 1.f / h->cfg.tonemap_gamma;
+  const int V = c.frag_dtype == DFB_F16 ? 8 : 4;
+  a.vec_ok = (reinterpret_cast<uintptr_t>(frag) % 16 == 0) && c.tile_w % V == 0 && sh.work_w % V == 0;
+  for (int k = 0; k < 4; ++k) a.bg[k] = c.background[k];
+  a.bg_image = c.background_image;
+  a.inv_gamma = 1.f / c.tonemap_gamma;
   a.mode = mode;
   a.n_acc = 0;    // the kernel takes it from the device frame state
   a.inv_n = 1.f;
+  return a;
+}
+
+FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
+  FrameArgs a = base_args(h->cfg, h->tiles_x, h->n_tiles, h->shape, h->frag, mode);
+  a.queue = h->d_queue_ring;
+  a.bg_image = h->bg_image;
   a.finished = h->finished;
   a.accum = h->accum;
   a.m2 = h->m2;
@@ -396,12 +406,18 @@ uint32_t display_mode(const dfb_config& c) {
   return m;
 }
 
-dfb_status grid_for(dfb_ctx* h, const void* func, int threads, size_t lds, int& grid) {
+// Persistent grid: as many workgroups as fit on the chip at once, at most
+// one per work unit.
+dfb_status grid_of(dfb_ctx* h, const void* func, int threads, size_t lds, int n_work, int n_cu, int& grid) {
   int per_cu = 0;
   DFB_HIP(h, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, threads, lds));
   if (per_cu < 1) return fail(h, DFB_ERR_UNSUPPORTED, "kernel does not fit on a compute unit with this shape");
-  grid = std::max(1, std::min(h->n_work, per_cu * h->n_cu));
+  grid = std::max(1, std::min(n_work, per_cu * n_cu));
   return DFB_OK;
+}
+
+dfb_status grid_for(dfb_ctx* h, const void* func, int threads, size_t lds, int& grid) {
+  return grid_of(h, func, threads, lds, h->n_work, h->n_cu, grid);
 }
 
 dfb::VarianceArgs make_var_args(dfb_ctx* h) {
@@ -684,6 +700,43 @@ dfb_status frame_view(dfb_ctx* h, FrameView* v, bool want_denoised) {
   return DFB_OK;
 }
 }  // namespace dfb
+
+// Scratch of dfb_composite_noalloc (the entry point for callers that cannot
+// allocate): the work queue's counters, finish counters and frame state
+// (kQueueWords words), then the longest-first work list of at most
+// DFB_NOALLOC_MAX_WORK units.  One copy per device, held until the process
+// ends.  Host code uses it only through the device address that
+// hipGetSymbolAddress returns for the current device, never by its name.
+namespace {
+constexpr int64_t kScratchWords = dfb::kQueueWords + DFB_NOALLOC_MAX_WORK;
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};  // device address of scratch, per device
+bool g_scratch_zeroed[kScratchDevices] = {};
+
+// The current device's scratch address, looked up once per device (with
+// that device current).  *first is set when this call is the device's
+// first: the caller then clears the scratch, stream-ordered before use.
+dfb_status scratch_of_current_device(void** out, bool* first) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) return fail(nullptr, DFB_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  *first = !g_scratch_zeroed[dev];
+  g_scratch_zeroed[dev] = true;
+  return DFB_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -1179,6 +1232,70 @@ int32_t dfb_kernel_times(dfb_handle h, float* ms, int32_t cap) {
   const int32_t n = static_cast<int32_t>(std::min<size_t>(h->times_ms.size(), static_cast<size_t>(cap)));
   std::copy(h->times_ms.begin(), h->times_ms.begin() + n, ms);
   return static_cast<int32_t>(h->times_ms.size());
+}
+
+dfb_status dfb_composite_noalloc(const dfb_config* cfg, const void* frag_dev, const int32_t* tile_off_dev,
+                                 const int64_t* layer_off_dev, int32_t max_layers, void* final_dev,
+                                 float* finished_dev, void* hip_stream) {
+  std::string msg;
+  dfb_status s = check_config(cfg, msg);
+  if (s != DFB_OK) return fail(nullptr, s, msg);
+  if (!cfg->work_w || !cfg->waves_per_tile)
+    return fail(nullptr, DFB_ERR_INVALID_ARG, "set work_w, work_h and waves_per_tile: the autotuner needs buffers");
+  if (cfg->flags & (DFB_VALIDATE | DFB_KEEP_SORT_ORDER))
+    return fail(nullptr, DFB_ERR_UNSUPPORTED, "DFB_VALIDATE and DFB_KEEP_SORT_ORDER need buffers of their own");
+  if (max_layers < 0 || max_layers > dfb::kMaxLayers)
+    return fail(nullptr, DFB_ERR_INVALID_ARG, "max_layers must be in [0, 4096]");
+  if (!tile_off_dev || (max_layers > 0 && (!frag_dev || !layer_off_dev)))
+    return fail(nullptr, DFB_ERR_INVALID_ARG, "null fragment buffer or layer table");
+  if (cfg->format != DFB_FMT_NONE && !final_dev) return fail(nullptr, DFB_ERR_INVALID_ARG, "final_dev is null");
+  if ((cfg->flags & DFB_KEEP_FINISHED) && !finished_dev)
+    return fail(nullptr, DFB_ERR_INVALID_ARG, "DFB_KEEP_FINISHED needs finished_dev");
+  const int tiles_x = (cfg->width + cfg->tile_w - 1) / cfg->tile_w;
+  const int n_tiles = tiles_x * ((cfg->height + cfg->tile_h - 1) / cfg->tile_h);
+  const int64_t n_work = static_cast<int64_t>(n_tiles) * (cfg->tile_w / cfg->work_w) * (cfg->tile_h / cfg->work_h);
+  if (n_work > DFB_NOALLOC_MAX_WORK)
+    return fail(nullptr, DFB_ERR_UNSUPPORTED, "the frame has " + std::to_string(n_work) +
+                                                  " work units; the static scratch holds at most " +
+                                                  std::to_string(DFB_NOALLOC_MAX_WORK) + " (use larger work units)");
+  void* base = nullptr;
+  bool first = false;
+  if ((s = scratch_of_current_device(&base, &first)) != DFB_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  uint32_t* queue = static_cast<uint32_t*>(base);
+  int32_t* work = reinterpret_cast<int32_t*>(queue + dfb::kQueueWords);
+  if (first) {  // counters and frame state start at zero; a fill kernel, no memset node
+    int64_t words = kScratchWords;
+    uint32_t zero = 0;
+    void* fp[] = {&queue, &zero, &words};
+    DFB_HIP(nullptr, hipLaunchKernel(dfb::fill_u32_kernel(), dim3(1024), dim3(256), fp, 0, st));
+  }
+  Shape sh{cfg->work_w, cfg->work_h, cfg->waves_per_tile, dfb::big_lds_bytes(max_layers)};
+  uint32_t mode = display_mode(*cfg);
+  if (cfg->flags & DFB_KEEP_FINISHED) mode |= dfb::kModeKeepFinished;
+  FrameArgs a = base_args(*cfg, tiles_x, n_tiles, sh, frag_dev, mode);
+  a.queue = queue;
+  a.finished = finished_dev;
+  a.final_out = final_dev;
+  const int kcap = kcap_for(max_layers);
+  const int threads = 64 * sh.waves;
+  const void* func = dfb::frame_kernel(cfg->frag_dtype, kcap, cfg->tile_op);
+  const size_t lds = cfg->tile_op == DFB_OP_ALPHA_BLEND ? dfb::frame_lds_bytes(kcap, threads, max_layers, sh.big_lds) : 0;
+  int dev = 0, n_cu = 0, grid = 0;
+  DFB_HIP(nullptr, hipGetDevice(&dev));
+  DFB_HIP(nullptr, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  if ((s = grid_of(nullptr, func, threads, lds, a.n_work, n_cu, grid)) != DFB_OK) return s;
+  if (lds > 64 * 1024)
+    DFB_HIP(nullptr, hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  a.n_queues = std::min(dfb::kQueues, grid);
+  int32_t nt = n_tiles, subs = a.subs_per_tile;
+  void* lp[] = {&tile_off_dev, &nt, &subs, &work};
+  DFB_HIP(nullptr, hipLaunchKernel(dfb::lpt_work_kernel(), dim3(1), dim3(dfb::kLptThreads), lp, 0, st));
+  const int32_t* tab_work = work;
+  void* fparams[] = {&a, &tile_off_dev, &layer_off_dev, &tab_work};
+  DFB_HIP(nullptr, hipLaunchKernel(func, dim3(grid), dim3(threads), fparams, lds, st));
+  DFB_HIP(nullptr, hipGetLastError());
+  return DFB_OK;
 }
 
 }  // extern "C"

@@ -147,3 +147,34 @@ int main() {
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-I", os.path.join(ROOT, "paper_2305_07083_amd", "csrc"),
                            str(src), "-o", str(exe)])
     assert subprocess.run([str(exe)]).returncode == 0
+
+
+def test_noalloc_entry_rejects_before_any_gpu_work(dfb):
+    """dfb_composite_noalloc checks its arguments on the host first: a frame
+    of more work units than its static scratch holds, a missing launch shape
+    and unsupported flags are refused without touching a device."""
+    big = dfb.make_config(32768, 32768, 16, work=16, waves=1)      # 4 Mi units > 1 Mi
+    with pytest.raises(dfb.DfbError) as e:
+        dfb.dfb_composite_noalloc(big, 1, 1, 1, 4, 1)
+    assert e.value.status == dfb.DFB_ERR_UNSUPPORTED
+    assert "work units" in str(e.value)
+    with pytest.raises(dfb.DfbError) as e:
+        dfb.dfb_composite_noalloc(dfb.make_config(256, 256, 64), 1, 1, 1, 4, 1)
+    assert e.value.status == dfb.DFB_ERR_INVALID_ARG
+    with pytest.raises(dfb.DfbError) as e:
+        dfb.dfb_composite_noalloc(dfb.make_config(256, 256, 64, work=64, waves=1, flags=dfb.DFB_KEEP_SORT_ORDER),
+                                  1, 1, 1, 4, 1)
+    assert e.value.status == dfb.DFB_ERR_UNSUPPORTED
+    with pytest.raises(dfb.DfbError) as e:
+        dfb.dfb_composite_noalloc(dfb.make_config(256, 256, 64, work=64, waves=1), 1, 1, 1, 5000, 1)
+    assert e.value.status == dfb.DFB_ERR_INVALID_ARG
+
+
+def test_layer_tables_of_a_layer_list(dfb):
+    f = workloads.uniform_frame(192, 128, 64, ranks=3, seed=4)
+    off, lo, kmax = dfb.layer_tables(f.layers, f.n_tiles, f.P)
+    assert kmax == 3 and list(off) == [0, 3, 6, 9, 12, 15, 18]
+    for t in range(f.n_tiles):
+        sel = f.layers[f.layers["tile_id"] == t]
+        expect = sel["block"][np.argsort(sel["source_id"])] * 5 * f.P
+        assert list(lo[off[t]:off[t + 1]]) == list(expect)
