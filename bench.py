@@ -551,6 +551,18 @@ def main():
         t_in = time.perf_counter()
         c.set_fragments(copies[1 % len(copies)], n_blocks, f.layers, f.expected)  # same layout
         same_layout_ms = (time.perf_counter() - t_in) * 1e3
+        # new layouts in steady state: the arrival order alternates between
+        # two permutations, so every call is a new layer list (validation,
+        # per-tile table, work list, upload), with frames in flight
+        alt = [f.layers, f.layers[::-1].copy()]
+        new_layout_ms = []
+        for i in range(10):
+            t_in = time.perf_counter()
+            c.set_fragments(copies[i % len(copies)], n_blocks, alt[(i + 1) % 2], f.expected)
+            new_layout_ms.append((time.perf_counter() - t_in) * 1e3)
+            c.composite(accumulate=False)
+        c.set_fragments(copies[0], n_blocks, f.layers, f.expected)
+        torch.cuda.synchronize()
         for i in range(args.warmup):
             c.set_fragments(copies[i % len(copies)], n_blocks, f.layers, f.expected)
             c.composite(accumulate=accumulate)
@@ -630,7 +642,10 @@ def main():
             "events_median_ms": median_mad(graph_ms)[0], "events_mad_ms": median_mad(graph_ms)[1],
             "how": "DFB_REPLAY: each frame a hipGraphLaunch of the handle's graph (frame kernel + variance "
                    "combine, one graph per input copy); events bracket the whole graph"},
-        "host_ms": {"ingest_new_layout": ingest_ms, "set_fragments_same_layout": same_layout_ms,
+        "host_ms": {"ingest_new_layout": median_mad(new_layout_ms)[0],
+                    "ingest_new_layout_how": "median of 10 dfb_set_fragments calls, each a new layer list "
+                                             "(alternating arrival orders), a frame composited after each",
+                    "ingest_first_layout": ingest_ms, "set_fragments_same_layout": same_layout_ms,
                     "assign_samples_4096_tiles": assign_samples_ms(dfb)},
         "hbm_gbps_algorithmic": achieved,
         "hbm_frac_of_peak": achieved / HBM_PEAK_GBPS,

@@ -49,6 +49,14 @@ namespace {
 #ifndef DFB_UPFRONT_MAX
 #define DFB_UPFRONT_MAX 0
 #endif
+// Streaming (non-temporal) loads in the K > 32 path too (1), or ordinary
+// loads (0, the default): those leave a line in L2 for the pixel group that
+// reads its other half (a group of 16 or fewer fp32 pixels covers half a
+// 128-byte line or less); on the 8192^2 heavy-tailed frame 36.5 against
+// 38.6 ms.
+#ifndef DFB_BIGK_NT
+#define DFB_BIGK_NT 0
+#endif
 // Layers whose plane loads the list and averaging operations keep in flight
 // per lane.
 #ifndef DFB_OP_CHUNK
@@ -760,6 +768,16 @@ constexpr int kBigC = DFB_BIG_C;
 
 __device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
 
+// Plane loads of the K > 32 path.
+template <typename FT>
+__device__ __forceinline__ float ldb(const FT* __restrict__ base, uint32_t i) {
+#if DFB_BIGK_NT
+  return ldf<FT>(base, i);
+#else
+  return static_cast<float>(base[i]);
+#endif
+}
+
 
 // a block is read as runs of 16 keys, none of which straddles a pad slot
 __device__ __forceinline__ void block_load(const uint64_t* r, int base, uint64_t (&k)[kBlk]) {
@@ -897,8 +915,8 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         cb[j] = 0.f;
         if (j < C && live && l < K) {
           const FT* __restrict__ b = frag + lofs[l];
-          dv[j] = ldf<FT>(b, 4 * P + p_me);
-          av[j] = ldf<FT>(b, 3 * P + p_me);
+          dv[j] = ldb<FT>(b, 4 * P + p_me);
+          av[j] = ldb<FT>(b, 3 * P + p_me);
         }
       }
 #pragma unroll
@@ -906,9 +924,9 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         const int l = sm + j * S;
         if (j < C && live && l < K) {
           const FT* __restrict__ b = frag + lofs[l];
-          cr[j] = ldf<FT>(b, p_me);
-          cg[j] = ldf<FT>(b, P + p_me);
-          cb[j] = ldf<FT>(b, 2 * P + p_me);
+          cr[j] = ldb<FT>(b, p_me);
+          cg[j] = ldb<FT>(b, P + p_me);
+          cb[j] = ldb<FT>(b, 2 * P + p_me);
         }
       }
 #pragma unroll
@@ -930,8 +948,8 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         av[j] = 0.f;
         if (j0 + j < C && live && l < K) {
           const FT* __restrict__ b = frag + lofs[l];
-          dv[j] = ldf<FT>(b, 4 * P + p_me);
-          av[j] = ldf<FT>(b, 3 * P + p_me);
+          dv[j] = ldb<FT>(b, 4 * P + p_me);
+          av[j] = ldb<FT>(b, 3 * P + p_me);
         }
       }
 #pragma unroll
@@ -1027,9 +1045,9 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         for (int j = 0; j < 4; ++j) {
           const FT* __restrict__ b = frag + lofs[l + j * S];
           w[j] = wrow[kslot(l + j * S)];
-          r4[j] = ldf<FT>(b, p_me);
-          g4[j] = ldf<FT>(b, P + p_me);
-          b4[j] = ldf<FT>(b, 2 * P + p_me);
+          r4[j] = ldb<FT>(b, p_me);
+          g4[j] = ldb<FT>(b, P + p_me);
+          b4[j] = ldb<FT>(b, 2 * P + p_me);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1041,9 +1059,9 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
       for (; l < K; l += S) {
         const FT* __restrict__ b = frag + lofs[l];
         const float w = wrow[kslot(l)];
-        R = fmaf(w, ldf<FT>(b, p_me), R);
-        Gc = fmaf(w, ldf<FT>(b, P + p_me), Gc);
-        B = fmaf(w, ldf<FT>(b, 2 * P + p_me), B);
+        R = fmaf(w, ldb<FT>(b, p_me), R);
+        Gc = fmaf(w, ldb<FT>(b, P + p_me), Gc);
+        B = fmaf(w, ldb<FT>(b, 2 * P + p_me), B);
       }
     }
     // lanes whose chunk is the last non-empty one hold the final T

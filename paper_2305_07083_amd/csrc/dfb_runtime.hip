@@ -26,12 +26,15 @@ std::string g_create_error;
 
 enum class State { kEmpty, kReady, kComposited };
 
+// A launch shape is chosen once per frame geometry, fragment type, tile
+// operation and layer-count class (the register-sort capacity and the
+// padded size of the largest tile's sort), so a new layer layout of the same
+// class reuses it instead of autotuning again.
 struct AutotuneKey {
-  int device, width, height, tile_w, tile_h, dtype, op, max_k;
-  uint64_t digest;
+  int device, width, height, tile_w, tile_h, dtype, op, kcap, lk;
   bool operator<(const AutotuneKey& o) const {
-    return std::tie(device, width, height, tile_w, tile_h, dtype, op, max_k, digest) <
-           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.op, o.max_k, o.digest);
+    return std::tie(device, width, height, tile_w, tile_h, dtype, op, kcap, lk) <
+           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.op, o.kcap, o.lk);
   }
 };
 struct Shape {
@@ -70,16 +73,37 @@ struct dfb_ctx {
   int64_t n_blocks = 0;
   int n_layers = 0, max_k = 0;
   std::vector<int32_t> h_off;
-  std::vector<int64_t> h_block;
   std::vector<dfb_layer> last_layers;
   std::vector<int32_t> last_expected;
   bool last_had_expected = false;
-  uint64_t digest = 0;
-  int32_t* d_off = nullptr;
+  // Two sets of device layer tables (per-tile offsets, layer offsets, work
+  // list), used by successive layer layouts in turn, each uploaded from
+  // pinned host staging: a new layout is written to the set the frames in
+  // flight do not read, so its upload needs no wait for them.  A set is
+  // reused two layouts later, after the event recorded when the frames
+  // stopped using it.
+  struct Tables {
+    int32_t* off = nullptr;
+    size_t off_cap = 0;
+    int64_t* block = nullptr;
+    size_t block_cap = 0;
+    int32_t* work = nullptr;
+    size_t work_cap = 0;
+    int32_t* st_off = nullptr;   // pinned staging
+    size_t st_off_cap = 0;
+    int64_t* st_block = nullptr;
+    size_t st_block_cap = 0;
+    int32_t* st_work = nullptr;
+    size_t st_work_cap = 0;
+    hipEvent_t released = nullptr;  // the frames that read this set are done
+    hipEvent_t staged[3] = {};      // uploads from st_off / st_block / st_work are done
+    bool released_pending = false;
+    bool staged_pending[3] = {};
+  } tables[2];
+  int cur_tables = 0;
+  int32_t* d_off = nullptr;    // the current set's arrays
   int64_t* d_block = nullptr;
-  size_t block_cap = 0;
   int32_t* d_work = nullptr;
-  size_t work_cap = 0;
   float* d_var_partial = nullptr;
   size_t partial_cap = 0;
   uint32_t* d_flag = nullptr;
@@ -228,12 +252,6 @@ dfb_status validate_layers(const dfb_config* c, int64_t n_blocks, const dfb_laye
   return DFB_OK;
 }
 
-uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
-  const unsigned char* b = static_cast<const unsigned char*>(p);
-  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
-  return h;
-}
-
 template <typename T>
 dfb_status ensure(dfb_ctx* h, T*& ptr, size_t& cap, size_t count) {
   if (count <= cap && ptr) return DFB_OK;
@@ -272,6 +290,14 @@ dfb_status check_usable(dfb_ctx* h) {
 
 int kcap_for(int max_k) { return max_k <= 8 ? 8 : (max_k <= 16 ? 16 : 32); }
 
+// log2 of the padded sort size of a tile with max_k layers (the K > 32 path
+// pads to a power of two of at least 64).
+int layer_class(int max_k) {
+  int lk = 0;
+  while ((1 << lk) < max_k) ++lk;
+  return lk;
+}
+
 // Candidate launch shapes: square work units of 16/32/64/128 that divide the
 // tile (else the whole tile), and full-width strips of the same pixel count
 // (a strip row is a whole tile row, so a unit's plane rows are contiguous in
@@ -307,6 +333,73 @@ std::vector<Shape> candidates(const dfb_config& c, int max_k) {
 
 void drop_graphs(dfb_ctx* h);
 
+// Device array of a table set, grown when too small.  Only called on a set
+// no frame in flight reads (the other set's, or during the autotuner's
+// synchronous sweep).
+template <typename T>
+dfb_status ensure_device_table(dfb_ctx* h, T*& ptr, size_t& cap, size_t count) {
+  if (count <= cap && ptr) return DFB_OK;
+  if (ptr) DFB_HIP(h, hipFree(ptr));
+  ptr = nullptr;
+  cap = 0;
+  const size_t n = std::max<size_t>(count, 1);
+  if (hipMalloc(reinterpret_cast<void**>(&ptr), n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+    return fail(h, DFB_ERR_OOM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  cap = n;
+  return DFB_OK;
+}
+
+// Pinned staging buffer `which` of a set, ready to be written: waits for the
+// last upload from it, grows it when too small.
+template <typename T>
+dfb_status stage(dfb_ctx* h, dfb_ctx::Tables& S, int which, T*& ptr, size_t& cap, size_t count) {
+  if (S.staged_pending[which]) {
+    DFB_HIP(h, hipEventSynchronize(S.staged[which]));
+    S.staged_pending[which] = false;
+  }
+  if (count <= cap && ptr) return DFB_OK;
+  if (ptr) DFB_HIP(h, hipHostFree(ptr));
+  ptr = nullptr;
+  cap = 0;
+  const size_t n = std::max<size_t>(count, 1);
+  if (hipHostMalloc(reinterpret_cast<void**>(&ptr), n * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ptr = nullptr;
+    return fail(h, DFB_ERR_OOM, "pinned host allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  cap = n;
+  return DFB_OK;
+}
+
+// Stream-ordered upload of a staged array; the staging is free again once
+// the recorded event has passed.
+template <typename T>
+dfb_status upload(dfb_ctx* h, dfb_ctx::Tables& S, int which, T* dev, const T* staging, size_t count) {
+  if (count) DFB_HIP(h, hipMemcpyAsync(dev, staging, count * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  if (!S.staged[which]) DFB_HIP(h, hipEventCreateWithFlags(&S.staged[which], hipEventDisableTiming));
+  DFB_HIP(h, hipEventRecord(S.staged[which], h->stream));
+  S.staged_pending[which] = true;
+  return DFB_OK;
+}
+
+void free_tables(dfb_ctx* h) {
+  for (auto& S : h->tables) {
+    if (S.off) (void)hipFree(S.off);
+    if (S.block) (void)hipFree(S.block);
+    if (S.work) (void)hipFree(S.work);
+    if (S.st_off) (void)hipHostFree(S.st_off);
+    if (S.st_block) (void)hipHostFree(S.st_block);
+    if (S.st_work) (void)hipHostFree(S.st_work);
+    if (S.released) (void)hipEventDestroy(S.released);
+    for (auto& e : S.staged)
+      if (e) (void)hipEventDestroy(e);
+    S = dfb_ctx::Tables{};
+  }
+}
+
 // Work list for a shape: every (tile, unit) pair, tiles with more layers
 // first (longest-processing-time order), ties by tile id.
 dfb_status build_work(dfb_ctx* h, const Shape& s) {
@@ -320,16 +413,20 @@ dfb_status build_work(dfb_ctx* h, const Shape& s) {
   std::stable_sort(tiles.begin(), tiles.end(), [&](int a, int b) {
     return (h->h_off[a + 1] - h->h_off[a]) > (h->h_off[b + 1] - h->h_off[b]);
   });
-  std::vector<int32_t> work(h->n_work);
+  dfb_ctx::Tables& T = h->tables[h->cur_tables];
+  const size_t n = static_cast<size_t>(h->n_work);
+  dfb_status st = ensure_device_table(h, T.work, T.work_cap, n);
+  if (st != DFB_OK) return st;
+  st = ensure(h, h->d_var_partial, h->partial_cap, n);
+  if (st != DFB_OK) return st;
+  st = stage(h, T, 2, T.st_work, T.st_work_cap, n);
+  if (st != DFB_OK) return st;
   size_t k = 0;
   for (int t : tiles)
-    for (int u = 0; u < h->subs_per_tile; ++u) work[k++] = t * h->subs_per_tile + u;
-  dfb_status st = ensure(h, h->d_work, h->work_cap, work.size());
+    for (int u = 0; u < h->subs_per_tile; ++u) T.st_work[k++] = t * h->subs_per_tile + u;
+  st = upload(h, T, 2, T.work, T.st_work, n);
   if (st != DFB_OK) return st;
-  st = ensure(h, h->d_var_partial, h->partial_cap, work.size());
-  if (st != DFB_OK) return st;
-  DFB_HIP(h, hipMemcpyAsync(h->d_work, work.data(), work.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  DFB_HIP(h, hipStreamSynchronize(h->stream));  // host vector goes out of scope
+  h->d_work = T.work;
   h->work_valid = true;
   return DFB_OK;
 }
@@ -588,7 +685,7 @@ dfb_status set_acc_count(dfb_ctx* h, int32_t value) {
 
 dfb_status autotune(dfb_ctx* h) {
   AutotuneKey key{h->device, h->cfg.width, h->cfg.height, h->cfg.tile_w, h->cfg.tile_h,
-                  h->cfg.frag_dtype, h->cfg.tile_op, h->max_k, h->digest};
+                  h->cfg.frag_dtype, h->cfg.tile_op, h->kcap, layer_class(h->max_k)};
   auto cands = candidates(h->cfg, h->max_k);
   if (cands.size() == 1) {
     h->shape = cands[0];
@@ -657,10 +754,10 @@ dfb_status prepare_shape(dfb_ctx* h) {
 
 // Device NaN scan of every layer's depth plane (DFB_VALIDATE).  Uses the
 // block table already on the device.
-dfb_status scan_nan(dfb_ctx* h, const void* frag_dev, int n_layers) {
+dfb_status scan_nan(dfb_ctx* h, const void* frag_dev, const int64_t* layer_table, int n_layers) {
   if (n_layers == 0) return DFB_OK;
   DFB_HIP(h, hipMemsetAsync(h->d_flag, 0, sizeof(uint32_t), h->stream));
-  dfb::ValidateArgs va{frag_dev, h->d_block, n_layers, h->P, h->d_flag};
+  dfb::ValidateArgs va{frag_dev, layer_table, n_layers, h->P, h->d_flag};
   void* params[] = {&va};
   DFB_HIP(h, hipLaunchKernel(dfb::validate_kernel(h->cfg.frag_dtype), dim3(n_layers), dim3(256), params, 0,
                              h->stream));
@@ -837,10 +934,11 @@ dfb_status dfb_destroy(dfb_handle h) {
     if (h->ev0[i]) (void)hipEventDestroy(h->ev0[i]);
     if (h->ev1[i]) (void)hipEventDestroy(h->ev1[i]);
   }
-  void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->denoised, h->d_off,
-                  h->d_block, h->d_work, h->d_var_partial, h->d_queue_ring, h->d_flag};
+  void* bufs[] = {h->finished, h->accum, h->m2, h->tile_var, h->final_out, h->order, h->denoised,
+                  h->d_var_partial, h->d_queue_ring, h->d_flag};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  free_tables(h);
   delete h;
   return DFB_OK;
 }
@@ -857,7 +955,7 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
                     (!expected || std::memcmp(expected, h->last_expected.data(), sizeof(int32_t) * h->n_tiles) == 0);
   if (same) {
     if (h->cfg.flags & DFB_VALIDATE) {
-      s = scan_nan(h, frag_dev, n_layers);
+      s = scan_nan(h, frag_dev, h->d_block, n_layers);
       if (s != DFB_OK) return s;
     }
     h->frag = frag_dev;
@@ -889,19 +987,26 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
     }
     max_k = std::max(max_k, counts[t]);
   }
-  size_t off_cap = 0;
-  if (!h->d_off) {
-    s = ensure(h, h->d_off, off_cap, off.size());
-    if (s != DFB_OK) return s;
+  // Upload into the table set that no frame in flight reads (no wait for
+  // the frames of the current layout).
+  const bool first = !h->tables[h->cur_tables].off;
+  const int nxt = first ? h->cur_tables : 1 - h->cur_tables;
+  dfb_ctx::Tables& T = h->tables[nxt];
+  if (T.released_pending) {  // frames of the layout before last: normally long done
+    DFB_HIP(h, hipEventSynchronize(T.released));
+    T.released_pending = false;
   }
-  s = ensure(h, h->d_block, h->block_cap, block.size());
-  if (s != DFB_OK) return s;
-  DFB_HIP(h, hipStreamSynchronize(h->stream));  // previous frame may still read the tables
-  DFB_HIP(h, hipMemcpy(h->d_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  if (n_layers) DFB_HIP(h, hipMemcpy(h->d_block, block.data(), block.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  if ((s = ensure_device_table(h, T.off, T.off_cap, off.size())) != DFB_OK) return s;
+  if ((s = ensure_device_table(h, T.block, T.block_cap, block.size())) != DFB_OK) return s;
+  if ((s = stage(h, T, 0, T.st_off, T.st_off_cap, off.size())) != DFB_OK) return s;
+  if ((s = stage(h, T, 1, T.st_block, T.st_block_cap, block.size())) != DFB_OK) return s;
+  std::copy(off.begin(), off.end(), T.st_off);
+  std::copy(block.begin(), block.end(), T.st_block);
+  if ((s = upload(h, T, 0, T.off, T.st_off, off.size())) != DFB_OK) return s;
+  if ((s = upload(h, T, 1, T.block, T.st_block, block.size())) != DFB_OK) return s;
   if (h->cfg.flags & DFB_VALIDATE) {
-    s = scan_nan(h, frag_dev, n_layers);
-    if (s != DFB_OK) {
+    s = scan_nan(h, frag_dev, T.block, n_layers);
+    if (s != DFB_OK) {  // the frame is refused: set_fragments must come again before a composite
       h->state = State::kEmpty;
       h->n_layers = -1;
       return s;
@@ -911,13 +1016,23 @@ dfb_status dfb_set_fragments(dfb_handle h, const void* frag_dev, int64_t n_block
     s = ensure(h, h->order, h->order_cap, static_cast<size_t>(n_layers) * h->P);
     if (s != DFB_OK) return s;
   }
-  // digest of the per-tile layer counts: the autotune cache key
-  uint64_t dg = fnv1a(counts.data(), counts.size() * sizeof(int32_t));
-  if (dg != h->digest || max_k != h->max_k || h->state == State::kEmpty) h->shape_valid = false;
-  h->digest = dg;
+  // graph replays in flight hold the old tables and shape
+  if (!h->graphs.empty()) DFB_HIP(h, hipStreamSynchronize(h->stream));
   drop_graphs(h);
+  if (!first) {  // the old set is free once the frames enqueued so far are done
+    dfb_ctx::Tables& O = h->tables[h->cur_tables];
+    if (!O.released) DFB_HIP(h, hipEventCreateWithFlags(&O.released, hipEventDisableTiming));
+    DFB_HIP(h, hipEventRecord(O.released, h->stream));
+    O.released_pending = true;
+  }
+  h->cur_tables = nxt;
+  h->d_off = T.off;
+  h->d_block = T.block;
+  h->d_work = T.work;
+  // a new launch shape only for a new layer-count class
+  if (h->state == State::kEmpty || kcap_for(max_k) != h->kcap || layer_class(max_k) != layer_class(h->max_k))
+    h->shape_valid = false;
   h->h_off.swap(off);
-  h->h_block.swap(block);
   h->n_layers = n_layers;
   h->n_blocks = n_blocks;
   h->max_k = max_k;

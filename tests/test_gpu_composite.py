@@ -391,3 +391,30 @@ def test_errors_are_reported(dfb):
         c.set_fragments(frag, f.frag.shape[0], f.layers, f.expected)
         c.composite()
         assert c.read(dfb.DFB_BUF_FINAL).shape == (16, 4096, 4)
+
+
+def test_layouts_changing_every_frame(dfb):
+    """New layer layouts frame after frame with nothing synchronised between
+    them (the layer tables alternate between two device sets): the running
+    mean of 6 frames over three different layouts -- two arrival orders of
+    one brick frame and a frame with other per-tile layer counts -- against
+    the oracle's Welford of the same frames."""
+    a = workloads.brick_frame(320, 256, (4, 4, 4), 64, seed=21)
+    b = workloads.brick_frame(320, 256, (4, 4, 4), 64, seed=21)
+    b.layers = b.layers[::-1].copy()                # same fragments, another arrival order
+    c_counts = workloads.ragged_counts(a.n_tiles, 12, seed=22)
+    c = workloads.generation_frame(320, 256, 64, c_counts, seed=23, depth_by_generation=False)
+    frames = [a, b, c, a, c, b]
+    bufs = [upload(f.frag) for f in frames]
+    cfg = dfb.make_config(320, 256, 64, work=32, waves=2, flags=dfb.DFB_KEEP_FINISHED)
+    mu = np.zeros((a.n_tiles, a.P, 4))
+    m2 = np.zeros((a.n_tiles, a.P, 3))
+    with dfb.Compositor(cfg, stream_handle()) as comp:
+        for k, (f, x) in enumerate(zip(frames, bufs)):
+            comp.set_fragments(x, f.frag.shape[0], f.layers, f.expected)
+            comp.composite(accumulate=True)
+            r = oracle.composite(f.frag, f.layers, 320, 256, 64, 64, expected=f.expected)
+            oracle.accumulate(mu, m2, r["rgba"], k + 1)
+        g_mu = comp.read(dfb.DFB_BUF_ACCUM_F32)
+        assert comp.info().accumulation_id == 6
+    assert np.all(np.abs(g_mu - mu) <= 1e-5 * (np.abs(mu) + 1.0)), float(np.abs(g_mu - mu).max())
