@@ -18,22 +18,32 @@ constexpr int kRegMax = 32;
 // mod kQueues, so same-address atomics do not serialise the whole chip.
 // Each counter has kSlots per-frame slots used as a ring: frame f counts in
 // slot f mod kSlots and clears slot (f + kSlots/2) mod kSlots, which no
-// frame in flight uses, so nothing is reset between frames.  After the
-// kQueues counter pages come one page of per-slot "workgroups finished"
-// counters and one page holding the FrameState below.
+// frame in flight uses, so nothing is reset between frames.  A ring is the
+// kQueues counter pages and one page of per-slot "workgroups finished"
+// counters.  A frame with tiles of more than kRegMax layers runs two
+// launches over the same work list -- the K > kRegMax tiles, then the rest
+// -- each with a ring of its own; after the two rings comes one page
+// holding the FrameState below.
 constexpr int kQueues = 16;
 constexpr int kQueueStride = 1024;  // 4-byte counters between queues
 constexpr int kSlots = 64;
-constexpr int kQueueWords = (kQueues + 2) * kQueueStride;  // the whole allocation, in u32
+constexpr int kRingWords = (kQueues + 1) * kQueueStride;
+constexpr int kQueueWords = 2 * kRingWords + kQueueStride;  // the whole allocation, in u32
 
 // Per-handle frame state in device memory.  Kernels read it at their start
 // and the last workgroup of a frame advances it, so a launch carries no
 // per-frame value in its arguments and one captured frame can be replayed
 // as every later frame.
 struct FrameState {
-  uint32_t seq;    // frame launches so far: selects the counter slot
+  uint32_t seq;    // frames so far: selects the counter slot
   int32_t n_acc;   // frames folded into the running mean since the reset
 };
+// Ring r (0: the register-path launch, 1: the K > kRegMax launch) and the
+// frame state inside a queue allocation.
+inline uint32_t* ring_of(uint32_t* queue_base, int r) { return queue_base + r * kRingWords; }
+inline FrameState* state_of(uint32_t* queue_base) {
+  return reinterpret_cast<FrameState*>(queue_base + 2 * kRingWords);
+}
 constexpr int kMaxLayers = 4096;
 // Largest LDS budget of the large-K path for keys (u64) and weights (f32);
 // the host passes 64, 96 or 112 KB depending on the frame's largest tile.
@@ -59,8 +69,10 @@ enum ModeBits : uint32_t {
 // table, the fragment buffer and the launch shape stay the same.
 struct FrameArgs {
   const void* frag;            // fragment blocks (caller's buffer)
-  uint32_t* queue;             // kQueues x kSlots counters, queues kQueueStride apart,
-                               // then the kSlots finish counters, then the FrameState
+  uint32_t* queue;             // this launch's ring: kQueues x kSlots counters, queues
+                               // kQueueStride apart, then the kSlots finish counters
+  FrameState* state;           // the frame state (shared by the frame's launches)
+  int32_t advance;             // 1: the last workgroup advances the state (the frame's last launch)
   int32_t slot, clear_slot;    // set by the kernel from FrameState::seq
   int32_t n_queues;            // counters in use: min(kQueues, grid)
   int32_t queue_block;         // consecutive work-list positions per counter block (units per tile)
@@ -130,10 +142,12 @@ struct FrameView {
 // Fails with DFB_ERR_STATE unless at least one frame has been accumulated.
 dfb_status frame_view(dfb_ctx* h, FrameView* out, bool want_denoised);
 
-// Kernel entry points for a given fragment type and register-sort cap.
-// dtype: 0 f32, 1 f16.  kcap: 8, 16 or 32 (layers handled in registers).
-// The persistent frame kernel for a fragment dtype, register-path capacity
-// and tile operation (dfb_tile_op).
+// The persistent frame kernel for a fragment dtype, register-sort capacity
+// and tile operation (dfb_tile_op).  dtype: 0 f32, 1 f16.  kcap 8, 16 or 32:
+// the per-pixel sort of tiles with at most kcap layers in registers (tiles
+// with more are left to the kcap 0 kernel); kcap 0 (ALPHA_BLEND only): the
+// workgroup-wide LDS sort of the tiles with more than kRegMax layers, others
+// left alone.
 const void* frame_kernel(int dtype, int kcap, int op);
 // Largest-remainder assignment of extra samples (host; dfb_assign_samples_host).
 dfb_status assign_samples(const float* variance, int32_t n_tiles, int64_t extra, int32_t* counts);
@@ -150,7 +164,8 @@ constexpr int kLptThreads = 1024;
 const void* validate_kernel(int dtype);
 
 // LDS budget of the K > 32 path for a frame whose largest tile has
-// max_layers layers, and the dynamic LDS bytes a frame launch needs.
+// max_layers layers, and the dynamic LDS bytes a frame launch needs (kcap as
+// for frame_kernel).
 int big_lds_bytes(int max_layers);
 size_t frame_lds_bytes(int kcap, int threads, int max_layers, int big_lds);
 

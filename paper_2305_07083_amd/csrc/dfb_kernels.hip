@@ -756,8 +756,8 @@ __device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* 
 constexpr int kBlkLog = DFB_BLK_LOG;   // keys sorted per lane in registers: 2^kBlkLog
 constexpr int kBlk = 1 << kBlkLog;
 // Layers per lane whose colours are loaded with the keys (held in registers
-// through the sort; past 8 the capacity-32 kernel loses its second wave per
-// SIMD), and the most merge stages one LDS pass runs.
+// through the sort; past 8 the kernel loses its second wave per SIMD), and
+// the most merge stages one LDS pass runs.
 #ifndef DFB_BIG_C
 #define DFB_BIG_C 8
 #endif
@@ -1177,9 +1177,7 @@ constexpr int min_waves(int kcap) {
 __device__ __forceinline__ uint32_t* finish_counters(const FrameArgs& a) {
   return a.queue + static_cast<size_t>(kQueues) * kQueueStride;
 }
-__device__ __forceinline__ FrameState* frame_state(const FrameArgs& a) {
-  return reinterpret_cast<FrameState*>(a.queue + static_cast<size_t>(kQueues + 1) * kQueueStride);
-}
+__device__ __forceinline__ FrameState* frame_state(const FrameArgs& a) { return a.state; }
 
 // The frame's sequence number and accumulation count, read once per
 // workgroup from the device state and shared through LDS.  The load's value
@@ -1203,6 +1201,8 @@ __device__ __forceinline__ uint32_t read_frame_state(FrameArgs& a, uint32_t* s_s
   return seq;
 }
 
+// KCAP 8, 16, 32: register-sort capacity (tiles with more layers are the
+// KCAP 0 launch's); KCAP 0: only the tiles with more than kRegMax layers.
 template <typename FT, int KCAP, int OP>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(KCAP))))
 frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
@@ -1240,12 +1240,17 @@ frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
     const int64_t* __restrict__ blk = layer_off + off;
     float* wl = reinterpret_cast<float*>(lds);
     float vs = 0.f;
-    if constexpr (OP == DFB_OP_AVERAGE) {
+    bool mine = true;  // uniform: this launch composites the unit
+    if constexpr (KCAP == 0) {
+      mine = K > kRegMax;
+      if (mine) vs = unit_bigk<FT>(a, u, blk, K, off, lds);
+    } else if constexpr (OP == DFB_OP_AVERAGE) {
       vs = (a.vec_ok && K > 0) ? unit_average_vec<FT>(a, u, blk, K) : unit_average<FT>(a, u, blk, K);
     } else if constexpr (OP == DFB_OP_LIST) {
       vs = K == 0 ? unit_background(a, u)
                   : (a.vec_ok ? unit_list_vec<FT>(a, u, blk, K, off) : unit_list<FT>(a, u, blk, K, off));
     } else {
+    mine = K <= KCAP;
     if (K == 0) vs = unit_background(a, u);
     else if (K <= 1) vs = unit_reg<FT, 1, KCAP>(a, u, blk, K, off, wl);
     else if (K <= 2) vs = unit_reg<FT, 2, KCAP>(a, u, blk, K, off, wl);
@@ -1262,11 +1267,10 @@ frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
       else if constexpr (KCAP >= 32) {
         if (K <= 24) vs = unit_reg<FT, 24, KCAP>(a, u, blk, K, off, wl);
         else if (K <= 32) vs = unit_reg<FT, 32, KCAP>(a, u, blk, K, off, wl);
-        else vs = unit_bigk<FT>(a, u, blk, K, off, lds);
       }
     }
     }
-    const bool acc = (a.mode & kModeAccumulate) != 0;
+    const bool acc = (a.mode & kModeAccumulate) != 0 && mine;
     if (acc) {
       vs = wave_sum(vs);  // fixed-order reductions only: deterministic
       if ((tid & 63) == 0) s_red[tid >> 6] = vs;
@@ -1292,7 +1296,7 @@ frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
   if (tid == 0)
     done = __hip_atomic_fetch_add(finish_counters(a) + a.slot, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   done = __builtin_amdgcn_readfirstlane(done);
-  const bool last = wave0 && done == gridDim.x - 1;
+  const bool last = a.advance && wave0 && done == gridDim.x - 1;
   if (last && tid == 0)
     __hip_atomic_store(&frame_state(a)->seq, seq + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (last && tid == 0 && (a.mode & kModeAccumulate))
@@ -1432,6 +1436,9 @@ __global__ void __launch_bounds__(256) validate_kernel_t(ValidateArgs a) {
 }  // namespace
 
 const void* frame_kernel(int dtype, int kcap, int op) {
+  if (kcap == 0)
+    return dtype == 0 ? reinterpret_cast<const void*>(&frame_kernel_t<float, 0, 0>)
+                      : reinterpret_cast<const void*>(&frame_kernel_t<_Float16, 0, 0>);
   if (dtype == 0) {
     if (op == DFB_OP_LIST) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8, DFB_OP_LIST>);
     if (op == DFB_OP_AVERAGE) return reinterpret_cast<const void*>(&frame_kernel_t<float, 8, DFB_OP_AVERAGE>);
@@ -1467,11 +1474,9 @@ int big_lds_bytes(int max_layers) {
 }
 
 size_t frame_lds_bytes(int kcap, int threads, int max_layers, int big_lds) {
-  size_t small = static_cast<size_t>(kcap) * threads * sizeof(float);
-  size_t big = 0;
+  if (kcap > 0) return static_cast<size_t>(kcap) * threads * sizeof(float);  // the walk's alpha / T columns
   // keys + alpha, the reduction rows [threads] float4, T_end [64], layer offsets [max_layers]
-  if (max_layers > kcap) big = big_lds + static_cast<size_t>(threads) * 16 + 64 * 4 + static_cast<size_t>(max_layers) * 8;
-  return small > big ? small : big;
+  return big_lds + static_cast<size_t>(threads) * 16 + 64 * 4 + static_cast<size_t>(max_layers) * 8;
 }
 
 }  // namespace dfb

@@ -483,7 +483,6 @@ FrameArgs base_args(const dfb_config& c, int tiles_x, int n_tiles, const Shape& 
 
 FrameArgs make_args(dfb_ctx* h, uint32_t mode) {
   FrameArgs a = base_args(h->cfg, h->tiles_x, h->n_tiles, h->shape, h->frag, mode);
-  a.queue = h->d_queue_ring;
   a.bg_image = h->bg_image;
   a.finished = h->finished;
   a.accum = h->accum;
@@ -532,67 +531,102 @@ dfb::VarianceArgs make_var_args(dfb_ctx* h) {
   return v;
 }
 
-// Everything one frame's launches take: the persistent frame kernel and,
-// for accumulating frames, the per-tile variance combine.  Nothing in it
-// changes from frame to frame (the frame's counter slot and accumulation
-// count live in the device frame state), so the same launches serve as a
-// graph replayed every frame.
-struct FrameLaunch {
+// Everything one frame's launches take: one or two persistent frame
+// kernels over the same work list -- the LDS-sort kernel for the tiles with
+// more than kRegMax layers (alpha-blend frames that have such tiles), then
+// the register-path kernel for the others, whose last workgroup advances the
+// frame state -- and, for accumulating frames, the per-tile variance
+// combine.  Nothing in it changes from frame to frame (the frame's counter
+// slot and accumulation count live in the device frame state), so the same
+// launches serve as a graph replayed every frame.
+struct KernelLaunch {
   const void* func;
   int grid, threads;
   size_t lds;
-  bool acc;
   FrameArgs fa;
-  dfb::VarianceArgs va;
   const int32_t* tab_off;
   const int64_t* tab_layer;
   const int32_t* tab_work;
-  void* fparams[4];
+  void* params[4];
+  void bind() {
+    params[0] = &fa;
+    params[1] = &tab_off;
+    params[2] = &tab_layer;
+    params[3] = &tab_work;
+  }
+};
+
+struct FrameLaunch {
+  int nk;
+  KernelLaunch k[2];
+  bool acc;
+  dfb::VarianceArgs va;
   void* vparams[1];
   void bind() {
-    fparams[0] = &fa;
-    fparams[1] = &tab_off;
-    fparams[2] = &tab_layer;
-    fparams[3] = &tab_work;
+    for (int i = 0; i < nk; ++i) k[i].bind();
     vparams[0] = &va;
   }
 };
 
+// The frame kernels of a frame (geometry args, queue allocation, tables and
+// per-kernel buffers filled in by the caller's base): fills L.k[0..nk).
+dfb_status plan_kernels(dfb_ctx* h, const dfb_config& c, const FrameArgs& base, uint32_t* queue_base,
+                        const Shape& sh, int max_k, int kcap, int n_work, int n_cu, const int32_t* tab_off,
+                        const int64_t* tab_layer, const int32_t* tab_work, FrameLaunch& L) {
+  const int threads = 64 * sh.waves;
+  const bool sorting = c.tile_op == DFB_OP_ALPHA_BLEND;
+  L.nk = 0;
+  const bool big = sorting && max_k > dfb::kRegMax;
+  for (int pass = big ? 0 : 1; pass < 2; ++pass) {
+    KernelLaunch& K = L.k[L.nk++];
+    const int kc = pass == 0 ? 0 : kcap;
+    K.func = dfb::frame_kernel(c.frag_dtype, kc, c.tile_op);
+    K.threads = threads;
+    // the list and averaging operations keep nothing in LDS
+    K.lds = sorting ? dfb::frame_lds_bytes(kc, threads, max_k, sh.big_lds) : 0;
+    dfb_status st = grid_of(h, K.func, threads, K.lds, n_work, n_cu, K.grid);
+    if (st != DFB_OK) return st;
+    if (K.lds > 64 * 1024)
+      DFB_HIP(h, hipFuncSetAttribute(K.func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(K.lds)));
+    K.fa = base;
+    K.fa.queue = dfb::ring_of(queue_base, pass == 0 ? 1 : 0);
+    K.fa.state = dfb::state_of(queue_base);
+    K.fa.advance = pass == 1;
+    K.fa.n_queues = std::min(dfb::kQueues, K.grid);
+    K.tab_off = tab_off;
+    K.tab_layer = tab_layer;
+    K.tab_work = tab_work;
+  }
+  return DFB_OK;
+}
+
 dfb_status prepare_launch(dfb_ctx* h, uint32_t mode, FrameLaunch& L) {
-  L.threads = 64 * h->shape.waves;
-  const bool sorting = h->cfg.tile_op == DFB_OP_ALPHA_BLEND;
-  L.func = dfb::frame_kernel(h->cfg.frag_dtype, h->kcap, h->cfg.tile_op);
-  // the list and averaging operations keep nothing in LDS
-  L.lds = sorting ? dfb::frame_lds_bytes(h->kcap, L.threads, h->max_k, h->shape.big_lds) : 0;
-  L.acc = (mode & dfb::kModeAccumulate) != 0;
-  dfb_status st = grid_for(h, L.func, L.threads, L.lds, L.grid);
+  FrameArgs base = make_args(h, mode);
+  dfb_status st = plan_kernels(h, h->cfg, base, h->d_queue_ring, h->shape, h->max_k, h->kcap, h->n_work, h->n_cu,
+                               h->d_off, h->d_block, h->d_work, L);
   if (st != DFB_OK) return st;
-  if (L.lds > 64 * 1024)
-    DFB_HIP(h, hipFuncSetAttribute(L.func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(L.lds)));
-  L.fa = make_args(h, mode);
-  L.fa.n_queues = std::min(dfb::kQueues, L.grid);
+  L.acc = (mode & dfb::kModeAccumulate) != 0;
   L.va = make_var_args(h);
-  L.tab_off = h->d_off;
-  L.tab_layer = h->d_block;
-  L.tab_work = h->d_work;
   L.bind();
   return DFB_OK;
 }
 
 // Launch one frame with the current shape on the caller's stream.  With
-// t0/t1 given, the two events bracket the frame kernel alone.
+// t0/t1 given, the two events bracket the frame kernels.
 dfb_status launch_frame(dfb_ctx* h, uint32_t mode, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr) {
   FrameLaunch L;
   dfb_status st = prepare_launch(h, mode, L);
   if (st != DFB_OK) return st;
   if (t0) DFB_HIP(h, hipEventRecord(t0, h->stream));
-  DFB_HIP(h, hipLaunchKernel(L.func, dim3(L.grid), dim3(L.threads), L.fparams, L.lds, h->stream));
+  for (int i = 0; i < L.nk; ++i)
+    DFB_HIP(h, hipLaunchKernel(L.k[i].func, dim3(L.k[i].grid), dim3(L.k[i].threads), L.k[i].params, L.k[i].lds,
+                               h->stream));
   if (t1) DFB_HIP(h, hipEventRecord(t1, h->stream));
   if (L.acc)
     DFB_HIP(h, hipLaunchKernel(dfb::tile_variance_kernel(), dim3((h->n_tiles + 255) / 256), dim3(256), L.vparams, 0,
                                h->stream));
   DFB_HIP(h, hipGetLastError());
-  h->grid = L.grid;
+  h->grid = L.k[L.nk - 1].grid;
   return DFB_OK;
 }
 
@@ -625,14 +659,18 @@ dfb_status frame_graph(dfb_ctx* h, uint32_t mode, hipGraphExec_t& exec) {
   dfb_ctx::GraphEntry e{h->frag, mode, nullptr, nullptr};
   DFB_HIP(h, hipGraphCreate(&e.graph, 0));
   hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(L.func);
-  kp.gridDim = dim3(L.grid);
-  kp.blockDim = dim3(L.threads);
-  kp.sharedMemBytes = static_cast<unsigned>(L.lds);
-  kp.kernelParams = L.fparams;
-  kp.extra = nullptr;
   hipGraphNode_t fnode = nullptr, vnode = nullptr;
-  hipError_t err = hipGraphAddKernelNode(&fnode, e.graph, nullptr, 0, &kp);
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < L.nk && err == hipSuccess; ++i) {
+    kp.func = const_cast<void*>(L.k[i].func);
+    kp.gridDim = dim3(L.k[i].grid);
+    kp.blockDim = dim3(L.k[i].threads);
+    kp.sharedMemBytes = static_cast<unsigned>(L.k[i].lds);
+    kp.kernelParams = L.k[i].params;
+    kp.extra = nullptr;
+    hipGraphNode_t prev = fnode;
+    err = hipGraphAddKernelNode(&fnode, e.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+  }
   if (err == hipSuccess && L.acc) {
     hipKernelNodeParams vp{};
     vp.func = const_cast<void*>(dfb::tile_variance_kernel());
@@ -649,7 +687,7 @@ dfb_status frame_graph(dfb_ctx* h, uint32_t mode, hipGraphExec_t& exec) {
     return hip_fail(h, err, "building the frame graph");
   }
   h->graphs.push_back(e);
-  h->grid = L.grid;
+  h->grid = L.k[L.nk - 1].grid;
   exec = e.exec;
   return DFB_OK;
 }
@@ -916,7 +954,7 @@ dfb_status dfb_create(const dfb_config* cfg, void* hip_stream, dfb_handle* out) 
   const size_t queue_bytes = sizeof(uint32_t) * dfb::kQueueWords;
   static_assert(dfb::kSlots <= dfb::kQueueStride, "a queue's slots fit in its stride");
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_queue_ring), queue_bytes)) != DFB_OK) return bail(s);
-  h->d_state = reinterpret_cast<dfb::FrameState*>(h->d_queue_ring + (dfb::kQueues + 1) * dfb::kQueueStride);
+  h->d_state = dfb::state_of(h->d_queue_ring);
   if ((s = alloc_plain(h, reinterpret_cast<void**>(&h->d_flag), 64)) != DFB_OK) return bail(s);
   e = hipMemsetAsync(h->d_queue_ring, 0, queue_bytes, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->tile_var, 0, h->n_tiles * sizeof(float), h->stream);
@@ -1389,26 +1427,22 @@ dfb_status dfb_composite_noalloc(const dfb_config* cfg, const void* frag_dev, co
   uint32_t mode = display_mode(*cfg);
   if (cfg->flags & DFB_KEEP_FINISHED) mode |= dfb::kModeKeepFinished;
   FrameArgs a = base_args(*cfg, tiles_x, n_tiles, sh, frag_dev, mode);
-  a.queue = queue;
   a.finished = finished_dev;
   a.final_out = final_dev;
-  const int kcap = kcap_for(max_layers);
-  const int threads = 64 * sh.waves;
-  const void* func = dfb::frame_kernel(cfg->frag_dtype, kcap, cfg->tile_op);
-  const size_t lds = cfg->tile_op == DFB_OP_ALPHA_BLEND ? dfb::frame_lds_bytes(kcap, threads, max_layers, sh.big_lds) : 0;
-  int dev = 0, n_cu = 0, grid = 0;
+  int dev = 0, n_cu = 0;
   DFB_HIP(nullptr, hipGetDevice(&dev));
   DFB_HIP(nullptr, hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-  if ((s = grid_of(nullptr, func, threads, lds, a.n_work, n_cu, grid)) != DFB_OK) return s;
-  if (lds > 64 * 1024)
-    DFB_HIP(nullptr, hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  a.n_queues = std::min(dfb::kQueues, grid);
+  FrameLaunch L;
+  if ((s = plan_kernels(nullptr, *cfg, a, queue, sh, max_layers, kcap_for(max_layers), a.n_work, n_cu, tile_off_dev,
+                        layer_off_dev, work, L)) != DFB_OK)
+    return s;
+  L.bind();
   int32_t nt = n_tiles, subs = a.subs_per_tile;
   void* lp[] = {&tile_off_dev, &nt, &subs, &work};
   DFB_HIP(nullptr, hipLaunchKernel(dfb::lpt_work_kernel(), dim3(1), dim3(dfb::kLptThreads), lp, 0, st));
-  const int32_t* tab_work = work;
-  void* fparams[] = {&a, &tile_off_dev, &layer_off_dev, &tab_work};
-  DFB_HIP(nullptr, hipLaunchKernel(func, dim3(grid), dim3(threads), fparams, lds, st));
+  for (int i = 0; i < L.nk; ++i)
+    DFB_HIP(nullptr, hipLaunchKernel(L.k[i].func, dim3(L.k[i].grid), dim3(L.k[i].threads), L.k[i].params,
+                                     L.k[i].lds, st));
   DFB_HIP(nullptr, hipGetLastError());
   return DFB_OK;
 }

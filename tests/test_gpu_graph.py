@@ -142,3 +142,27 @@ def test_accumulate_refuses_a_frame_already_accumulated(dfb, scene):
         mu = c.read(dfb.DFB_BUF_ACCUM_F32)
         fin = c.read(dfb.DFB_BUF_FINISHED_F32)
         assert np.array_equal(mu, fin)
+
+
+@pytest.mark.timeout(300)
+def test_replay_of_frames_with_large_tiles(dfb):
+    """Frames with tiles of more than 32 layers run two frame kernels (the
+    LDS sort of the large tiles, then the register sort of the rest, which
+    advances the frame state): replayed as one graph, 6 accumulating frames
+    are bit-identical to direct calls."""
+    torch = torch_dev()
+    counts = workloads.ragged_counts(24, 150, seed=31, p_empty=0.1)
+    f = workloads.generation_frame(384, 256, 64, counts, seed=32, depth_by_generation=False, name="K <= 150")
+    s = torch.cuda.current_stream()
+    buf = torch.empty(f.frag.shape, dtype=torch.float32, device="cuda:0")
+    with make(dfb, f, s.cuda_stream) as d, make(dfb, f, s.cuda_stream) as g:
+        for k in range(6):
+            x = f.frag.copy()
+            x[:, 0:3, :] *= np.float32(1.0 + 0.1 * k)
+            buf.copy_(torch.from_numpy(x))
+            d.set_fragments(buf, x.shape[0], f.layers, f.expected)
+            g.set_fragments(buf, x.shape[0], f.layers, f.expected)
+            d.composite(accumulate=True)
+            g.composite(accumulate=True, replay=True)
+            assert_same(snapshot(dfb, d), snapshot(dfb, g), "frame %d" % (k + 1))
+        assert g.info().accumulation_id == 6
