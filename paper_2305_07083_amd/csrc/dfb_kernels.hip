@@ -363,12 +363,19 @@ __device__ __forceinline__ float4 composite_px_two_phase(float& Tout, const Fram
 // per pixel instead of two, at the cost of registers.  The fp32 16-layer
 // kernel stays at 3 waves per SIMD with all its buckets up front (2048^2
 // bricks: 139 against 144 us); the fp16 one would drop from 4 to 3, so its
-// 12/16 buckets load in two phases.  The 32-layer kernels stay at 2 waves
-// with the 24 bucket up front (4096x1024: 225 against 232 us fp32, 186
-// against 193 us fp16); their 32 bucket loads in two phases.
+// 12/16 buckets load in two phases.  The fp32 32-layer kernel stays at 2
+// waves with the 24 bucket up front (4096x1024: 225 against 232 us); its 32
+// bucket loads in two phases.  The fp16 32-layer kernel loads up to 12
+// layers up front: 168 VGPRs, 3 waves per SIMD instead of 2 with the 24
+// bucket up front (211 VGPRs): the 4096x1024 fp16 frame takes 164 instead of
+// 186 us.
+#ifndef DFB_UPFRONT_F16_K32
+#define DFB_UPFRONT_F16_K32 12   // largest up-front bucket of the fp16 32-layer kernel
+#endif
 template <typename FT>
 constexpr int upfront_max(int kcap) {
-  return DFB_UPFRONT_MAX > 0 ? DFB_UPFRONT_MAX : (kcap <= 16 ? (sizeof(FT) == 4 ? 16 : 8) : 24);
+  return DFB_UPFRONT_MAX > 0 ? DFB_UPFRONT_MAX
+                             : (kcap <= 16 ? (sizeof(FT) == 4 ? 16 : 8) : (sizeof(FT) == 4 ? 24 : DFB_UPFRONT_F16_K32));
 }
 
 template <typename FT, int KMAX, int KCAP>
