@@ -763,14 +763,28 @@ __device__ float unit_average(const FrameArgs& a, const Unit& u, const int64_t* 
 constexpr int kBlkLog = DFB_BLK_LOG;   // keys sorted per lane in registers: 2^kBlkLog
 constexpr int kBlk = 1 << kBlkLog;
 // Layers per lane whose colours are loaded with the keys (held in registers
-// through the sort; past 8 the kernel loses its second wave per SIMD), and
-// the most merge stages one LDS pass runs.
+// through the sort: 16 keeps the LDS-sort kernel at 247 VGPRs, 2 waves per
+// SIMD, which its LDS allows anyway; 32 drops it to one), and the most merge
+// stages one LDS pass runs.
 #ifndef DFB_BIG_C
-#define DFB_BIG_C 8
+#define DFB_BIG_C 16
 #endif
 #ifndef DFB_MAX_M
 #define DFB_MAX_M 4
 #endif
+// Layers per lane whose depth and alpha loads are in flight together past
+// the first kBigC, and layers per lane whose colour loads are in flight
+// together after the walk.  On the 8192^2 heavy-tailed frame (16, 16, 8)
+// takes 34.4 ms against 35.7 ms for (8, 8, 4); larger batches of depth and
+// alpha past the first 8 layers were slower (24, 24: 38.0-38.1 ms).
+#ifndef DFB_BIG_FILL
+#define DFB_BIG_FILL 16
+#endif
+#ifndef DFB_BIG_COLS
+#define DFB_BIG_COLS 8
+#endif
+constexpr int kBigFill = DFB_BIG_FILL;
+constexpr int kBigCols = DFB_BIG_COLS;
 constexpr int kBigC = DFB_BIG_C;
 
 __device__ __forceinline__ int kslot(int i) { return i + (i >> 4); }
@@ -946,10 +960,10 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         }
       }
     }
-    for (int j0 = kBigC; j0 < C; j0 += 8) {  // more layers than kBigC per lane: keys only here
-      float dv[8], av[8];
+    for (int j0 = kBigC; j0 < C; j0 += kBigFill) {  // more layers than kBigC per lane: keys only here
+      float dv[kBigFill], av[kBigFill];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < kBigFill; ++j) {
         const int l = sm + (j0 + j) * S;
         dv[j] = 0.f;
         av[j] = 0.f;
@@ -960,7 +974,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         }
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < kBigFill; ++j) {
         const int l = sm + (j0 + j) * S;
         if (j0 + j < C) {
           krow[kslot(l)] = (live && l < K)
@@ -1046,10 +1060,10 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
         }
       }
       int l = sm4 + kBigC * S;
-      for (; l + 3 * S < K; l += 4 * S) {
-        float w[4], r4[4], g4[4], b4[4];
+      for (; l + (kBigCols - 1) * S < K; l += kBigCols * S) {
+        float w[kBigCols], r4[kBigCols], g4[kBigCols], b4[kBigCols];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kBigCols; ++j) {
           const FT* __restrict__ b = frag + lofs[l + j * S];
           w[j] = wrow[kslot(l + j * S)];
           r4[j] = ldb<FT>(b, p_me);
@@ -1057,7 +1071,7 @@ __device__ float unit_bigk(const FrameArgs& a, const Unit& u, const int64_t* __r
           b4[j] = ldb<FT>(b, 2 * P + p_me);
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kBigCols; ++j) {
           R = fmaf(w[j], r4[j], R);
           Gc = fmaf(w[j], g4[j], Gc);
           B = fmaf(w[j], b4[j], B);
@@ -1175,10 +1189,14 @@ __device__ __forceinline__ void store_partial(const FrameArgs& a, int w, const f
 // uniform across the workgroup; code that only lane 0 runs is a single
 // store or atomic, so no lane can be left behind in a loop that holds a
 // barrier.
-constexpr int min_waves(int kcap) {
+#ifndef DFB_WAVES_F16_K32
+#define DFB_WAVES_F16_K32 0
+#endif
+constexpr int min_waves(int kcap, bool half) {
   return kcap <= 8 ? (DFB_WAVES_K8 > 0 ? DFB_WAVES_K8 : 1)
                    : kcap <= 16 ? (DFB_WAVES_K16 > 0 ? DFB_WAVES_K16 : 1)
-                                : (DFB_WAVES_K32 > 0 ? DFB_WAVES_K32 : 1);
+                                : (half && DFB_WAVES_F16_K32 > 0 ? DFB_WAVES_F16_K32
+                                                                 : (DFB_WAVES_K32 > 0 ? DFB_WAVES_K32 : 1));
 }
 
 __device__ __forceinline__ uint32_t* finish_counters(const FrameArgs& a) {
@@ -1211,7 +1229,7 @@ __device__ __forceinline__ uint32_t read_frame_state(FrameArgs& a, uint32_t* s_s
 // KCAP 8, 16, 32: register-sort capacity (tiles with more layers are the
 // KCAP 0 launch's); KCAP 0: only the tiles with more than kRegMax layers.
 template <typename FT, int KCAP, int OP>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(KCAP))))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves(KCAP, sizeof(FT) == 2))))
 frame_kernel_t(FrameArgs args, const int32_t* __restrict__ tile_off,
                const int64_t* __restrict__ layer_off, const int32_t* __restrict__ work_list) {
   extern __shared__ __align__(16) char lds[];

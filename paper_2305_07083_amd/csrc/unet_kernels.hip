@@ -77,13 +77,17 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // coalesced stores, and optionally the 2x2 average pool of the tile (the
 // tile origin and TH are even).
 constexpr int kTW = 32;
+// bf16 elements of padding after each halo pixel and each weight row in LDS
+#ifndef DFB_CONV_PAD
+#define DFB_CONV_PAD 8
+#endif
 
 template <int BN, int CP, int TH>
 struct TileCfg {
   static constexpr int HW = kTW + 2, HH = TH + 2;
-  static constexpr int LDR = CP + 8;     // one halo pixel, bf16
-  static constexpr int LDB = CP + 8;     // one output channel's weights of a tap
-  static constexpr int LDO = BN + 8;     // one output pixel in the staging tile
+  static constexpr int LDR = CP + DFB_CONV_PAD;  // one halo pixel, bf16
+  static constexpr int LDB = CP + DFB_CONV_PAD;  // one output channel's weights of a tap
+  static constexpr int LDO = BN + 8;             // one output pixel in the staging tile
   static constexpr int HALO = HH * HW * LDR;
   static constexpr int BTAP = BN * LDB;
   static constexpr int OUT = TH * kTW * LDO;
