@@ -30,9 +30,12 @@ struct Shape {
 // y = bf16(relu(conv3x3(x') + b)) at the output shape s, where x' = x, or
 // with `up` the nearest-neighbour 2x up-sampling of x (x at s/2).  x channels
 // must be a multiple of 8; s.h and s.w even with `up` or `pool`.  With `pool`,
-// also pool = bf16(2x2 average of y) at s/2.
+// also pool = bf16(2x2 average of y) at s/2.  With `x2`, the input is the
+// channel concatenation of x and x2 (x.c a multiple of 32, x2.ld == x.ld):
+// two maps that are each written with full 64- or 128-byte pixel rows.
 hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y,
-                       const Shape& s, hipStream_t st, bool up = false, const Map* pool = nullptr);
+                       const Shape& s, hipStream_t st, bool up = false, const Map* pool = nullptr,
+                       const Map* x2 = nullptr);
 // g = bf16(dy * (y > 0)), the ReLU-gated output gradient (g.c == dy.c, a
 // multiple of 8 dividing 2048; rows and offsets of y and g multiples of 8),
 // and db[c] = sum_p dy*(y>0) in f32.  `partial` needs conv3x3_wgrad_scratch

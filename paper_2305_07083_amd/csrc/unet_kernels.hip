@@ -27,6 +27,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int BM = 64;    // rows per workgroup tile
 constexpr int LDK = 40;   // LDS row length in bf16 (32 + 8 padding)
@@ -63,209 +64,387 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
   return (static_cast<long long>(q.n) * s.h + rr) * s.w + cc;
 }
 
-// ------------------------------------------------------------- forward, spatial tiles
-// One workgroup computes a TH x 32 tile of output pixels for all BN output
-// channels.  The (TH+2) x 34 input halo (every input channel, zero outside
-// the image; read through the nearest-neighbour up-sampling when UP) is
-// staged in LDS once, so the nine taps re-read it from LDS instead of from
-// memory; the weights are staged one tap at a time, the next tap's loads in
-// flight during this tap's MFMAs (double-buffered in LDS where that does not
-// cost resident workgroups).  Wave w owns tile rows
-// w*TH/4 .. +TH/4-1 (TH/2 row blocks of 16 pixels) and every 16-column block
-// of BN; the MFMA takes the weights as its row operand, so each accumulator
-// holds 4 channels of one pixel.  K runs tap-major, then 32-channel slices.  Epilogue: bias, ReLU, bf16 into LDS, 16-byte
-// coalesced stores, and optionally the 2x2 average pool of the tile (the
-// tile origin and TH are even).
-constexpr int kTW = 32;
-// bf16 elements of padding after each halo pixel and each weight row in LDS
-#ifndef DFB_CONV_PAD
-#define DFB_CONV_PAD 8
+// ------------------------------------------------------------- forward
+// Persistent implicit-GEMM conv3x3 forward.  Workgroup b computes the
+// TH x 32-pixel output tiles b, b + gridDim.x, ... for all BN output
+// channels; a tile is CP/32 steps, one per 32-input-channel slice.  A step
+// stages the slice's (TH+2) x 34 input halo (zero outside the image; read
+// through the nearest-neighbour up-sampling when UP) and the slice's weights
+// of all nine taps in LDS, then runs the nine taps' MFMAs with no barrier
+// between them.  The next step's halo and weights are loaded into registers
+// while this step's MFMAs run, so a workgroup hides its own load latency.
+//
+// The MFMA is v_mfma_f32_32x32x16_bf16 (measured on the device: about 2.0
+// PFLOP/s, against about 1.15 for v_mfma_f32_16x16x32_bf16 with the same
+// number of independent accumulators).  It takes the weights as its row
+// operand (32 output channels) and a 32-pixel tile row as its column
+// operand; lane l holds pixel l % 32 and, in accumulator element r, channel
+// 8 (r / 4) + 4 (l / 32) + r % 4.  Wave w owns tile rows w*TH/4 .. +TH/4-1
+// and every 32-channel block of BN.  The accumulators start from the bias;
+// the epilogue (ReLU, v_cvt_pk_bf16_f32, optionally the 2x2 average pool)
+// goes through a staging tile in LDS so that the stores are coalesced.
+//
+// LDS rows hold 32 bf16 channels (4 16-byte chunks).  gfx950 serves a
+// ds_read_b128 16 lanes per cycle (per half-wave, the lanes whose bits 2-4
+// have even parity, then odd), and a fragment read is 32 consecutive rows
+// at one chunk per half-wave.  Halo pixels are 5 chunks apart (an odd pitch
+// puts each 16-lane set on distinct banks wherever the 32 pixels start);
+// weight rows are 4 chunks apart with the chunk index XOR-ed with
+// (row >> 2) & 3, which does the same for 32 rows starting at a multiple of
+// 32 (measured on the device: conflicting patterns take 2x the cycles).
+// Every address of the tap loop is a per-lane register plus an immediate,
+// so the loop issues no vector ALU work.
+constexpr int kTW = 32;  // tile width (pixels)
+constexpr int kKC = 32;  // input channels per step
+// Output-tile heights (rows of 32 pixels) of the layers with (output, input)
+// channels (32, 32), (32, 64), (64, 64) and (64, 128); the others use 8
+// (64, 32) and 4 (128, *).  A pooling layer needs a multiple of 8.
+#ifndef DFB_TH_32_32
+#define DFB_TH_32_32 8
+#endif
+#ifndef DFB_TH_32_64
+#define DFB_TH_32_64 8
+#endif
+#ifndef DFB_TH_64_64
+#define DFB_TH_64_64 8
+#endif
+#ifndef DFB_TH_64_128
+#define DFB_TH_64_128 8
 #endif
 
-template <int BN, int CP, int TH>
-struct TileCfg {
+template <int BN, int TH>
+struct ConvCfg {
   static constexpr int HW = kTW + 2, HH = TH + 2;
-  static constexpr int LDR = CP + DFB_CONV_PAD;  // one halo pixel, bf16
-  static constexpr int LDB = CP + DFB_CONV_PAD;  // one output channel's weights of a tap
-  static constexpr int LDO = BN + 8;             // one output pixel in the staging tile
-  static constexpr int HALO = HH * HW * LDR;
-  static constexpr int BTAP = BN * LDB;
-  static constexpr int OUT = TH * kTW * LDO;
-  static constexpr int elems(int nbuf) { return (HALO + nbuf * BTAP) > OUT ? (HALO + nbuf * BTAP) : OUT; }
-  // weight buffers: two (the next tap is stored while this one is read) unless
-  // one buffer lets more workgroups share a compute unit's 160 KB of LDS
-  static constexpr int NBUF = (160 * 1024) / (elems(1) * 2) > (160 * 1024) / (elems(2) * 2) ? 1 : 2;
-  static constexpr int ELEMS = elems(NBUF);
-  static constexpr size_t BYTES = static_cast<size_t>(ELEMS) * 2;
+  static constexpr int HPITCH = 5;             // 16-byte chunks per halo pixel (4 used)
+  static constexpr int HALO_CH = HH * HW * HPITCH;  // 16-byte chunks of a step's halo
+  static constexpr int HALO_EL = HH * HW * 4;       // chunks loaded per step
+  static constexpr int W_CH = 9 * BN * 4;      // 16-byte chunks of a step's weights
+  static constexpr int HIT = (HALO_EL + 255) / 256, WIT = (W_CH + 255) / 256;
+  static constexpr size_t BYTES = static_cast<size_t>(HALO_CH + W_CH) * 16 + BN * 4;  // + the bias
+  // waves per SIMD the register allocation is held to: the workgroups that
+  // fit a compute unit's 160 KB of LDS, at most 4
+  static constexpr int LDS_WG = static_cast<int>((160 * 1024) / BYTES);
+  static constexpr int WAVES = LDS_WG < 1 ? 1 : (LDS_WG > 4 ? 4 : LDS_WG);
 };
+// Raw buffer accesses with a 2 GB range from a per-step base: an offset of
+// kOOB is out of range, so the load returns zeros or the store is dropped.
+// Every lane issues every access, so the number of outstanding memory
+// operations is known at compile time and waiting for the prefetched loads
+// never waits for the stores issued after them.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kOOB = static_cast<int>(0x80000000u);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ uint4 buf_load16(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+  return uint4{v[0], v[1], v[2], v[3]};
+}
+__device__ __forceinline__ void buf_store16(__amdgpu_buffer_rsrc_t r, int byte_off, uint4 v) {
+  const u32x4 w = {v.x, v.y, v.z, v.w};
+  __builtin_amdgcn_raw_buffer_store_b128(w, r, byte_off, 0, 0);
+}
+__device__ __forceinline__ void buf_store8(__amdgpu_buffer_rsrc_t r, int byte_off, uint32_t lo, uint32_t hi) {
+  const u32x2 v = {lo, hi};
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, byte_off, 0, 0);
+}
+// LDS chunk of (row p, chunk q) of the swizzled weights
+__device__ __forceinline__ int swz(int p, int q) { return p * 4 + (q ^ ((p >> 2) & 3)); }
 
-template <int BN, int CP, int TH, bool UP>
-__global__ void __launch_bounds__(256) conv_fwd_tile_k(Map x, const uint16_t* __restrict__ w,
-                                                       const float* __restrict__ bias, Map y, Map pool, Shape s) {
-  using C = TileCfg<BN, CP, TH>;
-  constexpr int WR = TH / 4, MB = 2 * WR, NB = BN / 16, CH8 = CP / 8;
-  constexpr int BCH = BN * CH8, BPT = (BCH + 255) / 256;
-  extern __shared__ __align__(16) uint16_t smem[];
-  uint16_t* halo = smem;
-  uint16_t* bbuf = smem + C::HALO;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// two floats to bf16 (round to nearest even), packed low | high << 16
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  const f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
+
+template <int BN, int CP, int TH, bool UP, bool POOL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH>::WAVES)))
+conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, Shape s) {
+  using C = ConvCfg<BN, TH>;
+  constexpr int NCH = CP / kKC, MB = TH / 4, NB = BN / 32;  // tile rows and 32-channel blocks per wave
+  constexpr int HIT = C::HIT, WIT = C::WIT;
+  static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
+  extern __shared__ __align__(16) uint4 lds4[];
+  uint4* halo = lds4;              // [HH * 34][5]
+  uint4* wts = lds4 + C::HALO_CH;  // [9 * BN][4]
+  float* lbias = reinterpret_cast<float*>(wts + C::W_CH);  // [BN]: read per tile through LDS, so
+  // starting a tile waits on no global load issued after the prefetch
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
   const int tiles_x = (s.w + kTW - 1) / kTW, tiles_y = (s.h + TH - 1) / TH;
+  const long long tiles = static_cast<long long>(s.n) * tiles_x * tiles_y;
+  // workgroup b walks the tiles [b T / G, (b + 1) T / G) in row order (the
+  // host launches G <= T workgroups, so each has at least one), sharing the
+  // halo columns of consecutive tiles through its L2
+  const long long G = gridDim.x, b0 = blockIdx.x;
+  const long long t_begin = b0 * tiles / G, t_end = (b0 + 1) * tiles / G;
+  const int nsteps = static_cast<int>(t_end - t_begin) * NCH;
   const int hi = UP ? s.h / 2 : s.h, wi = UP ? s.w / 2 : s.w;  // the map x is read from
-  // Weights of one tap: BCH 16-byte chunks, BPT per thread.  Taps 1..D are
-  // loaded at the start and every later tap D taps before it is needed, so a
-  // tap's short MFMA phase does not wait for a load (D by register budget).
-  auto load_b = [&](int tap, uint4* reg) {
-#pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int e = tid + i * 256;
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (e < BCH) {
-        const int co = e / CH8, cc = e - co * CH8;
-        if (cc * 8 < x.c) v = *reinterpret_cast<const uint4*>(w + (static_cast<size_t>(tap) * BN + co) * x.c + cc * 8);
+  // The input is the channel concatenation of x and x2 (x2.c may be 0; else
+  // x.c is a multiple of 32 and x2.ld == x.ld): slices below x.c read x, the
+  // others x2.
+  const int cin = x.c + x2.c;
+  const bool full = cin == CP;  // else channels cin .. CP-1 are staged as zeros
+  struct Tile {
+    int n, ty, tx;
+  };
+  auto decode = [&](long long t) {
+    Tile u;
+    const long long per_img = static_cast<long long>(tiles_x) * tiles_y;
+    u.n = static_cast<int>(t / per_img);
+    const int r = static_cast<int>(t - u.n * per_img);
+    u.ty = r / tiles_x;
+    u.tx = r - u.ty * tiles_x;
+    return u;
+  };
+  auto advance = [&](Tile& u) {
+    if (++u.tx == tiles_x) {
+      u.tx = 0;
+      if (++u.ty == tiles_y) {
+        u.ty = 0;
+        ++u.n;
       }
-      reg[i] = v;
     }
   };
-  auto store_b = [&](int buf, const uint4* reg) {
+
+  // this thread's halo elements e = tid + 256 k: halo pixel e / 4 (row, column),
+  // chunk e % 4; byte offset from the step's source origin (the halo's
+  // top-left pixel, or the pixel it is up-sampled from); LDS chunk
+  // hlds + 64 * HPITCH * k
+  int hrel[HIT];
 #pragma unroll
-    for (int i = 0; i < BPT; ++i) {
-      const int e = tid + i * 256;
-      if (e < BCH) {
-        const int co = e / CH8, cc = e - co * CH8;
-        *reinterpret_cast<uint4*>(bbuf + buf * C::BTAP + co * C::LDB + cc * 8) = reg[i];
+  for (int k = 0; k < HIT; ++k) {
+    const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / C::HW, hc = hp - hr * C::HW;
+    hrel[k] = e < C::HALO_EL ? ((UP ? ((hr + 1) >> 1) * wi + ((hc + 1) >> 1) : hr * wi + hc) * x.ld + cc * 8) * 2 : kOOB;
+  }
+  const int hlds = (tid >> 2) * C::HPITCH + (tid & 3);
+  // fragment reads of 16-channel half kh: weights of (tap, j) at
+  // wts[(tap * BN + j * 32) * 4 + boff[kh]], halo of (m, tap) at
+  // halo[aoff + ((m + dr) * 34 + dc) * HPITCH + 2 kh]
+  const int boff[2] = {l32 * 4 + ((0 + lh) ^ ((l32 >> 2) & 3)), l32 * 4 + ((2 + lh) ^ ((l32 >> 2) & 3))};
+  const int aoff = (wave * MB * C::HW + l32) * C::HPITCH + lh;
+
+  // Halo of slice ck of tile u into hreg; every load is issued (with
+  // `none`, all out of range).
+  auto load_halo = [&](const Tile& u, int ck, bool none, uint4* hreg) {
+    const int oy0 = u.ty * TH, ox0 = u.tx * kTW;
+    const bool second = ck * kKC >= x.c;
+    const Map& xm = second ? x2 : x;
+    const int cb = second ? ck * kKC - x.c : ck * kKC;  // first channel of the slice in xm
+    const uint16_t* img = xm.p + xm.off + cb + static_cast<long long>(u.n) * hi * wi * xm.ld;
+    const __amdgpu_buffer_rsrc_t src =
+        buf_rsrc(img + (UP ? (oy0 / 2 - 1) * wi + ox0 / 2 - 1 : (oy0 - 1) * wi + ox0 - 1) * x.ld);
+    const bool inner = full && oy0 >= 1 && oy0 + TH + 1 <= s.h && ox0 >= 1 && ox0 + kTW + 1 <= s.w;
+    int off[HIT];
+    if (inner && !none) {
+#pragma unroll
+      for (int k = 0; k < HIT; ++k) off[k] = hrel[k];
+    } else {  // zeros outside the image and past xm.c
+#pragma unroll
+      for (int k = 0; k < HIT; ++k) {
+        const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / C::HW, hc = hp - hr * C::HW;
+        const int r = oy0 - 1 + hr, c = ox0 - 1 + hc;
+        const int ok = (static_cast<unsigned>(r) < static_cast<unsigned>(s.h)) &
+                       (static_cast<unsigned>(c) < static_cast<unsigned>(s.w)) & (cb + cc * 8 < xm.c) & !none;
+        off[k] = ok ? hrel[k] : kOOB;
       }
+    }
+#pragma unroll
+    for (int k = 0; k < HIT; ++k) hreg[k] = buf_load16(src, off[k]);
+  };
+  // weights [tap][co][cin]: a step's slice is 64 bytes of each (tap, co) row
+  const __amdgpu_buffer_rsrc_t wsrc = buf_rsrc(w);
+  int wrel[WIT];  // byte offset of this thread's chunks in slice 0
+#pragma unroll
+  for (int k = 0; k < WIT; ++k) {
+    const int e = tid + 256 * k;
+    wrel[k] = e < C::W_CH ? ((e >> 2) * cin + (e & 3) * 8) * 2 : kOOB;
+  }
+  auto load_w = [&](int ck, bool none, uint4* wreg) {
+    int off[WIT];
+    if (full && !none) {
+#pragma unroll
+      for (int k = 0; k < WIT; ++k) off[k] = wrel[k] + ck * kKC * 2;  // kOOB stays out of range
+    } else {
+#pragma unroll
+      for (int k = 0; k < WIT; ++k) {
+        const int cc = (tid + 256 * k) & 3;
+        off[k] = !none && ck * kKC + cc * 8 < cin ? wrel[k] + ck * kKC * 2 : kOOB;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < WIT; ++k) wreg[k] = buf_load16(wsrc, off[k]);
+  };
+  auto store_w = [&](const uint4* wreg) {
+#pragma unroll
+    for (int k = 0; k < WIT; ++k) {
+      const int e = tid + 256 * k;
+      if (e < C::W_CH) wts[swz(e >> 2, e & 3)] = wreg[k];
     }
   };
-  // every halo load is issued (after the weight prologue's) before the first
-  // LDS store, so their latencies overlap instead of adding up
-  constexpr int HTOT = C::HH * C::HW * CH8, HIT = (HTOT + 255) / 256;
-  constexpr int D = BPT >= 8 ? 1 : (BPT >= 4 ? 2 : (BPT >= 2 ? 4 : 8));
-  uint4 b0[BPT], ring[D][BPT], hreg[HIT];
-  const int t = static_cast<int>(blockIdx.x);
-  {
-    const int n = t / (tiles_x * tiles_y);
-    const int b = t - n * tiles_x * tiles_y;
-    const int oy0 = (b / tiles_x) * TH, ox0 = (b % tiles_x) * kTW;
-    load_b(0, b0);
+  f32x16 acc[MB][NB];
+  // Epilogue of tile u: ReLU and bf16 into a staging tile in LDS (over the
+  // halo, and over the weights when a step re-stages them), then 16-byte
+  // stores with consecutive lanes on consecutive addresses, and the 2x2
+  // pool from the staging tile.  Output channels j*32 + 8q + 4*lh .. +3 of
+  // pixel l32 are accumulator elements 4q .. 4q+3.  When the staging tile
+  // does not fit it is written and stored in two passes of TH/2 rows.  With
+  // `dummy` only the global stores are issued, all out of range: the
+  // prologue issues the same stores as a loop iteration, so the loop entry
+  // and its back edge leave the same memory operations behind the prefetch
+  // and the wait for it is exact on both.
+  constexpr int LDO = BN + 8;  // staging row (one pixel) in bf16
+  constexpr int OCH = BN / 8;  // 16-byte chunks per output pixel
+  constexpr size_t STG_ROOM = static_cast<size_t>(NCH > 1 ? C::HALO_CH + C::W_CH : C::HALO_CH) * 16;
+  constexpr int NPASS = static_cast<size_t>(TH) * kTW * LDO * 2 <= STG_ROOM ? 1 : 2;
+  constexpr int RP = TH / NPASS;  // tile rows per pass
+  static_assert(static_cast<size_t>(RP) * kTW * LDO * 2 <= STG_ROOM, "staging tile too large");
+  static_assert((RP * kTW * OCH) % 256 == 0 && RP % 2 == 0 && RP % MB == 0, "pass shape");
+  constexpr int NOUT = RP * kTW * OCH / 256;                                     // stores per thread and pass
+  constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + 255) / 256 : 0;  // pool stores per thread and pass
+  uint16_t* stg = reinterpret_cast<uint16_t*>(lds4);
+  auto epilogue = [&](const Tile& u, bool dummy) {
+    const int n = u.n, oy0 = u.ty * TH, ox0 = u.tx * kTW;
+    const bool out_full = oy0 + TH <= s.h && ox0 + kTW <= s.w;
+    const __amdgpu_buffer_rsrc_t yb = buf_rsrc(y.p + y.off + ((static_cast<long long>(n) * s.h + oy0) * s.w + ox0) * y.ld);
+    const int ph = s.h / 2, pw = s.w / 2;
+    const __amdgpu_buffer_rsrc_t pb =
+        buf_rsrc(POOL ? pool.p + pool.off + ((static_cast<long long>(n) * ph + oy0 / 2) * pw + ox0 / 2) * pool.ld : y.p);
 #pragma unroll
-    for (int j = 1; j <= D; ++j) load_b(j, ring[(j - 1) % D]);
+    for (int pass = 0; pass < NPASS; ++pass) {
+      if (!dummy) {
+        __syncthreads();  // every wave is done with the halo / weights (or the previous pass)
+        if (wave * MB / RP == pass) {
 #pragma unroll
-    for (int i = 0; i < HIT; ++i) {
-      const int e = tid + i * 256;
-      const int hp = e / CH8, cc = e - hp * CH8;
-      const int r = oy0 - 1 + hp / C::HW, c = ox0 - 1 + hp % C::HW;
-      uint4 v = {0u, 0u, 0u, 0u};
-      if (e < HTOT && r >= 0 && r < s.h && c >= 0 && c < s.w && cc * 8 < x.c) {
-        const long long src = UP ? (static_cast<long long>(n) * hi + (r >> 1)) * wi + (c >> 1)
-                                 : (static_cast<long long>(n) * hi + r) * wi + c;
-        v = *reinterpret_cast<const uint4*>(x.p + src * x.ld + x.off + cc * 8);
-      }
-      hreg[i] = v;
-    }
+          for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int i = 0; i < HIT; ++i) {
-      const int e = tid + i * 256;
-      if (e < HTOT) {
-        const int hp = e / CH8, cc = e - hp * CH8;
-        *reinterpret_cast<uint4*>(halo + hp * C::LDR + cc * 8) = hreg[i];
-      }
-    }
-    store_b(0, b0);
-    __syncthreads();
-    f32x4 acc[MB][NB];
+            for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int dr = tap / 3, dc = tap - (tap / 3) * 3;
-      const uint16_t* B = bbuf + (C::NBUF == 2 ? (tap & 1) : 0) * C::BTAP;
-#pragma unroll
-      for (int ks = 0; ks < CP / 32; ++ks) {
-        bf16x8 bf[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) bf[j] = lds_frag(B + (j * 16 + (lane & 15)) * C::LDB + ks * 32 + (lane >> 4) * 8);
-#pragma unroll
-        for (int m = 0; m < MB; ++m) {
-          const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
-          const bf16x8 a = lds_frag(halo + ((row + dr) * C::HW + col + dc) * C::LDR + ks * 32 + (lane >> 4) * 8);
-#pragma unroll
-          for (int j = 0; j < NB; ++j) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j], a, acc[m][j], 0, 0, 0);
+              for (int q = 0; q < 4; ++q) {
+                const f32x16& v = acc[m][j];
+                const int lrow = wave * MB + m - pass * RP;
+                *reinterpret_cast<uint2*>(stg + (lrow * kTW + l32) * LDO + j * 32 + 8 * q + 4 * lh) =
+                    uint2{pack_bf16(fmaxf(v[4 * q], 0.f), fmaxf(v[4 * q + 1], 0.f)),
+                          pack_bf16(fmaxf(v[4 * q + 2], 0.f), fmaxf(v[4 * q + 3], 0.f))};
+              }
         }
+        __syncthreads();
       }
-      if (tap + 1 < 9) {
-        if (C::NBUF == 1) __syncthreads();  // every wave is done with the single buffer
-        store_b(C::NBUF == 2 ? (tap + 1) & 1 : 0, ring[tap % D]);  // the slot of tap + 1
-        if (tap + 1 + D < 9) load_b(tap + 1 + D, ring[tap % D]);
+#pragma unroll
+      for (int k = 0; k < NOUT; ++k) {
+        const int e = tid + 256 * k, px = e / OCH, c = e % OCH, lrow = px / kTW, col = px % kTW;
+        const int row = pass * RP + lrow;
+        const int ok = !dummy & (out_full | ((oy0 + row < s.h) & (ox0 + col < s.w)));
+        const uint4 v = dummy ? uint4{0u, 0u, 0u, 0u} : *reinterpret_cast<const uint4*>(stg + (lrow * kTW + col) * LDO + c * 8);
+        // (distinct out-of-range offsets: identical ones would let the compiler drop all but the last)
+        buf_store16(yb, ok ? ((row * s.w + col) * y.ld + c * 8) * 2 : kOOB + (pass * NOUT + k) * 16, v);
       }
-      __syncthreads();
-    }
-    // epilogue: bias + ReLU + bf16 into the staging tile (the halo is no
-    // longer read); a lane holds 4 consecutive channels of one pixel, written
-    // as one 8-byte store
-    uint16_t* ot = smem;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int ch = j * 16 + (lane >> 4) * 4;
-      float bb[4];
+      for (int k = 0; k < NPOOL; ++k) {
+        // pooled pixel (qr, qc) of this pass: ((a + b) + c) + d of the staged
+        // bf16 values, a b over c d
+        const int e = tid + 256 * k, qi = e / OCH, c = e % OCH, qr = qi / (kTW / 2), qc = qi % (kTW / 2);
+        const int prow = pass * RP / 2 + qr;
+        const int ok = !dummy & (e < (RP / 2) * (kTW / 2) * OCH) &
+                       (out_full | ((oy0 / 2 + prow < ph) & (ox0 / 2 + qc < pw)));
+        uint4 o = {0u, 0u, 0u, 0u};
+        if (!dummy && e < (RP / 2) * (kTW / 2) * OCH) {
+          const uint16_t* t00 = stg + ((2 * qr) * kTW + 2 * qc) * LDO + c * 8;
+          const uint4 a4 = *reinterpret_cast<const uint4*>(t00);
+          const uint4 b4 = *reinterpret_cast<const uint4*>(t00 + LDO);
+          const uint4 c4 = *reinterpret_cast<const uint4*>(t00 + kTW * LDO);
+          const uint4 d4 = *reinterpret_cast<const uint4*>(t00 + (kTW + 1) * LDO);
+          const uint32_t A[4] = {a4.x, a4.y, a4.z, a4.w}, B[4] = {b4.x, b4.y, b4.z, b4.w},
+                         Cc[4] = {c4.x, c4.y, c4.z, c4.w}, D[4] = {d4.x, d4.y, d4.z, d4.w};
+          uint32_t r4[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) bb[r] = bias[ch + r];
-#pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const int row = wave * WR + m / 2, col = (m & 1) * 16 + (lane & 15);
-        uint32_t h[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float v = acc[m][j][r] + bb[r];
-          h[r] = to_bf16(v > 0.f ? v : 0.f);
-        }
-        *reinterpret_cast<uint2*>(ot + (row * kTW + col) * C::LDO + ch) = uint2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
-      }
-    }
-    __syncthreads();
-    constexpr int OCH = BN / 8;
-    for (int e = tid; e < TH * kTW * OCH; e += 256) {
-      const int pi = e / OCH, cc = e - pi * OCH;
-      const int r = oy0 + pi / kTW, c = ox0 + pi % kTW;
-      if (r < s.h && c < s.w) {
-        const long long p = (static_cast<long long>(n) * s.h + r) * s.w + c;
-        *reinterpret_cast<uint4*>(y.p + p * y.ld + y.off + cc * 8) =
-            *reinterpret_cast<const uint4*>(ot + pi * C::LDO + cc * 8);
-      }
-    }
-    if (pool.p) {
-      const int ph = s.h / 2, pw = s.w / 2;
-      for (int e = tid; e < (TH / 2) * (kTW / 2) * OCH; e += 256) {
-        const int qi = e / OCH, cc = e - qi * OCH;
-        const int qr = qi / (kTW / 2), qc = qi - qr * (kTW / 2);
-        const int r = oy0 / 2 + qr, c = ox0 / 2 + qc;
-        if (r < ph && c < pw) {
-          const uint16_t* t00 = ot + ((2 * qr) * kTW + 2 * qc) * C::LDO + cc * 8;
-          const uint4 a = *reinterpret_cast<const uint4*>(t00);
-          const uint4 bq = *reinterpret_cast<const uint4*>(t00 + C::LDO);
-          const uint4 c2 = *reinterpret_cast<const uint4*>(t00 + kTW * C::LDO);
-          const uint4 d = *reinterpret_cast<const uint4*>(t00 + (kTW + 1) * C::LDO);
-          const uint32_t A[4] = {a.x, a.y, a.z, a.w}, Bw[4] = {bq.x, bq.y, bq.z, bq.w},
-                         Cw[4] = {c2.x, c2.y, c2.z, c2.w}, Dw[4] = {d.x, d.y, d.z, d.w};
-          uint32_t o[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            uint32_t packed = 0;
-#pragma unroll
-            for (int hlf = 0; hlf < 2; ++hlf) {
-              const int sh = hlf * 16;
-              const float v = from_bf16(static_cast<uint16_t>(A[k] >> sh)) + from_bf16(static_cast<uint16_t>(Bw[k] >> sh)) +
-                              from_bf16(static_cast<uint16_t>(Cw[k] >> sh)) + from_bf16(static_cast<uint16_t>(Dw[k] >> sh));
-              packed |= static_cast<uint32_t>(to_bf16(0.25f * v)) << sh;
-            }
-            o[k] = packed;
+          for (int h = 0; h < 4; ++h) {
+            const float lo = ((bf16_lo(A[h]) + bf16_lo(B[h])) + bf16_lo(Cc[h])) + bf16_lo(D[h]);
+            const float hi2 = ((bf16_hi(A[h]) + bf16_hi(B[h])) + bf16_hi(Cc[h])) + bf16_hi(D[h]);
+            r4[h] = pack_bf16(0.25f * lo, 0.25f * hi2);
           }
-          const long long p = (static_cast<long long>(n) * ph + r) * pw + c;
-          *reinterpret_cast<uint4*>(pool.p + p * pool.ld + pool.off + cc * 8) = uint4{o[0], o[1], o[2], o[3]};
+          o = uint4{r4[0], r4[1], r4[2], r4[3]};
         }
+        buf_store16(pb, ok ? ((prow * pw + qc) * pool.ld + c * 8) * 2 : kOOB + (NPASS * NOUT + pass * NPOOL + k) * 16, o);
       }
     }
+  };
+
+  uint4 hreg[HIT], wreg[WIT];
+  if (tid < BN) lbias[tid] = bias[tid];
+  Tile cur = decode(t_begin), nxt = cur;  // the tile computed, the tile prefetched
+  if (NCH == 1) {  // one slice: the weights stay in LDS for every tile
+    load_w(0, false, wreg);
+    store_w(wreg);
+  }
+  load_halo(nxt, 0, false, hreg);
+  if (NCH > 1) load_w(0, false, wreg);
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[m][j][r] = 0.f;
+  epilogue(cur, true);
+  const int my_tiles = nsteps / NCH;
+  for (int it = 0; it < my_tiles; ++it) {
+#pragma unroll
+    for (int ck = 0; ck < NCH; ++ck) {
+      __syncthreads();  // the previous step's fragment reads are done
+#pragma unroll
+      for (int k = 0; k < HIT; ++k)
+        if (tid + 256 * k < C::HALO_EL) halo[hlds + 64 * C::HPITCH * k] = hreg[k];
+      if (NCH > 1) store_w(wreg);
+      __syncthreads();
+      // prefetch the next step: the next slice, or slice 0 of the next tile
+      const bool none = ck == NCH - 1 && it + 1 == my_tiles;
+      if (ck == NCH - 1 && !none) advance(nxt);
+      load_halo(nxt, (ck + 1) % NCH, none, hreg);
+      if (NCH > 1) load_w((ck + 1) % NCH, none, wreg);
+      // keep the prefetch ahead of the taps: the scheduler would otherwise
+      // sink the loads below the MFMAs and expose their latency
+      __builtin_amdgcn_sched_barrier(0);
+      if (ck == 0) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 b4 = *reinterpret_cast<const f32x4*>(lbias + j * 32 + 8 * q + 4 * lh);
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[m][j][4 * q + r] = b4[r];
+          }
+      }
+      // 18 (tap, 16-channel half) steps; the fragments of step i + 1 are
+      // read while step i's MFMAs run
+      bf16x8 wf[2][NB], hf[2][MB];
+      auto frag = [&](int i, int bsel) {
+        const int tap = i >> 1, kh = i & 1, dr = tap / 3, dc = tap - (tap / 3) * 3;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) wf[bsel][j] = __builtin_bit_cast(bf16x8, wts[(tap * BN + j * 32) * 4 + boff[kh]]);
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+          hf[bsel][m] = __builtin_bit_cast(bf16x8, halo[aoff + ((m + dr) * C::HW + dc) * C::HPITCH + 2 * kh]);
+      };
+      frag(0, 0);
+#pragma unroll
+      for (int i = 0; i < 18; ++i) {
+        if (i + 1 < 18) frag(i + 1, (i + 1) & 1);
+        __builtin_amdgcn_sched_barrier(0);  // the reads stay ahead of this step's MFMAs
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            acc[m][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wf[i & 1][j], hf[i & 1][m], acc[m][j], 0, 0, 0);
+      }
+    }
+    epilogue(cur, false);
+    cur = nxt;
   }
 }
 
@@ -774,43 +953,77 @@ inline unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t
 
 }  // namespace
 
-template <int BN, int CP, int TH, bool UP>
-hipError_t launch_tile(const Map& x, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
+template <int BN, int CP, int TH, bool UP, bool POOL>
+hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
                        const Shape& s, hipStream_t st) {
-  using C = TileCfg<BN, CP, TH>;
-  const void* f = reinterpret_cast<const void*>(&conv_fwd_tile_k<BN, CP, TH, UP>);
+  using C = ConvCfg<BN, TH>;
+  const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, POOL>);
+  const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
+  if (tiles == 0) return hipSuccess;
+  if (tiles > (1LL << 30)) return hipErrorInvalidValue;
+  // resident workgroups per compute unit, per device
+  static int per_cu[64] = {0};
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
   if (C::BYTES > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(C::BYTES));
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(C::BYTES));
     if (e != hipSuccess) return e;
   }
-  const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
-  if (tiles > (1LL << 30)) return hipErrorInvalidValue;
-  conv_fwd_tile_k<BN, CP, TH, UP><<<static_cast<unsigned>(tiles), 256, C::BYTES, st>>>(x, w, bias, y, pool, s);
+  if (per_cu[dev] == 0) {
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, C::BYTES);
+    if (e != hipSuccess) return e;
+    per_cu[dev] = nb > 0 ? nb : 1;
+  }
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const long long grid = tiles < static_cast<long long>(cus) * per_cu[dev] ? tiles : static_cast<long long>(cus) * per_cu[dev];
+  conv_fwd_k<BN, CP, TH, UP, POOL><<<static_cast<unsigned>(grid), 256, C::BYTES, st>>>(x, x2, w, bias, y, pool, s);
   return hipGetLastError();
 }
 
+template <int BN, int CP, int TH, bool UP>
+hipError_t launch_tile(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y,
+                       const Map& pool, const Shape& s, hipStream_t st) {
+  if (pool.p) {
+    if constexpr ((TH / 4) % 2 == 0) return launch_conv<BN, CP, TH, UP, true>(x, x2, w, bias, y, pool, s, st);
+    return hipErrorInvalidValue;
+  }
+  return launch_conv<BN, CP, TH, UP, false>(x, x2, w, bias, y, pool, s, st);
+}
+
 template <bool UP>
-hipError_t conv_tile(const Map& x, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
-                     const Shape& s, hipStream_t st) {
-  const int cp = (x.c + 31) / 32 * 32;
-  if (y.c == 32 && cp == 32) return launch_tile<32, 32, 8, UP>(x, w, bias, y, pool, s, st);
-  if (y.c == 32 && cp == 64) return launch_tile<32, 64, 8, UP>(x, w, bias, y, pool, s, st);
-  if (y.c == 64 && cp == 32) return launch_tile<64, 32, 8, UP>(x, w, bias, y, pool, s, st);
-  if (y.c == 64 && cp == 64) return launch_tile<64, 64, 8, UP>(x, w, bias, y, pool, s, st);
-  if (y.c == 64 && cp == 128) return launch_tile<64, 128, 4, UP>(x, w, bias, y, pool, s, st);
-  if (y.c == 128 && cp == 64) return launch_tile<128, 64, 4, UP>(x, w, bias, y, pool, s, st);
-  if (y.c == 128 && cp == 128) return launch_tile<128, 128, 4, UP>(x, w, bias, y, pool, s, st);
+hipError_t conv_tile(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y,
+                     const Map& pool, const Shape& s, hipStream_t st) {
+  const int cp = (x.c + x2.c + 31) / 32 * 32;
+#define DFB_CONV(BN_, CP_, TH_) \
+  if (y.c == BN_ && cp == CP_) return launch_tile<BN_, CP_, TH_, UP>(x, x2, w, bias, y, pool, s, st);
+  DFB_CONV(32, 32, DFB_TH_32_32)
+  DFB_CONV(32, 64, DFB_TH_32_64)
+  DFB_CONV(64, 32, 8)
+  DFB_CONV(64, 64, DFB_TH_64_64)
+  DFB_CONV(64, 128, DFB_TH_64_128)
+  DFB_CONV(128, 64, 4)
+  DFB_CONV(128, 128, 4)
+#undef DFB_CONV
   return hipErrorInvalidValue;
 }
 
 hipError_t conv3x3_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y, const Shape& s,
-                       hipStream_t st, bool up, const Map* pool) {
-  if (x.c % 8 || x.ld % 8 || x.off % 8 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
-  if ((up || pool) && (s.h % 2 || s.w % 2)) return hipErrorInvalidValue;
+                       hipStream_t st, bool up, const Map* pool, const Map* x2) {
   const Map none{nullptr, 0, 0, 0};
+  const Map& xb = x2 ? *x2 : none;
+  if (x.c % 8 || x.ld % 8 || x.off % 8 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
+  if (x2 && (x.c % 32 || xb.c % 8 || xb.ld != x.ld || xb.off % 8)) return hipErrorInvalidValue;
+  if ((up || pool) && (s.h % 2 || s.w % 2)) return hipErrorInvalidValue;
+  // per-image element offsets are 32-bit
+  const long long img = static_cast<long long>(up ? s.h / 2 : s.h) * (up ? s.w / 2 : s.w) * x.ld;
+  if (img >= (1LL << 30) || static_cast<long long>(s.h) * s.w * y.ld >= (1LL << 30)) return hipErrorInvalidValue;
   const Map& pl = pool ? *pool : none;
   if (pool && (pl.ld % 8 || pl.off % 8 || pl.c != y.c)) return hipErrorInvalidValue;
-  return up ? conv_tile<true>(x, w_fwd, bias, y, pl, s, st) : conv_tile<false>(x, w_fwd, bias, y, pl, s, st);
+  return up ? conv_tile<true>(x, xb, w_fwd, bias, y, pl, s, st) : conv_tile<false>(x, xb, w_fwd, bias, y, pl, s, st);
 }
 
 hipError_t conv3x3_gate(const MapF& dy, const Map& y, const Map& g, float* db, float* partial, const Shape& s,

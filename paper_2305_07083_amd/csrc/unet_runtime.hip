@@ -86,6 +86,7 @@ struct dfb_denoiser_ctx {
   int64_t frame_px = 0;
   float* frame_out = nullptr;
   Shape last{0, 0, 0};
+  bool planar = false;  // the last forward kept the skip concatenations as separate maps
   std::vector<void*> allocs;
 };
 
@@ -135,9 +136,27 @@ dfb_status refresh(dfb_denoiser_ctx* n) {
   return DFB_OK;
 }
 
+// Where the halves of the two skip concatenations live.  Training keeps
+// each concatenation interleaved per pixel (cat1 [p][64], cat2 [p][128]), as
+// the backward pass reads it; inference stores each half as a map of its own
+// inside the same allocation (cat1: [p][32] up1, then [p][32] enc1b; cat2:
+// [p][64] up2, then [p][64] enc2b), so that every layer writes and reads
+// whole pixel rows and no 64-byte half-line is written on its own.
+struct CatLayout {
+  Map up1, enc1b, up2, enc2b;
+};
+CatLayout cat_layout(const dfb_denoiser_ctx* n, const Shape& s0, bool planar) {
+  const int64_t p0 = s0.pixels(), p1 = p0 / 4;
+  if (planar)
+    return {mp(n->cat1, 32, 0, 32), mp(n->cat1 + p0 * 32, 32, 0, 32), mp(n->cat2, 64, 0, 64),
+            mp(n->cat2 + p1 * 64, 64, 0, 64)};
+  return {mp(n->cat1, 64, 0, 32), mp(n->cat1, 64, 32, 32), mp(n->cat2, 128, 0, 64), mp(n->cat2, 128, 64, 64)};
+}
+
 // forward on in (f32 NHWC 6 ch) -> n->out.  The 2x2 pools come out of the
 // enc1b / enc2b epilogues and the up-sampling is read through by up2 / up1;
-// `training` also materialises the up-sampled maps the backward pass reads.
+// `training` also materialises the up-sampled maps the backward pass reads
+// and keeps the skip concatenations interleaved.
 dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training) {
   const Shape s1{s0.n, s0.h / 2, s0.w / 2}, s2{s0.n, s0.h / 4, s0.w / 4};
   hipStream_t st = n->stream;
@@ -145,23 +164,31 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
   auto B = [&](int i) { return W + n->off_b[i]; };
   using dfb::unet::conv3x3_fwd;
   const Map pool1 = mp(n->pool1, 32, 0, 32), pool2 = mp(n->pool2, 64, 0, 64);
+  const CatLayout c = cat_layout(n, s0, !training);
   NHIP(n, dfb::unet::pack_input(in, 6, n->xin, s0, st));
   NHIP(n, conv3x3_fwd(mp(n->xin, 8, 0, 8), n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
-  NHIP(n, conv3x3_fwd(mp(n->e1a, 32, 0, 32), n->wf[ENC1B], B(ENC1B), mp(n->cat1, 64, 32, 32), s0, st, false, &pool1));
+  NHIP(n, conv3x3_fwd(mp(n->e1a, 32, 0, 32), n->wf[ENC1B], B(ENC1B), c.enc1b, s0, st, false, &pool1));
   NHIP(n, conv3x3_fwd(pool1, n->wf[ENC2A], B(ENC2A), mp(n->e2a, 64, 0, 64), s1, st));
-  NHIP(n, conv3x3_fwd(mp(n->e2a, 64, 0, 64), n->wf[ENC2B], B(ENC2B), mp(n->cat2, 128, 64, 64), s1, st, false, &pool2));
+  NHIP(n, conv3x3_fwd(mp(n->e2a, 64, 0, 64), n->wf[ENC2B], B(ENC2B), c.enc2b, s1, st, false, &pool2));
   NHIP(n, conv3x3_fwd(pool2, n->wf[ENC3A], B(ENC3A), mp(n->e3a, 128, 0, 128), s2, st));
   NHIP(n, conv3x3_fwd(mp(n->e3a, 128, 0, 128), n->wf[ENC3B], B(ENC3B), mp(n->e3b, 128, 0, 128), s2, st));
   if (training) NHIP(n, dfb::unet::upsample2(mp(n->e3b, 128, 0, 128), mp(n->up3, 128, 0, 128), s2, st));
-  NHIP(n, conv3x3_fwd(mp(n->e3b, 128, 0, 128), n->wf[UP2], B(UP2), mp(n->cat2, 128, 0, 64), s1, st, true));
-  NHIP(n, conv3x3_fwd(mp(n->cat2, 128, 0, 128), n->wf[DEC2A], B(DEC2A), mp(n->d2a, 64, 0, 64), s1, st));
+  NHIP(n, conv3x3_fwd(mp(n->e3b, 128, 0, 128), n->wf[UP2], B(UP2), c.up2, s1, st, true));
+  if (training)
+    NHIP(n, conv3x3_fwd(mp(n->cat2, 128, 0, 128), n->wf[DEC2A], B(DEC2A), mp(n->d2a, 64, 0, 64), s1, st));
+  else
+    NHIP(n, conv3x3_fwd(c.up2, n->wf[DEC2A], B(DEC2A), mp(n->d2a, 64, 0, 64), s1, st, false, nullptr, &c.enc2b));
   NHIP(n, conv3x3_fwd(mp(n->d2a, 64, 0, 64), n->wf[DEC2B], B(DEC2B), mp(n->d2b, 64, 0, 64), s1, st));
   if (training) NHIP(n, dfb::unet::upsample2(mp(n->d2b, 64, 0, 64), mp(n->upd2, 64, 0, 64), s1, st));
-  NHIP(n, conv3x3_fwd(mp(n->d2b, 64, 0, 64), n->wf[UP1], B(UP1), mp(n->cat1, 64, 0, 32), s0, st, true));
-  NHIP(n, conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
+  NHIP(n, conv3x3_fwd(mp(n->d2b, 64, 0, 64), n->wf[UP1], B(UP1), c.up1, s0, st, true));
+  if (training)
+    NHIP(n, conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
+  else
+    NHIP(n, conv3x3_fwd(c.up1, n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st, false, nullptr, &c.enc1b));
   NHIP(n, conv3x3_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), mp(n->d1b, 32, 0, 32), s0, st));
   NHIP(n, dfb::unet::out_conv_fwd(mp(n->d1b, 32, 0, 32), W + n->off_ow, W + n->off_ob, in, 6, n->out, s0, st));
   n->last = s0;
+  n->planar = !training;
   return DFB_OK;
 }
 
@@ -391,13 +418,11 @@ dfb_status dfb_denoiser_read_activation(dfb_denoiser n, int32_t layer, void* hos
   const int co = kConv[layer].co;
   if (bytes != px * co * 2) return nfail(n, DFB_ERR_INVALID_ARG, "wrong byte count for this layer");
   // where each layer's output lives (ld, off)
-  struct Loc {
-    const uint16_t* p;
-    int ld, off;
-  } loc[12] = {{n->e1a, 32, 0},  {n->cat1, 64, 32}, {n->e2a, 64, 0},  {n->cat2, 128, 64},
-               {n->e3a, 128, 0}, {n->e3b, 128, 0},  {n->cat2, 128, 0}, {n->d2a, 64, 0},
-               {n->d2b, 64, 0},  {n->cat1, 64, 0},  {n->d1a, 32, 0},  {n->d1b, 32, 0}};
-  const Loc& L = loc[layer];
+  const CatLayout c = cat_layout(n, s0, n->planar);
+  const Map loc[12] = {mp(n->e1a, 32, 0, 32),   c.enc1b, mp(n->e2a, 64, 0, 64), c.enc2b,
+                       mp(n->e3a, 128, 0, 128), mp(n->e3b, 128, 0, 128), c.up2, mp(n->d2a, 64, 0, 64),
+                       mp(n->d2b, 64, 0, 64),   c.up1,   mp(n->d1a, 32, 0, 32), mp(n->d1b, 32, 0, 32)};
+  const Map& L = loc[layer];
   NHIP(n, hipMemcpy2DAsync(host, co * 2, L.p + L.off, L.ld * 2, co * 2, px, hipMemcpyDeviceToHost, n->stream));
   NHIP(n, hipStreamSynchronize(n->stream));
   return DFB_OK;

@@ -81,6 +81,34 @@ def test_forward_and_gradients_match_oracle(dfb, n, h, w):
         assert rel_l2(a, b) <= 2e-2 and cos >= 0.999, (k, rel_l2(a, b), cos)
 
 
+@pytest.mark.timeout(600)
+def test_forward_many_tiles_per_workgroup(dfb):
+    """8 x 256 x 512: every conv layer has more output tiles than resident
+    workgroups (each workgroup walks several tiles and carries the next
+    step's loads across tile boundaries), and most tiles are away from the
+    image border (the unchecked load path)."""
+    torch = torch_dev()
+    n, h, w = 8, 256, 512
+    rng = np.random.default_rng(99)
+    p = trained_like_params(11)
+    x, _ = make_batch(rng, n, h, w)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty((n, h, w, 3), dtype=torch.float32, device="cuda")
+    net = dfb.dfb_denoiser_create(dfb.UnetConfig(n * h * w, 0, 0, 0, 0), stream_handle())
+    try:
+        dfb.dfb_denoiser_set_params(net, dfb.unet_params_to_flat(p))
+        dfb.dfb_denoiser_forward(net, xd, out, n, h, w)
+        acts = [bf16_to_f64(dfb.dfb_denoiser_read_activation(net, i, n, h, w)) for i in range(12)]
+        got_out = out.cpu().numpy()
+    finally:
+        dfb.dfb_denoiser_destroy(net)
+    p64 = {k: v.astype(np.float64) for k, v in p.items()}
+    ref_out, cache = unet.forward(p64, x.astype(np.float64), x[..., :3].astype(np.float64), bf16_on=True)
+    for i, (name, _, _) in enumerate(unet.CONV3):
+        assert rel_l2(acts[i], cache[name]) <= 1e-2, (name, rel_l2(acts[i], cache[name]))
+    assert rel_l2(got_out - x[..., :3], ref_out - x[..., :3]) <= 1e-2
+
+
 def test_adam_step_matches_oracle(dfb):
     torch = torch_dev()
     rng = np.random.default_rng(5)
