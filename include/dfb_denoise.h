@@ -66,7 +66,9 @@ dfb_status dfb_denoiser_train_step(dfb_denoiser net, const float* in_dev, const 
 
 /* bfloat16 output (NHWC, uint16 bit patterns) of conv3x3 layer `layer`
  * (0..11, order above) from the last forward, copied to host: bytes must be
- * n*h_l*w_l*c_out*2 for that layer's resolution. */
+ * n*h_l*w_l*c_out*2 for that layer's resolution.  After dfb_denoise the last
+ * layer (11) is not available (DFB_ERR_STATE): that call computes the output
+ * conv in the last layer's epilogue and does not store its activation. */
 dfb_status dfb_denoiser_read_activation(dfb_denoiser net, int32_t layer, void* host, int64_t bytes);
 
 /* The network input of the compositor's current accumulation (its mean,

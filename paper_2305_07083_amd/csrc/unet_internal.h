@@ -57,6 +57,11 @@ hipError_t upsample2(const Map& x, const Map& y, const Shape& s_in, hipStream_t 
 hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in, hipStream_t st);
 hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st);
 
+// The last conv3x3 (32 -> 32, ReLU, bf16) fused with the output conv:
+// out[p][c] = base[p][c] + ob[c] + sum_i y[p][i] ow[i][c] with y the conv's
+// bf16 output, which is not stored (inference).
+hipError_t conv3x3_out_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
+                           const float* base, int base_ld, float* out, const Shape& s, hipStream_t st);
 // out[p][c] = base[p][c] + b[c] + sum_i x[p][i] w[i][c]   (c < 3, f32)
 hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base,
                         int base_ld, float* out, const Shape& s, hipStream_t st);

@@ -132,6 +132,7 @@ struct ConvCfg {
 // operations is known at compile time and waiting for the prefetched loads
 // never waits for the stores issued after them.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kOOB = static_cast<int>(0x80000000u);
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
@@ -162,10 +163,24 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 __device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
-template <int BN, int CP, int TH, bool UP, bool POOL>
+// Epilogue kinds: plain, plus the 2x2 average pool, or instead of storing
+// y the network's 1x1 output conv and residual (inference, 32 channels).
+enum Epi { kEpiPlain = 0, kEpiPool = 1, kEpiOut = 2 };
+struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c < 3
+  const float* w;    // [32][3]
+  const float* b;    // [3]
+  const float* base; // [p][base_ld]
+  int base_ld;
+  float* out;        // [p][3]
+};
+
+template <int BN, int CP, int TH, bool UP, int EPI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH>::WAVES)))
-conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, Shape s) {
+conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
+           Shape s) {
   using C = ConvCfg<BN, TH>;
+  constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
+  static_assert(!OUT || (BN == 32 && TH * kTW == 256), "the output conv takes one pixel per thread");
   constexpr int NCH = CP / kKC, MB = TH / 4, NB = BN / 32;  // tile rows and 32-channel blocks per wave
   constexpr int HIT = C::HIT, WIT = C::WIT;
   static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
@@ -174,6 +189,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   uint4* wts = lds4 + C::HALO_CH;  // [9 * BN][4]
   float* lbias = reinterpret_cast<float*>(wts + C::W_CH);  // [BN]: read per tile through LDS, so
   // starting a tile waits on no global load issued after the prefetch
+  float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
   const int tiles_x = (s.w + kTW - 1) / kTW, tiles_y = (s.h + TH - 1) / TH;
   const long long tiles = static_cast<long long>(s.n) * tiles_x * tiles_y;
@@ -304,9 +320,10 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   constexpr int RP = TH / NPASS;  // tile rows per pass
   static_assert(static_cast<size_t>(RP) * kTW * LDO * 2 <= STG_ROOM, "staging tile too large");
   static_assert((RP * kTW * OCH) % 256 == 0 && RP % 2 == 0 && RP % MB == 0, "pass shape");
-  constexpr int NOUT = RP * kTW * OCH / 256;                                     // stores per thread and pass
+  constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / 256;                           // stores per thread and pass
   constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + 255) / 256 : 0;  // pool stores per thread and pass
   uint16_t* stg = reinterpret_cast<uint16_t*>(lds4);
+  float bcur[3] = {0.f, 0.f, 0.f};  // kEpiOut: base of this thread's pixel of the tile being computed
   auto epilogue = [&](const Tile& u, bool dummy) {
     const int n = u.n, oy0 = u.ty * TH, ox0 = u.tx * kTW;
     const bool out_full = oy0 + TH <= s.h && ox0 + kTW <= s.w;
@@ -371,11 +388,52 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
         }
         buf_store16(pb, ok ? ((prow * pw + qc) * pool.ld + c * 8) * 2 : kOOB + (NPASS * NOUT + pass * NPOOL + k) * 16, o);
       }
+      if (OUT) {
+        // pixel tid of the tile: the 1x1 conv over its 32 staged bf16
+        // channels, in channel order, then (base + b) + sum
+        const int lrow = tid / kTW, col = tid % kTW, row = pass * RP + lrow;
+        const int ok = !dummy & (out_full | ((oy0 + row < s.h) & (ox0 + col < s.w)));
+        float o3[3] = {0.f, 0.f, 0.f};
+        if (!dummy) {
+          float a3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+          for (int c8 = 0; c8 < 4; ++c8) {
+            const uint4 v = *reinterpret_cast<const uint4*>(stg + (lrow * kTW + col) * LDO + c8 * 8);
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int i = c8 * 8 + k;
+              const float xi = (k & 1) ? bf16_hi(wv[k >> 1]) : bf16_lo(wv[k >> 1]);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) a3[c] = fmaf(xi, lout[i * 3 + c], a3[c]);
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c) o3[c] = (bcur[c] + lout[96 + c]) + a3[c];
+        }
+        const __amdgpu_buffer_rsrc_t ob =
+            buf_rsrc(oc.out + ((static_cast<long long>(n) * s.h + oy0) * s.w + ox0) * 3);
+        const u32x3 ov = {__float_as_uint(o3[0]), __float_as_uint(o3[1]), __float_as_uint(o3[2])};
+        __builtin_amdgcn_raw_buffer_store_b96(ov, ob, ok ? (row * s.w + col) * 12 : kOOB + pass * 16, 0, 0);
+      }
     }
   };
 
   uint4 hreg[HIT], wreg[WIT];
+  float breg[3];  // kEpiOut: base of this thread's pixel of the tile being prefetched
+  auto load_base = [&](const Tile& u, bool none) {
+    if (!OUT) return;
+    const int oy0 = u.ty * TH, ox0 = u.tx * kTW, row = tid / kTW, col = tid % kTW;
+    const __amdgpu_buffer_rsrc_t br =
+        buf_rsrc(oc.base + ((static_cast<long long>(u.n) * s.h + oy0) * s.w + ox0) * oc.base_ld);
+    const int ok = !none & (oy0 + row < s.h) & (ox0 + col < s.w);
+    const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(br, ok ? (row * s.w + col) * oc.base_ld * 4 : kOOB, 0, 0);
+    breg[0] = __uint_as_float(v[0]);
+    breg[1] = __uint_as_float(v[1]);
+    breg[2] = __uint_as_float(v[2]);
+  };
   if (tid < BN) lbias[tid] = bias[tid];
+  if (OUT && tid < 99) lout[tid] = tid < 96 ? oc.w[tid] : oc.b[tid - 96];
   Tile cur = decode(t_begin), nxt = cur;  // the tile computed, the tile prefetched
   if (NCH == 1) {  // one slice: the weights stay in LDS for every tile
     load_w(0, false, wreg);
@@ -383,6 +441,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   }
   load_halo(nxt, 0, false, hreg);
   if (NCH > 1) load_w(0, false, wreg);
+  load_base(nxt, false);
 #pragma unroll
   for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -399,12 +458,18 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       for (int k = 0; k < HIT; ++k)
         if (tid + 256 * k < C::HALO_EL) halo[hlds + 64 * C::HPITCH * k] = hreg[k];
       if (NCH > 1) store_w(wreg);
+      if (OUT && ck == 0) {
+        bcur[0] = breg[0];
+        bcur[1] = breg[1];
+        bcur[2] = breg[2];
+      }
       __syncthreads();
       // prefetch the next step: the next slice, or slice 0 of the next tile
       const bool none = ck == NCH - 1 && it + 1 == my_tiles;
       if (ck == NCH - 1 && !none) advance(nxt);
       load_halo(nxt, (ck + 1) % NCH, none, hreg);
       if (NCH > 1) load_w((ck + 1) % NCH, none, wreg);
+      if (ck == NCH - 1) load_base(nxt, none);
       // keep the prefetch ahead of the taps: the scheduler would otherwise
       // sink the loads below the MFMAs and expose their latency
       __builtin_amdgcn_sched_barrier(0);
@@ -953,11 +1018,12 @@ inline unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t
 
 }  // namespace
 
-template <int BN, int CP, int TH, bool UP, bool POOL>
+template <int BN, int CP, int TH, bool UP, int EPI>
 hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
-                       const Shape& s, hipStream_t st) {
+                       const OutConv& oc, const Shape& s, hipStream_t st) {
   using C = ConvCfg<BN, TH>;
-  const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, POOL>);
+  const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, EPI>);
+  const size_t lds = C::BYTES + (EPI == kEpiOut ? 99 * 4 : 0);
   const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
   if (tiles == 0) return hipSuccess;
   if (tiles > (1LL << 30)) return hipErrorInvalidValue;
@@ -967,31 +1033,32 @@ hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const flo
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  if (C::BYTES > 64 * 1024) {
-    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(C::BYTES));
+  if (lds > 64 * 1024) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
   }
   if (per_cu[dev] == 0) {
     int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, C::BYTES);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, lds);
     if (e != hipSuccess) return e;
     per_cu[dev] = nb > 0 ? nb : 1;
   }
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const long long grid = tiles < static_cast<long long>(cus) * per_cu[dev] ? tiles : static_cast<long long>(cus) * per_cu[dev];
-  conv_fwd_k<BN, CP, TH, UP, POOL><<<static_cast<unsigned>(grid), 256, C::BYTES, st>>>(x, x2, w, bias, y, pool, s);
+  conv_fwd_k<BN, CP, TH, UP, EPI><<<static_cast<unsigned>(grid), 256, lds, st>>>(x, x2, w, bias, y, pool, oc, s);
   return hipGetLastError();
 }
 
 template <int BN, int CP, int TH, bool UP>
 hipError_t launch_tile(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y,
                        const Map& pool, const Shape& s, hipStream_t st) {
+  const OutConv none{nullptr, nullptr, nullptr, 0, nullptr};
   if (pool.p) {
-    if constexpr ((TH / 4) % 2 == 0) return launch_conv<BN, CP, TH, UP, true>(x, x2, w, bias, y, pool, s, st);
+    if constexpr ((TH / 4) % 2 == 0) return launch_conv<BN, CP, TH, UP, kEpiPool>(x, x2, w, bias, y, pool, none, s, st);
     return hipErrorInvalidValue;
   }
-  return launch_conv<BN, CP, TH, UP, false>(x, x2, w, bias, y, pool, s, st);
+  return launch_conv<BN, CP, TH, UP, kEpiPlain>(x, x2, w, bias, y, pool, none, s, st);
 }
 
 template <bool UP>
@@ -1096,6 +1163,17 @@ hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in,
 hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st) {
   add_into_k<<<blocks(s.pixels() * dst.c, 256), 256, 0, st>>>(src, dst, s);
   return hipGetLastError();
+}
+
+hipError_t conv3x3_out_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
+                           const float* base, int base_ld, float* out, const Shape& s, hipStream_t st) {
+  if (x.c != 32 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
+  if (static_cast<long long>(s.h) * s.w * x.ld >= (1LL << 30) || static_cast<long long>(s.h) * s.w * base_ld >= (1LL << 29))
+    return hipErrorInvalidValue;
+  const Map none{nullptr, 0, 0, 0};
+  const OutConv oc{ow, ob, base, base_ld, out};
+  const Map y{nullptr, 32, 0, 32};
+  return launch_conv<32, 32, 8, false, kEpiOut>(x, none, w_fwd, bias, y, none, oc, s, st);
 }
 
 hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base, int base_ld, float* out,

@@ -87,6 +87,7 @@ struct dfb_denoiser_ctx {
   float* frame_out = nullptr;
   Shape last{0, 0, 0};
   bool planar = false;  // the last forward kept the skip concatenations as separate maps
+  bool lean = false;    // the last forward fused the output conv and did not store dec1b
   std::vector<void*> allocs;
 };
 
@@ -156,8 +157,9 @@ CatLayout cat_layout(const dfb_denoiser_ctx* n, const Shape& s0, bool planar) {
 // forward on in (f32 NHWC 6 ch) -> n->out.  The 2x2 pools come out of the
 // enc1b / enc2b epilogues and the up-sampling is read through by up2 / up1;
 // `training` also materialises the up-sampled maps the backward pass reads
-// and keeps the skip concatenations interleaved.
-dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training) {
+// and keeps the skip concatenations interleaved.  `lean` (inference only)
+// computes the output conv in dec1b's epilogue and does not store dec1b.
+dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training, bool lean = false) {
   const Shape s1{s0.n, s0.h / 2, s0.w / 2}, s2{s0.n, s0.h / 4, s0.w / 4};
   hipStream_t st = n->stream;
   const float* W = n->w;
@@ -185,10 +187,16 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
     NHIP(n, conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
   else
     NHIP(n, conv3x3_fwd(c.up1, n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st, false, nullptr, &c.enc1b));
-  NHIP(n, conv3x3_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), mp(n->d1b, 32, 0, 32), s0, st));
-  NHIP(n, dfb::unet::out_conv_fwd(mp(n->d1b, 32, 0, 32), W + n->off_ow, W + n->off_ob, in, 6, n->out, s0, st));
+  if (lean && !training) {
+    NHIP(n, dfb::unet::conv3x3_out_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), W + n->off_ow, W + n->off_ob,
+                                       in, 6, n->out, s0, st));
+  } else {
+    NHIP(n, conv3x3_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), mp(n->d1b, 32, 0, 32), s0, st));
+    NHIP(n, dfb::unet::out_conv_fwd(mp(n->d1b, 32, 0, 32), W + n->off_ow, W + n->off_ob, in, 6, n->out, s0, st));
+  }
   n->last = s0;
   n->planar = !training;
+  n->lean = lean && !training;
   return DFB_OK;
 }
 
@@ -417,6 +425,7 @@ dfb_status dfb_denoiser_read_activation(dfb_denoiser n, int32_t layer, void* hos
   const int64_t px = s0.pixels() >> (2 * lvl);
   const int co = kConv[layer].co;
   if (bytes != px * co * 2) return nfail(n, DFB_ERR_INVALID_ARG, "wrong byte count for this layer");
+  if (layer == 11 && n->lean) return nfail(n, DFB_ERR_STATE, "dec1b is not stored by dfb_denoise");
   // where each layer's output lives (ld, off)
   const CatLayout c = cat_layout(n, s0, n->planar);
   const Map loc[12] = {mp(n->e1a, 32, 0, 32),   c.enc1b, mp(n->e2a, 64, 0, 64), c.enc2b,
@@ -459,7 +468,7 @@ dfb_status dfb_denoise(dfb_handle h, dfb_denoiser n, float var_threshold) {
     NHIP(n, hipEventDestroy(e));
   }
   NHIP(n, dfb::unet::frame_to_input(fv.glue, n->frame_in, n->stream));
-  if ((s = forward(n, n->frame_in, Shape{1, H, W}, false)) != DFB_OK) return s;
+  if ((s = forward(n, n->frame_in, Shape{1, H, W}, false, true)) != DFB_OK) return s;
   NHIP(n, dfb::unet::frame_from_output(fv.glue, n->out, var_threshold, fv.denoised, fv.final_out, fv.display_mode,
                                        fv.inv_gamma, n->stream));
   if (n->stream != fv.stream) {

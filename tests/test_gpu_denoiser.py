@@ -109,6 +109,35 @@ def test_forward_many_tiles_per_workgroup(dfb):
     assert rel_l2(got_out - x[..., :3], ref_out - x[..., :3]) <= 1e-2
 
 
+@pytest.mark.timeout(300)
+def test_denoise_matches_forward_on_a_large_frame(dfb):
+    """dfb_denoise (skip concatenations as separate maps, the output conv in
+    the last layer's epilogue, several tiles per workgroup) against
+    dfb_denoiser_forward on the same input, through the oracle's select."""
+    torch = torch_dev()
+    W, H = 1024, 512
+    f = workloads.brick_frame(W, H, (4, 4, 4), 64, seed=21)
+    cfg = dfb.make_config(W, H, 64, work=32, waves=4)
+    with dfb.Compositor(cfg, stream_handle()) as c, dfb.Denoiser(W * H, seed=3, stream=stream_handle()) as dn:
+        for k in range(2):
+            x = workloads.noisy_colour(f, 0.2, 4, k)
+            c.set_fragments(torch.from_numpy(x).cuda(), x.shape[0], f.layers, f.expected)
+            c.composite(accumulate=True)
+        g_mu = c.read(dfb.DFB_BUF_ACCUM_F32)
+        g_v = c.read(dfb.DFB_BUF_TILE_VARIANCE)
+        inp = torch.empty((H, W, 6), dtype=torch.float32, device="cuda")
+        dfb.dfb_denoiser_frame_input(c.h, inp)
+        out = torch.empty((1, H, W, 3), dtype=torch.float32, device="cuda")
+        dfb.dfb_denoiser_forward(dn.net, inp, out, 1, H, W)
+        tau = float(np.median(g_v))
+        dfb.dfb_denoise(c.h, dn.net, tau)
+        got = c.read(dfb.DFB_BUF_DENOISED_F32)
+        with pytest.raises(dfb.DfbError):
+            dfb.dfb_denoiser_read_activation(dn.net, 11, 1, H, W)
+    ref = unet.select(g_mu, g_v, out.cpu().numpy()[0], 2, tau, W, H, 64, 64)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-6)
+
+
 def test_adam_step_matches_oracle(dfb):
     torch = torch_dev()
     rng = np.random.default_rng(5)
