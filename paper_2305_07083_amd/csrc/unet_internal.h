@@ -57,6 +57,12 @@ hipError_t upsample2(const Map& x, const Map& y, const Shape& s_in, hipStream_t 
 hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in, hipStream_t st);
 hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st);
 
+// The first conv3x3 (8 input channels -> 32, ReLU, bf16) with the nine
+// taps packed into a 72-deep contraction, reading either the packed bf16
+// input x (x.c == 8) or, with x null, the f32 network input xin [p][xin_ld]
+// (its first 6 channels, rounded to bf16 as pack_input does).
+hipError_t conv3x3_in_fwd(const Map* x, const float* xin, int xin_ld, const uint16_t* w_fwd, const float* bias,
+                          const Map& y, const Shape& s, hipStream_t st);
 // The last conv3x3 (32 -> 32, ReLU, bf16) fused with the output conv:
 // out[p][c] = base[p][c] + ob[c] + sum_i y[p][i] ow[i][c] with y the conv's
 // bf16 output, which is not stored (inference).

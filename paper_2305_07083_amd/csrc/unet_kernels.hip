@@ -112,7 +112,7 @@ constexpr int kKC = 32;  // input channels per step
 #define DFB_TH_64_128 8
 #endif
 
-template <int BN, int TH>
+template <int BN, int TH, int NCH>
 struct ConvCfg {
   static constexpr int HW = kTW + 2, HH = TH + 2;
   static constexpr int HPITCH = 5;             // 16-byte chunks per halo pixel (4 used)
@@ -120,7 +120,11 @@ struct ConvCfg {
   static constexpr int HALO_EL = HH * HW * 4;       // chunks loaded per step
   static constexpr int W_CH = 9 * BN * 4;      // 16-byte chunks of a step's weights
   static constexpr int HIT = (HALO_EL + 255) / 256, WIT = (W_CH + 255) / 256;
-  static constexpr size_t BYTES = static_cast<size_t>(HALO_CH + W_CH) * 16 + BN * 4;  // + the bias
+  // weight slices held in LDS: all of them when that still leaves room for
+  // two workgroups per compute unit (no weight traffic per step), else the
+  // step's slice, re-staged every step
+  static constexpr int WS = (HALO_CH + NCH * W_CH) * 16 + BN * 4 <= 80 * 1024 ? NCH : 1;
+  static constexpr size_t BYTES = static_cast<size_t>(HALO_CH + WS * W_CH) * 16 + BN * 4;  // + the bias
   // waves per SIMD the register allocation is held to: the workgroups that
   // fit a compute unit's 160 KB of LDS, at most 4
   static constexpr int LDS_WG = static_cast<int>((160 * 1024) / BYTES);
@@ -175,10 +179,10 @@ struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c
 };
 
 template <int BN, int CP, int TH, bool UP, int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH>::WAVES)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC>::WAVES)))
 conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
            Shape s) {
-  using C = ConvCfg<BN, TH>;
+  using C = ConvCfg<BN, TH, CP / kKC>;
   constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
   static_assert(!OUT || (BN == 32 && TH * kTW == 256), "the output conv takes one pixel per thread");
   constexpr int NCH = CP / kKC, MB = TH / 4, NB = BN / 32;  // tile rows and 32-channel blocks per wave
@@ -186,8 +190,8 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
   extern __shared__ __align__(16) uint4 lds4[];
   uint4* halo = lds4;              // [HH * 34][5]
-  uint4* wts = lds4 + C::HALO_CH;  // [9 * BN][4]
-  float* lbias = reinterpret_cast<float*>(wts + C::W_CH);  // [BN]: read per tile through LDS, so
+  uint4* wts = lds4 + C::HALO_CH;  // [WS][9 * BN][4]
+  float* lbias = reinterpret_cast<float*>(wts + C::WS * C::W_CH);  // [BN]: read per tile through LDS, so
   // starting a tile waits on no global load issued after the prefetch
   float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
@@ -295,11 +299,11 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 #pragma unroll
     for (int k = 0; k < WIT; ++k) wreg[k] = buf_load16(wsrc, off[k]);
   };
-  auto store_w = [&](const uint4* wreg) {
+  auto store_w = [&](const uint4* wreg, int slot) {
 #pragma unroll
     for (int k = 0; k < WIT; ++k) {
       const int e = tid + 256 * k;
-      if (e < C::W_CH) wts[swz(e >> 2, e & 3)] = wreg[k];
+      if (e < C::W_CH) wts[slot * C::W_CH + swz(e >> 2, e & 3)] = wreg[k];
     }
   };
   f32x16 acc[MB][NB];
@@ -315,7 +319,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   // and the wait for it is exact on both.
   constexpr int LDO = BN + 8;  // staging row (one pixel) in bf16
   constexpr int OCH = BN / 8;  // 16-byte chunks per output pixel
-  constexpr size_t STG_ROOM = static_cast<size_t>(NCH > 1 ? C::HALO_CH + C::W_CH : C::HALO_CH) * 16;
+  constexpr size_t STG_ROOM = static_cast<size_t>(C::WS == 1 && NCH > 1 ? C::HALO_CH + C::W_CH : C::HALO_CH) * 16;
   constexpr int NPASS = static_cast<size_t>(TH) * kTW * LDO * 2 <= STG_ROOM ? 1 : 2;
   constexpr int RP = TH / NPASS;  // tile rows per pass
   static_assert(static_cast<size_t>(RP) * kTW * LDO * 2 <= STG_ROOM, "staging tile too large");
@@ -435,12 +439,16 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   if (tid < BN) lbias[tid] = bias[tid];
   if (OUT && tid < 99) lout[tid] = tid < 96 ? oc.w[tid] : oc.b[tid - 96];
   Tile cur = decode(t_begin), nxt = cur;  // the tile computed, the tile prefetched
-  if (NCH == 1) {  // one slice: the weights stay in LDS for every tile
-    load_w(0, false, wreg);
-    store_w(wreg);
+  constexpr bool RESW = C::WS == NCH;  // every slice's weights stay in LDS for every tile
+  if (RESW) {
+#pragma unroll
+    for (int ck = 0; ck < NCH; ++ck) {
+      load_w(ck, false, wreg);
+      store_w(wreg, ck);
+    }
   }
   load_halo(nxt, 0, false, hreg);
-  if (NCH > 1) load_w(0, false, wreg);
+  if (!RESW) load_w(0, false, wreg);
   load_base(nxt, false);
 #pragma unroll
   for (int m = 0; m < MB; ++m)
@@ -457,7 +465,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 #pragma unroll
       for (int k = 0; k < HIT; ++k)
         if (tid + 256 * k < C::HALO_EL) halo[hlds + 64 * C::HPITCH * k] = hreg[k];
-      if (NCH > 1) store_w(wreg);
+      if (!RESW) store_w(wreg, 0);
       if (OUT && ck == 0) {
         bcur[0] = breg[0];
         bcur[1] = breg[1];
@@ -468,7 +476,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       const bool none = ck == NCH - 1 && it + 1 == my_tiles;
       if (ck == NCH - 1 && !none) advance(nxt);
       load_halo(nxt, (ck + 1) % NCH, none, hreg);
-      if (NCH > 1) load_w((ck + 1) % NCH, none, wreg);
+      if (!RESW) load_w((ck + 1) % NCH, none, wreg);
       if (ck == NCH - 1) load_base(nxt, none);
       // keep the prefetch ahead of the taps: the scheduler would otherwise
       // sink the loads below the MFMAs and expose their latency
@@ -491,7 +499,8 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       auto frag = [&](int i, int bsel) {
         const int tap = i >> 1, kh = i & 1, dr = tap / 3, dc = tap - (tap / 3) * 3;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) wf[bsel][j] = __builtin_bit_cast(bf16x8, wts[(tap * BN + j * 32) * 4 + boff[kh]]);
+        for (int j = 0; j < NB; ++j)
+          wf[bsel][j] = __builtin_bit_cast(bf16x8, wts[(RESW ? ck : 0) * C::W_CH + (tap * BN + j * 32) * 4 + boff[kh]]);
 #pragma unroll
         for (int m = 0; m < MB; ++m)
           hf[bsel][m] = __builtin_bit_cast(bf16x8, halo[aoff + ((m + dr) * C::HW + dc) * C::HPITCH + 2 * kh]);
@@ -510,6 +519,105 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     }
     epilogue(cur, false);
     cur = nxt;
+  }
+}
+
+// ------------------------------------------------------------- first layer
+// The first conv (8 input channels, the last two zero) as a 72-deep
+// contraction: two taps' 8 channels per 16-wide K slice, so a 32 x 32
+// output block takes 5 v_mfma_f32_32x32x16_bf16 (the tenth tap slot has
+// zero weights) where the general kernel takes 18 with K padded to 32.  One
+// 8 x 32-pixel tile per workgroup; a halo pixel is one 16-byte LDS chunk
+// (an odd pitch: fragment reads are free of bank conflicts), a weight row
+// 11 chunks (10 tap slots and one of padding).  With F32IN the network
+// input (6 f32 channels per pixel) is read directly and rounded to bf16
+// while it is staged, as the input packing does.
+constexpr int kInTH = 8, kInHW = kTW + 2, kInHH = kInTH + 2, kInHalo = kInHH * kInHW, kInWP = 11;
+template <bool F32IN>
+__global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict__ xin, int xin_ld,
+                                                 const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y,
+                                                 Shape s) {
+  constexpr int LDO = 40;  // staging row (one pixel) in bf16
+  __shared__ __align__(16) uint4 halo[kInHalo];
+  __shared__ __align__(16) uint4 wl[32 * kInWP];
+  __shared__ __align__(16) uint16_t stg[kInTH * kTW * LDO];
+  __shared__ __align__(16) float lb[32];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
+  const int tiles_x = (s.w + kTW - 1) / kTW, tiles_y = (s.h + kInTH - 1) / kInTH;
+  const int t = static_cast<int>(blockIdx.x), n = t / (tiles_x * tiles_y), rr = t - n * tiles_x * tiles_y;
+  const int oy0 = (rr / tiles_x) * kInTH, ox0 = (rr % tiles_x) * kTW;
+  // halo pixels tid and tid + 256 (of kInHalo), image row oy0 - 1 + hr, column ox0 - 1 + hc
+  uint4 hv[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + 256 * k, hr = e / kInHW, hc = e - hr * kInHW, r = oy0 - 1 + hr, c = ox0 - 1 + hc;
+    const int ok = (e < kInHalo) & (static_cast<unsigned>(r) < static_cast<unsigned>(s.h)) &
+                   (static_cast<unsigned>(c) < static_cast<unsigned>(s.w));
+    const int pix = r * s.w + c;  // within image n
+    if (F32IN) {
+      const __amdgpu_buffer_rsrc_t src = buf_rsrc(xin + static_cast<long long>(n) * s.h * s.w * xin_ld);
+      const int off = ok ? pix * xin_ld * 4 : kOOB;
+      const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(src, off, 0, 0);
+      const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(src, off + 8, 0, 0);
+      const u32x2 c2 = __builtin_amdgcn_raw_buffer_load_b64(src, off + 16, 0, 0);
+      hv[k] = uint4{pack_bf16(__uint_as_float(a[0]), __uint_as_float(a[1])),
+                    pack_bf16(__uint_as_float(b[0]), __uint_as_float(b[1])),
+                    pack_bf16(__uint_as_float(c2[0]), __uint_as_float(c2[1])), 0u};
+    } else {
+      const __amdgpu_buffer_rsrc_t src = buf_rsrc(x.p + x.off + static_cast<long long>(n) * s.h * s.w * x.ld);
+      hv[k] = buf_load16(src, ok ? pix * x.ld * 2 : kOOB);
+    }
+  }
+  // weights [tap][co][8] -> wl[co][tap] (tap slot 9 zero)
+  const __amdgpu_buffer_rsrc_t wsrc = buf_rsrc(w);
+  uint4 wv[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + 256 * k, co = e / 10, tap = e - co * 10;
+    wv[k] = buf_load16(wsrc, e < 320 && tap < 9 ? (tap * 32 + co) * 16 : kOOB);
+  }
+  if (tid < 32) lb[tid] = bias[tid];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = tid + 256 * k;
+    if (e < kInHalo) halo[e] = hv[k];
+    if (e < 320) wl[(e / 10) * kInWP + e % 10] = wv[k];
+  }
+  __syncthreads();
+  // wave w: tile rows 2w, 2w + 1; slice i holds taps 2i (lanes 0-31) and 2i + 1 (lanes 32-63)
+  f32x16 acc[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x4 b4 = *reinterpret_cast<const f32x4*>(lb + 8 * q + 4 * lh);
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][4 * q + r] = b4[r];
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const int tap = 2 * i + lh < 9 ? 2 * i + lh : 8, dr = tap / 3, dc = tap - (tap / 3) * 3;
+    const bf16x8 a = __builtin_bit_cast(bf16x8, wl[l32 * kInWP + 2 * i + lh]);
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const bf16x8 b = __builtin_bit_cast(bf16x8, halo[(2 * wave + m + dr) * kInHW + l32 + dc]);
+      acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[m], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<uint2*>(stg + ((2 * wave + m) * kTW + l32) * LDO + 8 * q + 4 * lh) =
+          uint2{pack_bf16(fmaxf(acc[m][4 * q], 0.f), fmaxf(acc[m][4 * q + 1], 0.f)),
+                pack_bf16(fmaxf(acc[m][4 * q + 2], 0.f), fmaxf(acc[m][4 * q + 3], 0.f))};
+  __syncthreads();
+  const __amdgpu_buffer_rsrc_t yb = buf_rsrc(y.p + y.off + ((static_cast<long long>(n) * s.h + oy0) * s.w + ox0) * y.ld);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + 256 * k, px = e / 4, c = e % 4, row = px / kTW, col = px % kTW;
+    const int ok = (oy0 + row < s.h) & (ox0 + col < s.w);
+    buf_store16(yb, ok ? ((row * s.w + col) * y.ld + c * 8) * 2 : kOOB, *reinterpret_cast<const uint4*>(stg + px * LDO + c * 8));
   }
 }
 
@@ -1021,7 +1129,7 @@ inline unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t
 template <int BN, int CP, int TH, bool UP, int EPI>
 hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
                        const OutConv& oc, const Shape& s, hipStream_t st) {
-  using C = ConvCfg<BN, TH>;
+  using C = ConvCfg<BN, TH, CP / kKC>;
   const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, EPI>);
   const size_t lds = C::BYTES + (EPI == kEpiOut ? 99 * 4 : 0);
   const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
@@ -1162,6 +1270,24 @@ hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in,
 }
 hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st) {
   add_into_k<<<blocks(s.pixels() * dst.c, 256), 256, 0, st>>>(src, dst, s);
+  return hipGetLastError();
+}
+
+hipError_t conv3x3_in_fwd(const Map* x, const float* xin, int xin_ld, const uint16_t* w_fwd, const float* bias,
+                          const Map& y, const Shape& s, hipStream_t st) {
+  if (y.c != 32 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
+  if (x && (x->c != 8 || x->ld % 8 || x->off % 8)) return hipErrorInvalidValue;
+  if (!x && (!xin || xin_ld < 6 || xin_ld % 2)) return hipErrorInvalidValue;
+  const long long img = static_cast<long long>(s.h) * s.w;
+  if (img * (x ? x->ld : xin_ld) * 4 >= (1LL << 31) || img * y.ld >= (1LL << 30)) return hipErrorInvalidValue;
+  const long long tiles = static_cast<long long>(s.n) * ((s.h + kInTH - 1) / kInTH) * ((s.w + kTW - 1) / kTW);
+  if (tiles == 0) return hipSuccess;
+  if (tiles > (1LL << 30)) return hipErrorInvalidValue;
+  const Map none{nullptr, 0, 0, 0};
+  if (x)
+    conv_in_k<false><<<static_cast<unsigned>(tiles), 256, 0, st>>>(*x, nullptr, 0, w_fwd, bias, y, s);
+  else
+    conv_in_k<true><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, xin, xin_ld, w_fwd, bias, y, s);
   return hipGetLastError();
 }
 

@@ -167,8 +167,13 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
   using dfb::unet::conv3x3_fwd;
   const Map pool1 = mp(n->pool1, 32, 0, 32), pool2 = mp(n->pool2, 64, 0, 64);
   const CatLayout c = cat_layout(n, s0, !training);
-  NHIP(n, dfb::unet::pack_input(in, 6, n->xin, s0, st));
-  NHIP(n, conv3x3_fwd(mp(n->xin, 8, 0, 8), n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
+  if (lean && !training) {  // the first layer reads the f32 input itself
+    NHIP(n, dfb::unet::conv3x3_in_fwd(nullptr, in, 6, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
+  } else {
+    NHIP(n, dfb::unet::pack_input(in, 6, n->xin, s0, st));
+    const Map xin = mp(n->xin, 8, 0, 8);
+    NHIP(n, dfb::unet::conv3x3_in_fwd(&xin, nullptr, 0, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
+  }
   NHIP(n, conv3x3_fwd(mp(n->e1a, 32, 0, 32), n->wf[ENC1B], B(ENC1B), c.enc1b, s0, st, false, &pool1));
   NHIP(n, conv3x3_fwd(pool1, n->wf[ENC2A], B(ENC2A), mp(n->e2a, 64, 0, 64), s1, st));
   NHIP(n, conv3x3_fwd(mp(n->e2a, 64, 0, 64), n->wf[ENC2B], B(ENC2B), c.enc2b, s1, st, false, &pool2));
