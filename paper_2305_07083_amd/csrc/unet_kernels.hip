@@ -97,8 +97,8 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 constexpr int kTW = 32;  // tile width (pixels)
 constexpr int kKC = 32;  // input channels per step
 // Output-tile heights (rows of 32 pixels) of the layers with (output, input)
-// channels (32, 32), (32, 64), (64, 64) and (64, 128); the others use 8
-// (64, 32) and 4 (128, *).  A pooling layer needs a multiple of 8.
+// channels (32, 32), (32, 64), (64, 64), (64, 128) and (128, *); (64, 32)
+// uses 8.  A pooling layer needs a multiple of 8.
 #ifndef DFB_TH_32_32
 #define DFB_TH_32_32 8
 #endif
@@ -110,6 +110,9 @@ constexpr int kKC = 32;  // input channels per step
 #endif
 #ifndef DFB_TH_64_128
 #define DFB_TH_64_128 8
+#endif
+#ifndef DFB_TH_128
+#define DFB_TH_128 8
 #endif
 
 template <int BN, int TH, int NCH>
@@ -1180,8 +1183,8 @@ hipError_t conv_tile(const Map& x, const Map& x2, const uint16_t* w, const float
   DFB_CONV(64, 32, 8)
   DFB_CONV(64, 64, DFB_TH_64_64)
   DFB_CONV(64, 128, DFB_TH_64_128)
-  DFB_CONV(128, 64, 4)
-  DFB_CONV(128, 128, 4)
+  DFB_CONV(128, 64, DFB_TH_128)
+  DFB_CONV(128, 128, DFB_TH_128)
 #undef DFB_CONV
   return hipErrorInvalidValue;
 }
