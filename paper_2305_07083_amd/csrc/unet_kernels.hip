@@ -115,6 +115,10 @@ constexpr int kKC = 32;  // input channels per step
 #define DFB_TH_128 8
 #endif
 
+// LDS bytes up to which a layer keeps every input slice's weights resident
+#ifndef DFB_RESW_KB
+#define DFB_RESW_KB 104
+#endif
 template <int BN, int TH, int NCH>
 struct ConvCfg {
   static constexpr int HW = kTW + 2, HH = TH + 2;
@@ -126,7 +130,7 @@ struct ConvCfg {
   // weight slices held in LDS: all of them when that still leaves room for
   // two workgroups per compute unit (no weight traffic per step), else the
   // step's slice, re-staged every step
-  static constexpr int WS = (HALO_CH + NCH * W_CH) * 16 + BN * 4 <= 80 * 1024 ? NCH : 1;
+  static constexpr int WS = (HALO_CH + NCH * W_CH) * 16 + BN * 4 <= DFB_RESW_KB * 1024 ? NCH : 1;
   static constexpr size_t BYTES = static_cast<size_t>(HALO_CH + WS * W_CH) * 16 + BN * 4;  // + the bias
   // waves per SIMD the register allocation is held to: the workgroups that
   // fit a compute unit's 160 KB of LDS, at most 4
