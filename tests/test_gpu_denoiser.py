@@ -109,6 +109,39 @@ def test_forward_many_tiles_per_workgroup(dfb):
     assert rel_l2(got_out - x[..., :3], ref_out - x[..., :3]) <= 1e-2
 
 
+@pytest.mark.timeout(600)
+def test_forward_2048_on_sampled_regions(dfb):
+    """The 2048x2048 forward (the size the benchmark times) against the oracle
+    on 96 x 96 crops at 8 places: corners, edges, interior.  Crops start on
+    multiples of 4, so both pooling levels line up with the full image's, and
+    output pixels at least 32 pixels from a crop edge inside the image (28
+    is the network's reach, checked on the CPU) are the full image's."""
+    torch = torch_dev()
+    n, h, w = 1, 2048, 2048
+    rng = np.random.default_rng(2048)
+    p = trained_like_params(13)
+    x, _ = make_batch(rng, n, h, w)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty((n, h, w, 3), dtype=torch.float32, device="cuda")
+    net = dfb.dfb_denoiser_create(dfb.UnetConfig(n * h * w, 0, 0, 0, 0), stream_handle())
+    try:
+        dfb.dfb_denoiser_set_params(net, dfb.unet_params_to_flat(p))
+        dfb.dfb_denoiser_forward(net, xd, out, n, h, w)
+        got = out.cpu().numpy()
+    finally:
+        dfb.dfb_denoiser_destroy(net)
+    p64 = {k: v.astype(np.float64) for k, v in p.items()}
+    C, M = 96, 32
+    for r0, c0 in [(0, 0), (0, 976), (0, 1952), (976, 0), (1024, 1024), (1952, 1952), (1952, 480), (512, 1952)]:
+        crop = x[:, r0:r0 + C, c0:c0 + C].astype(np.float64)
+        ref, _ = unet.forward(p64, crop, crop[..., :3], bf16_on=True)
+        r_lo, r_hi = (0 if r0 == 0 else M), (C if r0 + C == h else C - M)
+        c_lo, c_hi = (0 if c0 == 0 else M), (C if c0 + C == w else C - M)
+        g = got[0, r0 + r_lo:r0 + r_hi, c0 + c_lo:c0 + c_hi] - x[0, r0 + r_lo:r0 + r_hi, c0 + c_lo:c0 + c_hi, :3]
+        r = ref[0, r_lo:r_hi, c_lo:c_hi] - crop[0, r_lo:r_hi, c_lo:c_hi, :3]
+        assert rel_l2(g, r) <= 1e-2, (r0, c0, rel_l2(g, r))
+
+
 @pytest.mark.timeout(300)
 def test_denoise_matches_forward_on_a_large_frame(dfb):
     """dfb_denoise (skip concatenations as separate maps, the output conv in
