@@ -5,15 +5,16 @@
 // deterministic.
 //
 // The three convolutions are one GEMM shape, D[M][N] += A[M][K] B[K][N],
-// read from LDS in 32-wide K slices:
+// read from LDS in K slices:
 //   forward  M = c_out,  N = pixels, K = (tap, c_in)   A = W, B = x[p + tap]
 //   dgrad    M = pixels, N = c_in,  K = (tap, c_out)  A = dy[p - tap], B = W^T
 //   wgrad    M = c_in,   N = c_out, K = pixels (per tap, split over chunks)
-// A workgroup is 4 waves, one v_mfma_f32_16x16x32_bf16 per 16x16 block per K
-// slice.  In dgrad and wgrad wave w owns rows 16w..16w+15 of a 64-row tile
-// and every 16-column block of N; the forward kernel's tiling is below.  Operand layout (checked on the device): lane l holds k =
-// (l/16)*8 .. +7 of row/column l%16; the result element r of lane l is row
-// (l/16)*4 + r, column l%16.
+// The forward kernels (below) use v_mfma_f32_32x32x16_bf16.  dgrad and wgrad
+// use v_mfma_f32_16x16x32_bf16: a workgroup is 4 waves, wave w owns rows
+// 16w..16w+15 of a 64-row tile and every 16-column block of N, one MFMA per
+// 16x16 block per 32-wide K slice.  Operand layout of the 16x16x32 form
+// (checked on the device): lane l holds k = (l/16)*8 .. +7 of row/column
+// l%16; the result element r of lane l is row (l/16)*4 + r, column l%16.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
