@@ -634,7 +634,10 @@ __global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict_
 // W[tap][ci][co].  K runs over (tap, 32-wide c_out slice) in stages of
 // kDgradKS slices (one barrier pair per stage; slots past the last slice
 // stage zeros); the next stage's A chunks and weights are loaded into
-// registers while this stage's MFMAs run.
+// registers while this stage's MFMAs run.  The MFMA is
+// v_mfma_f32_32x32x16_bf16 on 32-pixel x 32-c_in blocks, split over the
+// waves as in the weight gradient below (the K steps of a slice are split
+// between two waves per block when there are only two blocks).
 constexpr int kDgradKS = 4;
 constexpr int LDD = 32 * kDgradKS + 8;  // LDS row: the stage's K + 8 padding
 
@@ -642,14 +645,20 @@ template <int BN>
 __global__ void __launch_bounds__(256) conv_dgrad_k(Map g, const uint16_t* __restrict__ w, MapF dx, Shape s) {
   __shared__ __align__(16) uint16_t As[BM * LDD];
   __shared__ __align__(16) uint16_t Bs[BN * LDD];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
   const long long m0 = static_cast<long long>(blockIdx.x) * BM;
   const int ap = tid >> 2, ach = (tid & 3) * 8;
   const Pix q = pixel_of(m0 + ap, s);
   const int co_n = g.c;
-  f32x4 acc[BN / 16];
+  constexpr int NBLK = 2 * (BN / 32);                      // 32 x 32 output blocks
+  constexpr int KSPLIT = NBLK >= 4 ? 1 : 4 / NBLK;         // waves per block
+  constexpr int BPW = NBLK >= 4 ? NBLK / 4 : 1;            // blocks per wave
+  const int kpart = wave / (4 / KSPLIT);                   // which 16-wide K step of a slice
+  f32x16 acc[BPW];
 #pragma unroll
-  for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < BPW; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
   const int nk = (co_n + 31) / 32, n_it = 9 * nk;
   constexpr int WPT = (BN * 4 + 255) / 256;  // 16-byte weight chunks per thread and slice
   uint4 av[kDgradKS], wv[kDgradKS][WPT];
@@ -692,24 +701,46 @@ __global__ void __launch_bounds__(256) conv_dgrad_k(Map g, const uint16_t* __res
 #pragma unroll
     for (int sl = 0; sl < kDgradKS; ++sl) {
       if (it0 + sl < n_it) {  // uniform
-        const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDD + sl * 32 + (lane >> 4) * 8);
 #pragma unroll
-        for (int j = 0; j < BN / 16; ++j) {
-          const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDD + sl * 32 + (lane >> 4) * 8);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        for (int kk = 0; kk < 2 / KSPLIT; ++kk) {
+          const int k = sl * 32 + (KSPLIT > 1 ? kpart : kk) * 16 + lh * 8;
+#pragma unroll
+          for (int b = 0; b < BPW; ++b) {
+            const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk & 1, nb = blk >> 1;
+            const bf16x8 a = lds_frag(As + (mb * 32 + l32) * LDD + k);
+            const bf16x8 bv = lds_frag(Bs + (nb * 32 + l32) * LDD + k);
+            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
+          }
         }
       }
     }
     __syncthreads();
   }
+  if constexpr (KSPLIT > 1) {  // part 0 + part 1 (the stage loop ended on a barrier: As is free)
+    static_assert(KSPLIT == 2 && NBLK * 64 * 16 * 4 <= BM * LDD * 2, "reduction fits As");
+    float* red = reinterpret_cast<float*>(As);
+    const int blk = wave % NBLK;
+    if (kpart == 1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) red[(blk * 16 + r) * 64 + lane] = acc[0][r];
+    }
+    __syncthreads();
+    if (kpart == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[0][r] += red[(blk * 16 + r) * 64 + lane];
+    }
+  }
   const long long P = s.pixels();
+  if (kpart == 0) {
 #pragma unroll
-  for (int j = 0; j < BN / 16; ++j) {
-    const int col = j * 16 + (lane & 15);
+    for (int b = 0; b < BPW; ++b) {
+      const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk & 1, nb = blk >> 1;
+      const int col = nb * 32 + l32;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long p = m0 + wave * 16 + (lane >> 4) * 4 + r;
-      if (p < P) dx.p[p * dx.ld + dx.off + col] = acc[j][r];
+      for (int r = 0; r < 16; ++r) {
+        const long long p = m0 + mb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (p < P) dx.p[p * dx.ld + dx.off + col] = acc[b][r];
+      }
     }
   }
 }
@@ -765,18 +796,31 @@ constexpr int kWgradChunk = 1024;
 constexpr int kWgradKS = 4;
 constexpr int LDW = 32 * kWgradKS + 8;  // LDS row: the stage's pixels + 8 padding
 
+// The MFMA is v_mfma_f32_32x32x16_bf16 on 32 c_in x 32 c_out blocks (row
+// and column operands read as 32 consecutive LDS rows at one 16-byte chunk;
+// the 136-element row pitch is an odd number of chunks, so the reads are free
+// of bank conflicts).  Wave w takes blocks w, w + 4, ... of the 2 * BN / 32
+// blocks; with fewer blocks than waves (BN = 32) the stage's pixels are split
+// between two waves per block and their sums added in a fixed order.
 template <int BN>
 __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restrict__ partial, Shape s) {
   __shared__ __align__(16) uint16_t As[BM * LDW];   // [ci][px]
   __shared__ __align__(16) uint16_t Bs[BN * LDW];   // [co][px]
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
   const int chunk = blockIdx.x, tap = blockIdx.y, ci0 = blockIdx.z * BM;
   const int dr = tap / 3 - 1, dc = tap % 3 - 1;
   const long long P = s.pixels();
   const long long p_begin = static_cast<long long>(chunk) * kWgradChunk;
-  f32x4 acc[BN / 16];
+  constexpr int NBLK = 2 * (BN / 32);                      // 32 x 32 output blocks
+  constexpr int KSPLIT = NBLK >= 4 ? 1 : 4 / NBLK;         // waves per block
+  constexpr int BPW = NBLK >= 4 ? NBLK / 4 : 1;            // blocks per wave
+  constexpr int KSUB = 32 * kWgradKS / 16 / KSPLIT;        // 16-pixel MFMA steps per wave and stage
+  const int kpart = wave / (4 / KSPLIT);                   // which part of the stage's pixels
+  f32x16 acc[BPW];
 #pragma unroll
-  for (int j = 0; j < BN / 16; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < BPW; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
   // thread (q, cg) stages the 4 consecutive pixels 4q..4q+3 of the stage
   // (q < 32) for channel group cg: 4 loads of x and of g, then one 8-byte
   // LDS store per channel (4 pixels of one channel, transposed in registers)
@@ -836,26 +880,44 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restr
     const bool more = k1 < kWgradChunk && p_begin + k1 < P;
     if (more) load(k1);
 #pragma unroll
-    for (int sl = 0; sl < kWgradKS; ++sl) {
-      const bf16x8 a = lds_frag(As + (wave * 16 + (lane & 15)) * LDW + sl * 32 + (lane >> 4) * 8);
+    for (int kk = 0; kk < KSUB; ++kk) {
+      const int px = (kpart * KSUB + kk) * 16 + lh * 8;
 #pragma unroll
-      for (int j = 0; j < BN / 16; ++j) {
-        const bf16x8 b = lds_frag(Bs + (j * 16 + (lane & 15)) * LDW + sl * 32 + (lane >> 4) * 8);
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+      for (int b = 0; b < BPW; ++b) {
+        const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk & 1, nb = blk >> 1;
+        const bf16x8 a = lds_frag(As + (mb * 32 + l32) * LDW + px);
+        const bf16x8 bv = lds_frag(Bs + (nb * 32 + l32) * LDW + px);
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
       }
     }
     __syncthreads();
     if (!more) break;
   }
+  if constexpr (KSPLIT > 1) {  // part 0 + part 1 (the stage loop ended on a barrier: As is free)
+    static_assert(KSPLIT == 2 && NBLK * 64 * 16 * 4 <= BM * LDW * 2, "reduction fits As");
+    float* red = reinterpret_cast<float*>(As);
+    const int blk = wave % NBLK;
+    if (kpart == 1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) red[(blk * 16 + r) * 64 + lane] = acc[0][r];
+    }
+    __syncthreads();
+    if (kpart == 0) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[0][r] += red[(blk * 16 + r) * 64 + lane];
+    }
+  }
   const int ci_n = x.c;
+  if (kpart == 0) {
 #pragma unroll
-  for (int j = 0; j < BN / 16; ++j) {
-    const int co = j * 16 + (lane & 15);
+    for (int b = 0; b < BPW; ++b) {
+      const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk & 1, nb = blk >> 1;
+      const int co = nb * 32 + l32;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ci = ci0 + wave * 16 + (lane >> 4) * 4 + r;
-      if (ci < ci_n)
-        partial[((static_cast<size_t>(chunk) * 9 + tap) * ci_n + ci) * BN + co] = acc[j][r];
+      for (int r = 0; r < 16; ++r) {
+        const int ci = ci0 + mb * 32 + 8 * (r / 4) + 4 * lh + (r % 4);
+        if (ci < ci_n) partial[((static_cast<size_t>(chunk) * 9 + tap) * ci_n + ci) * BN + co] = acc[b][r];
+      }
     }
   }
 }
