@@ -9,12 +9,13 @@
 //   forward  M = c_out,  N = pixels, K = (tap, c_in)   A = W, B = x[p + tap]
 //   dgrad    M = pixels, N = c_in,  K = (tap, c_out)  A = dy[p - tap], B = W^T
 //   wgrad    M = c_in,   N = c_out, K = pixels (per tap, split over chunks)
-// The forward kernels (below) use v_mfma_f32_32x32x16_bf16.  dgrad and wgrad
-// use v_mfma_f32_16x16x32_bf16: a workgroup is 4 waves, wave w owns rows
-// 16w..16w+15 of a 64-row tile and every 16-column block of N, one MFMA per
-// 16x16 block per 32-wide K slice.  Operand layout of the 16x16x32 form
-// (checked on the device): lane l holds k = (l/16)*8 .. +7 of row/column
-// l%16; the result element r of lane l is row (l/16)*4 + r, column l%16.
+// All three use v_mfma_f32_32x32x16_bf16.  Operand layout (checked on the
+// device): lane l holds k = (l/32)*8 .. +7 of row/column l%32; the result
+// element r of lane l is row 8*(r/4) + 4*(l/32) + r%4, column l%32.  In
+// dgrad and wgrad a workgroup is 4 waves over a 64-row tile and every
+// 32-column block of N: wave w takes 32x32 blocks w, w + 4, ...; with only
+// two blocks (N = 32) two waves share a block, each taking half of the K
+// steps, and their sums are added in a fixed order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
