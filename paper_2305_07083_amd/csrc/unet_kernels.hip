@@ -195,7 +195,14 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
   static_assert(!OUT || (BN == 32 && TH * kTW == 256), "the output conv takes one pixel per thread");
   constexpr int NCH = CP / kKC, MB = TH / 4, NB = BN / 32;  // tile rows and 32-channel blocks per wave
-  constexpr int HIT = C::HIT, WIT = C::WIT;
+  // With UP the halo is staged at the source resolution: (TH/2 + 2) x 18
+  // pixels, each read by the up to four output-halo pixels it is
+  // up-sampled to (the fragment reads index it through the same
+  // nearest-neighbour map).
+  constexpr int SHH = UP ? TH / 2 + 2 : C::HH, SHW = UP ? kTW / 2 + 2 : C::HW;  // staged halo rows, columns
+  constexpr int HALO_EL = SHH * SHW * 4;                   // chunks loaded per step
+  constexpr int HIT = (HALO_EL + 255) / 256, WIT = C::WIT;
+  static_assert(HALO_EL <= C::HH * C::HW * 4, "the staged halo fits its LDS region");
   static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
   extern __shared__ __align__(16) uint4 lds4[];
   uint4* halo = lds4;              // [HH * 34][5]
@@ -247,15 +254,21 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   int hrel[HIT];
 #pragma unroll
   for (int k = 0; k < HIT; ++k) {
-    const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / C::HW, hc = hp - hr * C::HW;
-    hrel[k] = e < C::HALO_EL ? ((UP ? ((hr + 1) >> 1) * wi + ((hc + 1) >> 1) : hr * wi + hc) * x.ld + cc * 8) * 2 : kOOB;
+    const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / SHW, hc = hp - hr * SHW;
+    hrel[k] = e < HALO_EL ? ((hr * wi + hc) * x.ld + cc * 8) * 2 : kOOB;
   }
   const int hlds = (tid >> 2) * C::HPITCH + (tid & 3);
   // fragment reads of 16-channel half kh: weights of (tap, j) at
   // wts[(tap * BN + j * 32) * 4 + boff[kh]], halo of (m, tap) at
-  // halo[aoff + ((m + dr) * 34 + dc) * HPITCH + 2 kh]
+  // halo[aoff[dc] + hrow(m + dr) * SHW * HPITCH + 2 kh], where output-halo
+  // row r of the wave is staged row r (or (r + 1) / 2 with UP) and
+  // aoff[dc] holds the lane's column: l32 + dc (or (l32 + dc + 1) / 2)
   const int boff[2] = {l32 * 4 + ((0 + lh) ^ ((l32 >> 2) & 3)), l32 * 4 + ((2 + lh) ^ ((l32 >> 2) & 3))};
-  const int aoff = (wave * MB * C::HW + l32) * C::HPITCH + lh;
+  const int wrow0 = UP ? wave * MB / 2 : wave * MB;  // the wave's first staged row (MB is even with UP)
+  int aoff[UP ? 3 : 1];
+#pragma unroll
+  for (int dc = 0; dc < (UP ? 3 : 1); ++dc)
+    aoff[dc] = (wrow0 * SHW + (UP ? (l32 + dc + 1) >> 1 : l32)) * C::HPITCH + lh;
 
   // Halo of slice ck of tile u into hreg; every load is issued (with
   // `none`, all out of range).
@@ -265,9 +278,10 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     const Map& xm = second ? x2 : x;
     const int cb = second ? ck * kKC - x.c : ck * kKC;  // first channel of the slice in xm
     const uint16_t* img = xm.p + xm.off + cb + static_cast<long long>(u.n) * hi * wi * xm.ld;
-    const __amdgpu_buffer_rsrc_t src =
-        buf_rsrc(img + (UP ? (oy0 / 2 - 1) * wi + ox0 / 2 - 1 : (oy0 - 1) * wi + ox0 - 1) * x.ld);
-    const bool inner = full && oy0 >= 1 && oy0 + TH + 1 <= s.h && ox0 >= 1 && ox0 + kTW + 1 <= s.w;
+    // the staged halo's top-left pixel in the map read (hi x wi)
+    const int sy0 = UP ? oy0 / 2 - 1 : oy0 - 1, sx0 = UP ? ox0 / 2 - 1 : ox0 - 1;
+    const bool inner = full && sy0 >= 0 && sy0 + SHH <= hi && sx0 >= 0 && sx0 + SHW <= wi;
+    const __amdgpu_buffer_rsrc_t src = buf_rsrc(img + (static_cast<long long>(sy0) * wi + sx0) * x.ld);
     int off[HIT];
     if (inner && !none) {
 #pragma unroll
@@ -275,10 +289,10 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     } else {  // zeros outside the image and past xm.c
 #pragma unroll
       for (int k = 0; k < HIT; ++k) {
-        const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / C::HW, hc = hp - hr * C::HW;
-        const int r = oy0 - 1 + hr, c = ox0 - 1 + hc;
-        const int ok = (static_cast<unsigned>(r) < static_cast<unsigned>(s.h)) &
-                       (static_cast<unsigned>(c) < static_cast<unsigned>(s.w)) & (cb + cc * 8 < xm.c) & !none;
+        const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / SHW, hc = hp - hr * SHW;
+        const int r = sy0 + hr, c = sx0 + hc;
+        const int ok = (static_cast<unsigned>(r) < static_cast<unsigned>(hi)) &
+                       (static_cast<unsigned>(c) < static_cast<unsigned>(wi)) & (cb + cc * 8 < xm.c) & !none;
         off[k] = ok ? hrel[k] : kOOB;
       }
     }
@@ -473,7 +487,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       __syncthreads();  // the previous step's fragment reads are done
 #pragma unroll
       for (int k = 0; k < HIT; ++k)
-        if (tid + 256 * k < C::HALO_EL) halo[hlds + 64 * C::HPITCH * k] = hreg[k];
+        if (tid + 256 * k < HALO_EL) halo[hlds + 64 * C::HPITCH * k] = hreg[k];
       if (!RESW) store_w(wreg, 0);
       if (OUT && ck == 0) {
         bcur[0] = breg[0];
@@ -512,7 +526,8 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
           wf[bsel][j] = __builtin_bit_cast(bf16x8, wts[(RESW ? ck : 0) * C::W_CH + (tap * BN + j * 32) * 4 + boff[kh]]);
 #pragma unroll
         for (int m = 0; m < MB; ++m)
-          hf[bsel][m] = __builtin_bit_cast(bf16x8, halo[aoff + ((m + dr) * C::HW + dc) * C::HPITCH + 2 * kh]);
+          hf[bsel][m] = __builtin_bit_cast(
+              bf16x8, halo[aoff[UP ? dc : 0] + ((UP ? (m + dr + 1) >> 1 : m + dr) * SHW + (UP ? 0 : dc)) * C::HPITCH + 2 * kh]);
       };
       frag(0, 0);
 #pragma unroll
