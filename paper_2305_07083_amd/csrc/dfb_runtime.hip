@@ -29,12 +29,15 @@ enum class State { kEmpty, kReady, kComposited };
 // A launch shape is chosen once per frame geometry, fragment type, tile
 // operation and layer-count class (the register-sort capacity and the
 // padded size of the largest tile's sort), so a new layer layout of the same
-// class reuses it instead of autotuning again.
+// class reuses it instead of autotuning again.  The caller's fixed work
+// unit and wave count (0 = tuned) are part of the key: they restrict the
+// candidates.
 struct AutotuneKey {
-  int device, width, height, tile_w, tile_h, dtype, op, kcap, lk;
+  int device, width, height, tile_w, tile_h, dtype, op, kcap, lk, work_w, work_h, waves;
   bool operator<(const AutotuneKey& o) const {
-    return std::tie(device, width, height, tile_w, tile_h, dtype, op, kcap, lk) <
-           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.op, o.kcap, o.lk);
+    return std::tie(device, width, height, tile_w, tile_h, dtype, op, kcap, lk, work_w, work_h, waves) <
+           std::tie(o.device, o.width, o.height, o.tile_w, o.tile_h, o.dtype, o.op, o.kcap, o.lk, o.work_w,
+                    o.work_h, o.waves);
   }
 };
 struct Shape {
@@ -722,8 +725,9 @@ dfb_status set_acc_count(dfb_ctx* h, int32_t value) {
 }
 
 dfb_status autotune(dfb_ctx* h) {
-  AutotuneKey key{h->device, h->cfg.width, h->cfg.height, h->cfg.tile_w, h->cfg.tile_h,
-                  h->cfg.frag_dtype, h->cfg.tile_op, h->kcap, layer_class(h->max_k)};
+  AutotuneKey key{h->device,      h->cfg.width,   h->cfg.height,          h->cfg.tile_w,
+                  h->cfg.tile_h,  h->cfg.frag_dtype, h->cfg.tile_op,      h->kcap,
+                  layer_class(h->max_k), h->cfg.work_w, h->cfg.work_h, h->cfg.waves_per_tile};
   auto cands = candidates(h->cfg, h->max_k);
   if (cands.size() == 1) {
     h->shape = cands[0];

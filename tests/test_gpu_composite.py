@@ -160,6 +160,21 @@ def test_work_units_identical_for_many_layers(dfb, work):
     assert np.array_equal(base["order"], g["order"])
 
 
+def test_fixed_work_unit_is_honoured_after_autotuning(dfb):
+    """A caller's fixed work unit and wave count are used even after another
+    context with the same frame geometry was autotuned: tuned shapes are
+    cached per geometry and per fixed unit / wave count.  More than 128
+    layers, so even a fixed unit leaves the LDS budget to the autotuner."""
+    f = workloads.uniform_frame(128, 128, 64, ranks=140, seed=5)
+    tuned = composite_gpu(dfb, f, work=0, waves=0)
+    for work, waves in ((16, 4), ((64, 16), 4), (32, 2), (16, 1)):
+        g, _ = check_frame(dfb, f, work=work, waves=waves)
+        ww, wh = (work, work) if isinstance(work, int) else work
+        assert (g["info"].work_w, g["info"].work_h, g["info"].waves_per_tile) == (ww, wh, waves)
+    again = composite_gpu(dfb, f, work=0, waves=0)
+    assert (again["info"].work_w, again["info"].work_h) == (tuned["info"].work_w, tuned["info"].work_h)
+
+
 @pytest.mark.parametrize("ranks", [6, 40])
 def test_depth_ties_break_by_source(dfb, ranks):
     f = workloads.uniform_frame(64, 64, 64, ranks=ranks, seed=3)
