@@ -97,6 +97,7 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // Every address of the tap loop is a per-lane register plus an immediate,
 // so the loop issues no vector ALU work.
 constexpr int kTW = 32;  // tile width (pixels)
+constexpr int kXcds = 8;  // XCDs (each with its own L2) the workgroups of a launch are dealt to in turn
 constexpr int kKC = 32;  // input channels per step
 // Output-tile heights (rows of 32 pixels) of the layers with (output, input)
 // channels (32, 32), (32, 64), (64, 64), (64, 128) and (128, *); (64, 32)
@@ -116,28 +117,54 @@ constexpr int kKC = 32;  // input channels per step
 #ifndef DFB_TH_128
 #define DFB_TH_128 8
 #endif
+// the same for the up-sampled layers (32, 64) and (64, 128)
+#ifndef DFB_THU_32_64
+#define DFB_THU_32_64 8
+#endif
+#ifndef DFB_THU_64_128
+#define DFB_THU_64_128 8
+#endif
 
 // LDS bytes up to which a layer keeps every input slice's weights resident
 #ifndef DFB_RESW_KB
 #define DFB_RESW_KB 104
 #endif
-template <int BN, int TH, int NCH>
+template <int BN, int TH, int NCH, bool UP>
 struct ConvCfg {
-  static constexpr int HW = kTW + 2, HH = TH + 2;
+  // With UP the halo is staged at the source resolution: (TH/2 + 2) x 18
+  // pixels, each read by the up to four output-halo pixels it is
+  // up-sampled to (the fragment reads index it through the same
+  // nearest-neighbour map).
+  static constexpr int SHH = UP ? TH / 2 + 2 : TH + 2, SHW = UP ? kTW / 2 + 2 : kTW + 2;  // staged rows, columns
   static constexpr int HPITCH = 5;             // 16-byte chunks per halo pixel (4 used)
-  static constexpr int HALO_CH = HH * HW * HPITCH;  // 16-byte chunks of a step's halo
-  static constexpr int HALO_EL = HH * HW * 4;       // chunks loaded per step
+  static constexpr int HALO_CH = SHH * SHW * HPITCH;  // 16-byte chunks of a step's halo
+  static constexpr int HALO_EL = SHH * SHW * 4;       // chunks loaded per step
   static constexpr int W_CH = 9 * BN * 4;      // 16-byte chunks of a step's weights
   static constexpr int HIT = (HALO_EL + 255) / 256, WIT = (W_CH + 255) / 256;
+  // The epilogue's staging tile (TH x 32 pixels of BN bf16 + 8 padding)
+  // overlays the halo region, and the weights when a step re-stages them;
+  // it is written in two passes of TH/2 rows when it does not fit.  The
+  // small halo of an up-sampled layer is given room for at least one pass
+  // (counting the weights' region when even the halo alone leaves no room
+  // for all weight slices).
+  static constexpr int STG1 = TH * kTW * (BN + 8) * 2;  // bytes of the whole staging tile
+  static constexpr int WEXTRA = NCH > 1 && (HALO_CH + NCH * W_CH) * 16 + BN * 4 > DFB_RESW_KB * 1024 ? W_CH : 0;
+  static constexpr int REGION_CH = UP && (HALO_CH + WEXTRA) * 16 < STG1 / 2 ? STG1 / 32 - WEXTRA : HALO_CH;
   // weight slices held in LDS: all of them when that still leaves room for
   // two workgroups per compute unit (no weight traffic per step), else the
   // step's slice, re-staged every step
-  static constexpr int WS = (HALO_CH + NCH * W_CH) * 16 + BN * 4 <= DFB_RESW_KB * 1024 ? NCH : 1;
-  static constexpr size_t BYTES = static_cast<size_t>(HALO_CH + WS * W_CH) * 16 + BN * 4;  // + the bias
+  static constexpr int WS = (REGION_CH + NCH * W_CH) * 16 + BN * 4 <= DFB_RESW_KB * 1024 ? NCH : 1;
+  static constexpr int STG_ROOM = (WS == 1 && NCH > 1 ? REGION_CH + W_CH : REGION_CH) * 16;
+  static constexpr int NPASS = STG1 <= STG_ROOM ? 1 : 2;
+  static constexpr size_t BYTES = static_cast<size_t>(REGION_CH + WS * W_CH) * 16 + BN * 4;  // + the bias
   // waves per SIMD the register allocation is held to: the workgroups that
   // fit a compute unit's 160 KB of LDS, at most 4
   static constexpr int LDS_WG = static_cast<int>((160 * 1024) / BYTES);
-  static constexpr int WAVES = LDS_WG < 1 ? 1 : (LDS_WG > 4 ? 4 : LDS_WG);
+  // ... and at most 2 where a step re-stages 64 or more channels' weights:
+  // their prefetch registers and accumulators need more than 168 VGPRs
+  static constexpr int REG_WAVES = WS == 1 && NCH > 1 && BN >= 64 ? 2 : 4;
+  static constexpr int WAVES_LDS = LDS_WG < 1 ? 1 : (LDS_WG > 4 ? 4 : LDS_WG);
+  static constexpr int WAVES = WAVES_LDS < REG_WAVES ? WAVES_LDS : REG_WAVES;
 };
 // Raw buffer accesses with a 2 GB range from a per-step base: an offset of
 // kOOB is out of range, so the load returns zeros or the store is dropped.
@@ -188,25 +215,18 @@ struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c
 };
 
 template <int BN, int CP, int TH, bool UP, int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC>::WAVES)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
 conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
            Shape s) {
-  using C = ConvCfg<BN, TH, CP / kKC>;
+  using C = ConvCfg<BN, TH, CP / kKC, UP>;
   constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
   static_assert(!OUT || (BN == 32 && TH * kTW == 256), "the output conv takes one pixel per thread");
   constexpr int NCH = CP / kKC, MB = TH / 4, NB = BN / 32;  // tile rows and 32-channel blocks per wave
-  // With UP the halo is staged at the source resolution: (TH/2 + 2) x 18
-  // pixels, each read by the up to four output-halo pixels it is
-  // up-sampled to (the fragment reads index it through the same
-  // nearest-neighbour map).
-  constexpr int SHH = UP ? TH / 2 + 2 : C::HH, SHW = UP ? kTW / 2 + 2 : C::HW;  // staged halo rows, columns
-  constexpr int HALO_EL = SHH * SHW * 4;                   // chunks loaded per step
-  constexpr int HIT = (HALO_EL + 255) / 256, WIT = C::WIT;
-  static_assert(HALO_EL <= C::HH * C::HW * 4, "the staged halo fits its LDS region");
+  constexpr int SHH = C::SHH, SHW = C::SHW, HALO_EL = C::HALO_EL, HIT = C::HIT, WIT = C::WIT;
   static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
   extern __shared__ __align__(16) uint4 lds4[];
-  uint4* halo = lds4;              // [HH * 34][5]
-  uint4* wts = lds4 + C::HALO_CH;  // [WS][9 * BN][4]
+  uint4* halo = lds4;                // [SHH * SHW][5], and the epilogue's staging tile
+  uint4* wts = lds4 + C::REGION_CH;  // [WS][9 * BN][4]
   float* lbias = reinterpret_cast<float*>(wts + C::WS * C::W_CH);  // [BN]: read per tile through LDS, so
   // starting a tile waits on no global load issued after the prefetch
   float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut)
@@ -215,8 +235,14 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   const long long tiles = static_cast<long long>(s.n) * tiles_x * tiles_y;
   // workgroup b walks the tiles [b T / G, (b + 1) T / G) in row order (the
   // host launches G <= T workgroups, so each has at least one), sharing the
-  // halo columns of consecutive tiles through its L2
-  const long long G = gridDim.x, b0 = blockIdx.x;
+  // halo columns of consecutive tiles through its L2.  b is the workgroup's
+  // rank on its XCD (the hardware deals workgroups to the 8 XCDs in turn)
+  // after those of the XCDs before it, so each XCD walks one contiguous
+  // band of tiles and the workgroups working on vertically adjacent tiles
+  // at the same time share their halo rows through the same L2.
+  const long long G = gridDim.x;
+  const int xcd = static_cast<int>(blockIdx.x % kXcds), xr = static_cast<int>(blockIdx.x / kXcds);
+  const long long b0 = xcd * (G / kXcds) + (xcd < G % kXcds ? xcd : G % kXcds) + xr;
   const long long t_begin = b0 * tiles / G, t_end = (b0 + 1) * tiles / G;
   const int nsteps = static_cast<int>(t_end - t_begin) * NCH;
   const int hi = UP ? s.h / 2 : s.h, wi = UP ? s.w / 2 : s.w;  // the map x is read from
@@ -342,10 +368,9 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   // and the wait for it is exact on both.
   constexpr int LDO = BN + 8;  // staging row (one pixel) in bf16
   constexpr int OCH = BN / 8;  // 16-byte chunks per output pixel
-  constexpr size_t STG_ROOM = static_cast<size_t>(C::WS == 1 && NCH > 1 ? C::HALO_CH + C::W_CH : C::HALO_CH) * 16;
-  constexpr int NPASS = static_cast<size_t>(TH) * kTW * LDO * 2 <= STG_ROOM ? 1 : 2;
+  constexpr int NPASS = C::NPASS;
   constexpr int RP = TH / NPASS;  // tile rows per pass
-  static_assert(static_cast<size_t>(RP) * kTW * LDO * 2 <= STG_ROOM, "staging tile too large");
+  static_assert(RP * kTW * LDO * 2 <= C::STG_ROOM, "staging tile too large");
   static_assert((RP * kTW * OCH) % 256 == 0 && RP % 2 == 0 && RP % MB == 0, "pass shape");
   constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / 256;                           // stores per thread and pass
   constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + 255) / 256 : 0;  // pool stores per thread and pass
@@ -1215,7 +1240,7 @@ inline unsigned blocks(long long n, int t) { return static_cast<unsigned>((n + t
 template <int BN, int CP, int TH, bool UP, int EPI>
 hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y, const Map& pool,
                        const OutConv& oc, const Shape& s, hipStream_t st) {
-  using C = ConvCfg<BN, TH, CP / kKC>;
+  using C = ConvCfg<BN, TH, CP / kKC, UP>;
   const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, EPI>);
   const size_t lds = C::BYTES + (EPI == kEpiOut ? 99 * 4 : 0);
   const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
@@ -1259,15 +1284,15 @@ template <bool UP>
 hipError_t conv_tile(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y,
                      const Map& pool, const Shape& s, hipStream_t st) {
   const int cp = (x.c + x2.c + 31) / 32 * 32;
-#define DFB_CONV(BN_, CP_, TH_) \
-  if (y.c == BN_ && cp == CP_) return launch_tile<BN_, CP_, TH_, UP>(x, x2, w, bias, y, pool, s, st);
-  DFB_CONV(32, 32, DFB_TH_32_32)
-  DFB_CONV(32, 64, DFB_TH_32_64)
-  DFB_CONV(64, 32, 8)
-  DFB_CONV(64, 64, DFB_TH_64_64)
-  DFB_CONV(64, 128, DFB_TH_64_128)
-  DFB_CONV(128, 64, DFB_TH_128)
-  DFB_CONV(128, 128, DFB_TH_128)
+#define DFB_CONV(BN_, CP_, TH_, THU_) \
+  if (y.c == BN_ && cp == CP_) return launch_tile<BN_, CP_, UP ? THU_ : TH_, UP>(x, x2, w, bias, y, pool, s, st);
+  DFB_CONV(32, 32, DFB_TH_32_32, DFB_TH_32_32)
+  DFB_CONV(32, 64, DFB_TH_32_64, DFB_THU_32_64)
+  DFB_CONV(64, 32, 8, 8)
+  DFB_CONV(64, 64, DFB_TH_64_64, DFB_TH_64_64)
+  DFB_CONV(64, 128, DFB_TH_64_128, DFB_THU_64_128)
+  DFB_CONV(128, 64, DFB_TH_128, DFB_TH_128)
+  DFB_CONV(128, 128, DFB_TH_128, DFB_TH_128)
 #undef DFB_CONV
   return hipErrorInvalidValue;
 }
