@@ -81,8 +81,10 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // number of independent accumulators).  It takes the weights as its row
 // operand (32 output channels) and a 32-pixel tile row as its column
 // operand; lane l holds pixel l % 32 and, in accumulator element r, channel
-// 8 (r / 4) + 4 (l / 32) + r % 4.  Wave w owns tile rows w*TH/4 .. +TH/4-1
-// and every 32-channel block of BN.  The accumulators start from the bias;
+// 8 (r / 4) + 4 (l / 32) + r % 4.  A workgroup is TH/2 waves; wave w owns
+// tile rows 2w and 2w + 1 and every 32-channel block of BN, so a taller tile
+// spreads a staged weight slice over more waves at the same registers per
+// wave.  The accumulators start from the bias;
 // the epilogue (ReLU, v_cvt_pk_bf16_f32, optionally the 2x2 average pool)
 // goes through a staging tile in LDS so that the stores are coalesced.
 //
@@ -99,9 +101,12 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 constexpr int kTW = 32;  // tile width (pixels)
 constexpr int kXcds = 8;  // XCDs (each with its own L2) the workgroups of a launch are dealt to in turn
 constexpr int kKC = 32;  // input channels per step
-// Output-tile heights (rows of 32 pixels) of the layers with (output, input)
-// channels (32, 32), (32, 64), (64, 64), (64, 128) and (128, *); (64, 32)
-// uses 8.  A pooling layer needs a multiple of 8.
+// Output-tile heights (rows of 32 pixels, 8 or 16) of the layers with
+// (output, input) channels (32, 32), (32, 64), (64, 64), (64, 128) and
+// (128, *); (64, 32) uses 8.  16 rows (8 waves) for the 64-channel layers:
+// a staged weight slice serves twice the pixels (2048^2 enc2b / dec2b 107 /
+// 98 -> 94 / 87 us, dec2a 181 -> 169 us); the 32-channel layers gain nothing
+// from it and the 128-channel ones would spill.
 #ifndef DFB_TH_32_32
 #define DFB_TH_32_32 8
 #endif
@@ -109,10 +114,10 @@ constexpr int kKC = 32;  // input channels per step
 #define DFB_TH_32_64 8
 #endif
 #ifndef DFB_TH_64_64
-#define DFB_TH_64_64 8
+#define DFB_TH_64_64 16
 #endif
 #ifndef DFB_TH_64_128
-#define DFB_TH_64_128 8
+#define DFB_TH_64_128 16
 #endif
 #ifndef DFB_TH_128
 #define DFB_TH_128 8
@@ -122,12 +127,13 @@ constexpr int kKC = 32;  // input channels per step
 #define DFB_THU_32_64 8
 #endif
 #ifndef DFB_THU_64_128
-#define DFB_THU_64_128 8
+#define DFB_THU_64_128 16
 #endif
 
 // LDS bytes up to which a layer keeps every input slice's weights resident
+// (the 16-row 64 -> 64 layers need 123 KB: one 8-wave workgroup per CU)
 #ifndef DFB_RESW_KB
-#define DFB_RESW_KB 104
+#define DFB_RESW_KB 124
 #endif
 template <int BN, int TH, int NCH, bool UP>
 struct ConvCfg {
@@ -140,7 +146,8 @@ struct ConvCfg {
   static constexpr int HALO_CH = SHH * SHW * HPITCH;  // 16-byte chunks of a step's halo
   static constexpr int HALO_EL = SHH * SHW * 4;       // chunks loaded per step
   static constexpr int W_CH = 9 * BN * 4;      // 16-byte chunks of a step's weights
-  static constexpr int HIT = (HALO_EL + 255) / 256, WIT = (W_CH + 255) / 256;
+  static constexpr int NT = 32 * TH;           // threads: a wave per two tile rows
+  static constexpr int HIT = (HALO_EL + NT - 1) / NT, WIT = (W_CH + NT - 1) / NT;
   // The epilogue's staging tile (TH x 32 pixels of BN bf16 + 8 padding)
   // overlays the halo region, and the weights when a step re-stages them;
   // it is written in two passes of TH/2 rows when it does not fit.  The
@@ -150,20 +157,20 @@ struct ConvCfg {
   static constexpr int STG1 = TH * kTW * (BN + 8) * 2;  // bytes of the whole staging tile
   static constexpr int WEXTRA = NCH > 1 && (HALO_CH + NCH * W_CH) * 16 + BN * 4 > DFB_RESW_KB * 1024 ? W_CH : 0;
   static constexpr int REGION_CH = UP && (HALO_CH + WEXTRA) * 16 < STG1 / 2 ? STG1 / 32 - WEXTRA : HALO_CH;
-  // weight slices held in LDS: all of them when that still leaves room for
-  // two workgroups per compute unit (no weight traffic per step), else the
-  // step's slice, re-staged every step
+  // weight slices held in LDS: all of them when the layer's LDS stays
+  // within DFB_RESW_KB (no weight traffic per step), else the step's slice,
+  // re-staged every step
   static constexpr int WS = (REGION_CH + NCH * W_CH) * 16 + BN * 4 <= DFB_RESW_KB * 1024 ? NCH : 1;
   static constexpr int STG_ROOM = (WS == 1 && NCH > 1 ? REGION_CH + W_CH : REGION_CH) * 16;
   static constexpr int NPASS = STG1 <= STG_ROOM ? 1 : 2;
   static constexpr size_t BYTES = static_cast<size_t>(REGION_CH + WS * W_CH) * 16 + BN * 4;  // + the bias
-  // waves per SIMD the register allocation is held to: the workgroups that
-  // fit a compute unit's 160 KB of LDS, at most 4
+  // waves per SIMD the register allocation is held to: those of the
+  // workgroups that fit a compute unit's 160 KB of LDS, at most 4
   static constexpr int LDS_WG = static_cast<int>((160 * 1024) / BYTES);
   // ... and at most 2 where a step re-stages 64 or more channels' weights:
   // their prefetch registers and accumulators need more than 168 VGPRs
   static constexpr int REG_WAVES = WS == 1 && NCH > 1 && BN >= 64 ? 2 : 4;
-  static constexpr int WAVES_LDS = LDS_WG < 1 ? 1 : (LDS_WG > 4 ? 4 : LDS_WG);
+  static constexpr int WAVES_LDS = LDS_WG * NT / 256 < 1 ? 1 : (LDS_WG * NT / 256 > 4 ? 4 : LDS_WG * NT / 256);
   static constexpr int WAVES = WAVES_LDS < REG_WAVES ? WAVES_LDS : REG_WAVES;
 };
 // Raw buffer accesses with a 2 GB range from a per-step base: an offset of
@@ -215,13 +222,14 @@ struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c
 };
 
 template <int BN, int CP, int TH, bool UP, int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
+__global__ void __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
 conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
            Shape s) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
   constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
-  static_assert(!OUT || (BN == 32 && TH * kTW == 256), "the output conv takes one pixel per thread");
-  constexpr int NCH = CP / kKC, MB = TH / 4, NB = BN / 32;  // tile rows and 32-channel blocks per wave
+  static_assert(!OUT || BN == 32, "the output conv takes 32 channels, one pixel per thread");
+  constexpr int NT = C::NT;  // threads (a wave per two tile rows)
+  constexpr int NCH = CP / kKC, MB = 2, NB = BN / 32;  // tile rows and 32-channel blocks per wave
   constexpr int SHH = C::SHH, SHW = C::SHW, HALO_EL = C::HALO_EL, HIT = C::HIT, WIT = C::WIT;
   static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
   extern __shared__ __align__(16) uint4 lds4[];
@@ -273,14 +281,14 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     }
   };
 
-  // this thread's halo elements e = tid + 256 k: halo pixel e / 4 (row, column),
+  // this thread's halo elements e = tid + NT k: halo pixel e / 4 (row, column),
   // chunk e % 4; byte offset from the step's source origin (the halo's
   // top-left pixel, or the pixel it is up-sampled from); LDS chunk
   // hlds + 64 * HPITCH * k
   int hrel[HIT];
 #pragma unroll
   for (int k = 0; k < HIT; ++k) {
-    const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / SHW, hc = hp - hr * SHW;
+    const int e = tid + NT * k, hp = e >> 2, cc = e & 3, hr = hp / SHW, hc = hp - hr * SHW;
     hrel[k] = e < HALO_EL ? ((hr * wi + hc) * x.ld + cc * 8) * 2 : kOOB;
   }
   const int hlds = (tid >> 2) * C::HPITCH + (tid & 3);
@@ -315,7 +323,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     } else {  // zeros outside the image and past xm.c
 #pragma unroll
       for (int k = 0; k < HIT; ++k) {
-        const int e = tid + 256 * k, hp = e >> 2, cc = e & 3, hr = hp / SHW, hc = hp - hr * SHW;
+        const int e = tid + NT * k, hp = e >> 2, cc = e & 3, hr = hp / SHW, hc = hp - hr * SHW;
         const int r = sy0 + hr, c = sx0 + hc;
         const int ok = (static_cast<unsigned>(r) < static_cast<unsigned>(hi)) &
                        (static_cast<unsigned>(c) < static_cast<unsigned>(wi)) & (cb + cc * 8 < xm.c) & !none;
@@ -330,7 +338,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   int wrel[WIT];  // byte offset of this thread's chunks in slice 0
 #pragma unroll
   for (int k = 0; k < WIT; ++k) {
-    const int e = tid + 256 * k;
+    const int e = tid + NT * k;
     wrel[k] = e < C::W_CH ? ((e >> 2) * cin + (e & 3) * 8) * 2 : kOOB;
   }
   auto load_w = [&](int ck, bool none, uint4* wreg) {
@@ -341,7 +349,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     } else {
 #pragma unroll
       for (int k = 0; k < WIT; ++k) {
-        const int cc = (tid + 256 * k) & 3;
+        const int cc = (tid + NT * k) & 3;
         off[k] = !none && ck * kKC + cc * 8 < cin ? wrel[k] + ck * kKC * 2 : kOOB;
       }
     }
@@ -351,7 +359,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   auto store_w = [&](const uint4* wreg, int slot) {
 #pragma unroll
     for (int k = 0; k < WIT; ++k) {
-      const int e = tid + 256 * k;
+      const int e = tid + NT * k;
       if (e < C::W_CH) wts[slot * C::W_CH + swz(e >> 2, e & 3)] = wreg[k];
     }
   };
@@ -371,9 +379,9 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   constexpr int NPASS = C::NPASS;
   constexpr int RP = TH / NPASS;  // tile rows per pass
   static_assert(RP * kTW * LDO * 2 <= C::STG_ROOM, "staging tile too large");
-  static_assert((RP * kTW * OCH) % 256 == 0 && RP % 2 == 0 && RP % MB == 0, "pass shape");
-  constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / 256;                           // stores per thread and pass
-  constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + 255) / 256 : 0;  // pool stores per thread and pass
+  static_assert((RP * kTW * OCH) % NT == 0 && RP % 2 == 0 && RP % MB == 0, "pass shape");
+  constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / NT;                             // stores per thread and pass
+  constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + NT - 1) / NT : 0;  // pool stores per thread and pass
   uint16_t* stg = reinterpret_cast<uint16_t*>(lds4);
   float bcur[3] = {0.f, 0.f, 0.f};  // kEpiOut: base of this thread's pixel of the tile being computed
   auto epilogue = [&](const Tile& u, bool dummy) {
@@ -405,7 +413,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       }
 #pragma unroll
       for (int k = 0; k < NOUT; ++k) {
-        const int e = tid + 256 * k, px = e / OCH, c = e % OCH, lrow = px / kTW, col = px % kTW;
+        const int e = tid + NT * k, px = e / OCH, c = e % OCH, lrow = px / kTW, col = px % kTW;
         const int row = pass * RP + lrow;
         const int ok = !dummy & (out_full | ((oy0 + row < s.h) & (ox0 + col < s.w)));
         const uint4 v = dummy ? uint4{0u, 0u, 0u, 0u} : *reinterpret_cast<const uint4*>(stg + (lrow * kTW + col) * LDO + c * 8);
@@ -416,7 +424,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       for (int k = 0; k < NPOOL; ++k) {
         // pooled pixel (qr, qc) of this pass: ((a + b) + c) + d of the staged
         // bf16 values, a b over c d
-        const int e = tid + 256 * k, qi = e / OCH, c = e % OCH, qr = qi / (kTW / 2), qc = qi % (kTW / 2);
+        const int e = tid + NT * k, qi = e / OCH, c = e % OCH, qr = qi / (kTW / 2), qc = qi % (kTW / 2);
         const int prow = pass * RP / 2 + qr;
         const int ok = !dummy & (e < (RP / 2) * (kTW / 2) * OCH) &
                        (out_full | ((oy0 / 2 + prow < ph) & (ox0 / 2 + qc < pw)));
@@ -512,7 +520,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       __syncthreads();  // the previous step's fragment reads are done
 #pragma unroll
       for (int k = 0; k < HIT; ++k)
-        if (tid + 256 * k < HALO_EL) halo[hlds + 64 * C::HPITCH * k] = hreg[k];
+        if (tid + NT * k < HALO_EL) halo[hlds + (NT / 4) * C::HPITCH * k] = hreg[k];
       if (!RESW) store_w(wreg, 0);
       if (OUT && ck == 0) {
         bcur[0] = breg[0];
@@ -1258,14 +1266,14 @@ hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const flo
   }
   if (per_cu[dev] == 0) {
     int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, C::NT, lds);
     if (e != hipSuccess) return e;
     per_cu[dev] = nb > 0 ? nb : 1;
   }
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const long long grid = tiles < static_cast<long long>(cus) * per_cu[dev] ? tiles : static_cast<long long>(cus) * per_cu[dev];
-  conv_fwd_k<BN, CP, TH, UP, EPI><<<static_cast<unsigned>(grid), 256, lds, st>>>(x, x2, w, bias, y, pool, oc, s);
+  conv_fwd_k<BN, CP, TH, UP, EPI><<<static_cast<unsigned>(grid), C::NT, lds, st>>>(x, x2, w, bias, y, pool, oc, s);
   return hipGetLastError();
 }
 
