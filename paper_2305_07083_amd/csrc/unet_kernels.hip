@@ -102,16 +102,21 @@ constexpr int kTW = 32;  // tile width (pixels)
 constexpr int kXcds = 8;  // XCDs (each with its own L2) the workgroups of a launch are dealt to in turn
 constexpr int kKC = 32;  // input channels per step
 // Output-tile heights (rows of 32 pixels, 8 or 16) of the layers with
-// (output, input) channels (32, 32), (32, 64), (64, 64), (64, 128) and
-// (128, *); (64, 32) uses 8.  16 rows (8 waves) for the 64-channel layers:
-// a staged weight slice serves twice the pixels (2048^2 enc2b / dec2b 107 /
-// 98 -> 94 / 87 us, dec2a 181 -> 169 us); the 32-channel layers gain nothing
-// from it and the 128-channel ones would spill.
+// (output, input) channels (32, 32), (32, 64), (64, 32), (64, 64), (64, 128)
+// and (128, *).  16 rows (8 waves) for the 64-channel layers: a staged
+// weight slice serves twice the pixels (2048^2 enc2b / dec2b 107 / 98 -> 94 /
+// 87 us, dec2a 181 -> 169 us); and for the 32 -> 32 layers (4 waves per
+// SIMD instead of 3: enc1b 131 -> 126 us).  The 32 -> 64 and 64 -> 32
+// layers were slower with 16 rows (dec1a 186 -> 199, enc2a 53 -> 56 us) and
+// the 128-channel ones would spill.
 #ifndef DFB_TH_32_32
-#define DFB_TH_32_32 8
+#define DFB_TH_32_32 16
 #endif
 #ifndef DFB_TH_32_64
 #define DFB_TH_32_64 8
+#endif
+#ifndef DFB_TH_64_32
+#define DFB_TH_64_32 8
 #endif
 #ifndef DFB_TH_64_64
 #define DFB_TH_64_64 16
@@ -380,6 +385,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   constexpr int RP = TH / NPASS;  // tile rows per pass
   static_assert(RP * kTW * LDO * 2 <= C::STG_ROOM, "staging tile too large");
   static_assert((RP * kTW * OCH) % NT == 0 && RP % 2 == 0 && RP % MB == 0, "pass shape");
+  static_assert(!OUT || NPASS == 1, "the output conv reads every staged row of the tile");
   constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / NT;                             // stores per thread and pass
   constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + NT - 1) / NT : 0;  // pool stores per thread and pass
   uint16_t* stg = reinterpret_cast<uint16_t*>(lds4);
@@ -1296,7 +1302,7 @@ hipError_t conv_tile(const Map& x, const Map& x2, const uint16_t* w, const float
   if (y.c == BN_ && cp == CP_) return launch_tile<BN_, CP_, UP ? THU_ : TH_, UP>(x, x2, w, bias, y, pool, s, st);
   DFB_CONV(32, 32, DFB_TH_32_32, DFB_TH_32_32)
   DFB_CONV(32, 64, DFB_TH_32_64, DFB_THU_32_64)
-  DFB_CONV(64, 32, 8, 8)
+  DFB_CONV(64, 32, DFB_TH_64_32, DFB_TH_64_32)
   DFB_CONV(64, 64, DFB_TH_64_64, DFB_TH_64_64)
   DFB_CONV(64, 128, DFB_TH_64_128, DFB_THU_64_128)
   DFB_CONV(128, 64, DFB_TH_128, DFB_TH_128)
@@ -1418,7 +1424,7 @@ hipError_t conv3x3_out_fwd(const Map& x, const uint16_t* w_fwd, const float* bia
   const Map none{nullptr, 0, 0, 0};
   const OutConv oc{ow, ob, base, base_ld, out};
   const Map y{nullptr, 32, 0, 32};
-  return launch_conv<32, 32, 8, false, kEpiOut>(x, none, w_fwd, bias, y, none, oc, s, st);
+  return launch_conv<32, 32, DFB_TH_32_32, false, kEpiOut>(x, none, w_fwd, bias, y, none, oc, s, st);
 }
 
 hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base, int base_ld, float* out,
