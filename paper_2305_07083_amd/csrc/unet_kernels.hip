@@ -81,10 +81,10 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // number of independent accumulators).  It takes the weights as its row
 // operand (32 output channels) and a 32-pixel tile row as its column
 // operand; lane l holds pixel l % 32 and, in accumulator element r, channel
-// 8 (r / 4) + 4 (l / 32) + r % 4.  A workgroup is TH/2 waves; wave w owns
-// tile rows 2w and 2w + 1 and every 32-channel block of BN, so a taller tile
-// spreads a staged weight slice over more waves at the same registers per
-// wave.  The accumulators start from the bias;
+// 8 (r / 4) + 4 (l / 32) + r % 4.  A workgroup is CS * TH/2 waves; each
+// owns two tile rows and BN / CS output channels (CS = 2 for 128 channels,
+// else 1), so a taller tile spreads a staged weight slice over more waves at
+// the same registers per wave.  The accumulators start from the bias;
 // the epilogue (ReLU, v_cvt_pk_bf16_f32, optionally the 2x2 average pool)
 // goes through a staging tile in LDS so that the stores are coalesced.
 //
@@ -135,6 +135,12 @@ constexpr int kKC = 32;  // input channels per step
 #define DFB_THU_64_128 16
 #endif
 
+// Waves that share a tile's 128 output channels (each takes 128 / DFB_CS_128
+// of them): 2 halves the accumulators per wave, so the 128-channel layers
+// run 2 waves per SIMD instead of 1 at the same LDS.
+#ifndef DFB_CS_128
+#define DFB_CS_128 2
+#endif
 // LDS bytes up to which a layer keeps every input slice's weights resident
 // (the 16-row 64 -> 64 layers need 123 KB: one 8-wave workgroup per CU)
 #ifndef DFB_RESW_KB
@@ -151,7 +157,8 @@ struct ConvCfg {
   static constexpr int HALO_CH = SHH * SHW * HPITCH;  // 16-byte chunks of a step's halo
   static constexpr int HALO_EL = SHH * SHW * 4;       // chunks loaded per step
   static constexpr int W_CH = 9 * BN * 4;      // 16-byte chunks of a step's weights
-  static constexpr int NT = 32 * TH;           // threads: a wave per two tile rows
+  static constexpr int CS = BN >= 128 ? DFB_CS_128 : 1;  // waves sharing a tile row pair's channels
+  static constexpr int NT = 32 * TH * CS;      // threads: CS waves per two tile rows
   static constexpr int HIT = (HALO_EL + NT - 1) / NT, WIT = (W_CH + NT - 1) / NT;
   // The epilogue's staging tile (TH x 32 pixels of BN bf16 + 8 padding)
   // overlays the halo region, and the weights when a step re-stages them;
@@ -227,14 +234,16 @@ struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c
 };
 
 template <int BN, int CP, int TH, bool UP, int EPI>
-__global__ void __launch_bounds__(32 * TH) __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
+__global__ void __launch_bounds__((ConvCfg<BN, TH, CP / kKC, UP>::NT))
+__attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
 conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
            Shape s) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
   constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
   static_assert(!OUT || BN == 32, "the output conv takes 32 channels, one pixel per thread");
-  constexpr int NT = C::NT;  // threads (a wave per two tile rows)
-  constexpr int NCH = CP / kKC, MB = 2, NB = BN / 32;  // tile rows and 32-channel blocks per wave
+  constexpr int NT = C::NT;  // threads (CS waves per two tile rows)
+  constexpr int NCH = CP / kKC, MB = 2, NB = BN / 32 / C::CS;  // tile rows and 32-channel blocks per wave
+  static_assert(NB >= 1 && NB * 32 * C::CS == BN, "channel split");
   constexpr int SHH = C::SHH, SHW = C::SHW, HALO_EL = C::HALO_EL, HIT = C::HIT, WIT = C::WIT;
   static_assert(!POOL || MB % 2 == 0, "the pool pairs rows inside a wave");
   extern __shared__ __align__(16) uint4 lds4[];
@@ -244,6 +253,9 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   // starting a tile waits on no global load issued after the prefetch
   float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
+  // wave = (channel group) * TH/2 + (row pair): rows 2 rw, 2 rw + 1 and the
+  // channel blocks cb0 / 32 .. + NB - 1
+  const int rw = C::CS > 1 ? wave % (TH / 2) : wave, cb0 = C::CS > 1 ? (wave / (TH / 2)) * NB * 32 : 0;
   const int tiles_x = (s.w + kTW - 1) / kTW, tiles_y = (s.h + TH - 1) / TH;
   const long long tiles = static_cast<long long>(s.n) * tiles_x * tiles_y;
   // workgroup b walks the tiles [b T / G, (b + 1) T / G) in row order (the
@@ -303,7 +315,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   // row r of the wave is staged row r (or (r + 1) / 2 with UP) and
   // aoff[dc] holds the lane's column: l32 + dc (or (l32 + dc + 1) / 2)
   const int boff[2] = {l32 * 4 + ((0 + lh) ^ ((l32 >> 2) & 3)), l32 * 4 + ((2 + lh) ^ ((l32 >> 2) & 3))};
-  const int wrow0 = UP ? wave * MB / 2 : wave * MB;  // the wave's first staged row (MB is even with UP)
+  const int wrow0 = UP ? rw * MB / 2 : rw * MB;  // the wave's first staged row (MB is even with UP)
   int aoff[UP ? 3 : 1];
 #pragma unroll
   for (int dc = 0; dc < (UP ? 3 : 1); ++dc)
@@ -401,7 +413,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
     for (int pass = 0; pass < NPASS; ++pass) {
       if (!dummy) {
         __syncthreads();  // every wave is done with the halo / weights (or the previous pass)
-        if (wave * MB / RP == pass) {
+        if (rw * MB / RP == pass) {
 #pragma unroll
           for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -409,8 +421,8 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
                 const f32x16& v = acc[m][j];
-                const int lrow = wave * MB + m - pass * RP;
-                *reinterpret_cast<uint2*>(stg + (lrow * kTW + l32) * LDO + j * 32 + 8 * q + 4 * lh) =
+                const int lrow = rw * MB + m - pass * RP;
+                *reinterpret_cast<uint2*>(stg + (lrow * kTW + l32) * LDO + cb0 + j * 32 + 8 * q + 4 * lh) =
                     uint2{pack_bf16(fmaxf(v[4 * q], 0.f), fmaxf(v[4 * q + 1], 0.f)),
                           pack_bf16(fmaxf(v[4 * q + 2], 0.f), fmaxf(v[4 * q + 3], 0.f))};
               }
@@ -548,7 +560,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
         for (int j = 0; j < NB; ++j)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const f32x4 b4 = *reinterpret_cast<const f32x4*>(lbias + j * 32 + 8 * q + 4 * lh);
+            const f32x4 b4 = *reinterpret_cast<const f32x4*>(lbias + cb0 + j * 32 + 8 * q + 4 * lh);
 #pragma unroll
             for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -562,7 +574,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
         const int tap = i >> 1, kh = i & 1, dr = tap / 3, dc = tap - (tap / 3) * 3;
 #pragma unroll
         for (int j = 0; j < NB; ++j)
-          wf[bsel][j] = __builtin_bit_cast(bf16x8, wts[(RESW ? ck : 0) * C::W_CH + (tap * BN + j * 32) * 4 + boff[kh]]);
+          wf[bsel][j] = __builtin_bit_cast(bf16x8, wts[(RESW ? ck : 0) * C::W_CH + (tap * BN + cb0 + j * 32) * 4 + boff[kh]]);
 #pragma unroll
         for (int m = 0; m < MB; ++m)
           hf[bsel][m] = __builtin_bit_cast(
