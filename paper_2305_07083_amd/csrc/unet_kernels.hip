@@ -866,10 +866,12 @@ constexpr int LDW = 32 * kWgradKS + 8;  // LDS row: the stage's pixels + 8 paddi
 // The MFMA is v_mfma_f32_32x32x16_bf16 on 32 c_in x 32 c_out blocks (row
 // and column operands read as 32 consecutive LDS rows at one 16-byte chunk;
 // the 136-element row pitch is an odd number of chunks, so the reads are free
-// of bank conflicts).  Wave w takes blocks w, w + 4, ... of the 2 * BN / 32
-// blocks; with fewer blocks than waves (BN = 32) the stage's pixels are split
-// between two waves per block and their sums added in a fixed order.
-template <int BN>
+// of bank conflicts).  Wave w takes blocks w, w + 4, ... of the MBLK * BN / 32
+// blocks (MBLK = 1 when the input has at most 32 channels: the c_in tile's
+// upper half is zero and is not multiplied); with fewer blocks than waves the
+// stage's pixels are split between 4 / blocks waves per block and their sums
+// added in a fixed order.
+template <int BN, bool HALF>
 __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restrict__ partial, Shape s) {
   __shared__ __align__(16) uint16_t As[BM * LDW];   // [ci][px]
   __shared__ __align__(16) uint16_t Bs[BN * LDW];   // [co][px]
@@ -878,7 +880,8 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restr
   const int dr = tap / 3 - 1, dc = tap % 3 - 1;
   const long long P = s.pixels();
   const long long p_begin = static_cast<long long>(chunk) * kWgradChunk;
-  constexpr int NBLK = 2 * (BN / 32);                      // 32 x 32 output blocks
+  constexpr int MBLK = HALF ? 1 : 2;                       // 32-row c_in blocks multiplied
+  constexpr int NBLK = MBLK * (BN / 32);                   // 32 x 32 output blocks
   constexpr int KSPLIT = NBLK >= 4 ? 1 : 4 / NBLK;         // waves per block
   constexpr int BPW = NBLK >= 4 ? NBLK / 4 : 1;            // blocks per wave
   constexpr int KSUB = 32 * kWgradKS / 16 / KSPLIT;        // 16-pixel MFMA steps per wave and stage
@@ -951,7 +954,7 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restr
       const int px = (kpart * KSUB + kk) * 16 + lh * 8;
 #pragma unroll
       for (int b = 0; b < BPW; ++b) {
-        const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk & 1, nb = blk >> 1;
+        const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk % MBLK, nb = blk / MBLK;
         const bf16x8 a = lds_frag(As + (mb * 32 + l32) * LDW + px);
         const bf16x8 bv = lds_frag(Bs + (nb * 32 + l32) * LDW + px);
         acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc[b], 0, 0, 0);
@@ -960,25 +963,27 @@ __global__ void __launch_bounds__(256) conv_wgrad_k(Map x, Map g, float* __restr
     __syncthreads();
     if (!more) break;
   }
-  if constexpr (KSPLIT > 1) {  // part 0 + part 1 (the stage loop ended on a barrier: As is free)
-    static_assert(KSPLIT == 2 && NBLK * 64 * 16 * 4 <= BM * LDW * 2, "reduction fits As");
+  if constexpr (KSPLIT > 1) {  // part 0 + part 1 + ... (the stage loop ended on a barrier: As is free)
+    static_assert((KSPLIT - 1) * NBLK * 64 * 16 * 4 <= BM * LDW * 2, "reduction fits As");
     float* red = reinterpret_cast<float*>(As);
     const int blk = wave % NBLK;
-    if (kpart == 1) {
+    if (kpart > 0) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) red[(blk * 16 + r) * 64 + lane] = acc[0][r];
+      for (int r = 0; r < 16; ++r) red[(((kpart - 1) * NBLK + blk) * 16 + r) * 64 + lane] = acc[0][r];
     }
     __syncthreads();
     if (kpart == 0) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[0][r] += red[(blk * 16 + r) * 64 + lane];
+      for (int k = 1; k < KSPLIT; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[0][r] += red[(((k - 1) * NBLK + blk) * 16 + r) * 64 + lane];
     }
   }
   const int ci_n = x.c;
   if (kpart == 0) {
 #pragma unroll
     for (int b = 0; b < BPW; ++b) {
-      const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk & 1, nb = blk >> 1;
+      const int blk = KSPLIT > 1 ? wave % NBLK : wave + 4 * b, mb = blk % MBLK, nb = blk / MBLK;
       const int co = nb * 32 + l32;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -1376,10 +1381,20 @@ hipError_t conv3x3_wgrad(const Map& x, const Map& g, float* dw, float* partial, 
   if (x.c % 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
   if (g.ld % 4 || g.off % 4) return hipErrorInvalidValue;
   dim3 grid(chunks, 9, (x.c + BM - 1) / BM);
+  const bool half = x.c <= 32;  // one 32-row c_in block carries every input channel
   switch (g.c) {
-    case 32: conv_wgrad_k<32><<<grid, 256, 0, st>>>(x, g, partial, s); break;
-    case 64: conv_wgrad_k<64><<<grid, 256, 0, st>>>(x, g, partial, s); break;
-    case 128: conv_wgrad_k<128><<<grid, 256, 0, st>>>(x, g, partial, s); break;
+    case 32:
+      if (half) conv_wgrad_k<32, true><<<grid, 256, 0, st>>>(x, g, partial, s);
+      else conv_wgrad_k<32, false><<<grid, 256, 0, st>>>(x, g, partial, s);
+      break;
+    case 64:
+      if (half) conv_wgrad_k<64, true><<<grid, 256, 0, st>>>(x, g, partial, s);
+      else conv_wgrad_k<64, false><<<grid, 256, 0, st>>>(x, g, partial, s);
+      break;
+    case 128:
+      if (half) conv_wgrad_k<128, true><<<grid, 256, 0, st>>>(x, g, partial, s);
+      else conv_wgrad_k<128, false><<<grid, 256, 0, st>>>(x, g, partial, s);
+      break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
