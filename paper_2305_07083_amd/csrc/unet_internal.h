@@ -86,13 +86,22 @@ hipError_t adam_update(float* w, const float* g, float* m, float* v, long long n
 hipError_t refresh_bf16(const float* w_master, uint16_t* w_fwd, uint16_t* w_dgrad, int ci, int co,
                         hipStream_t st);
 
-// Compositor glue: NHWC denoiser input from tile-major mean / tile variance,
-// and the per-tile choice between denoised and plain mean + tonemap.
+// Compositor glue: NHWC denoiser input from tile-major mean / tile variance.
 using dfb::FrameGlue;
 hipError_t frame_to_input(const FrameGlue& g, float* in6, hipStream_t st);
-hipError_t frame_from_output(const FrameGlue& g, const float* out3, float var_threshold,
-                             float* denoised, void* final_out, uint32_t mode, float inv_gamma,
-                             hipStream_t st);
+// conv3x3_in_fwd reading that input straight from the frame (one image of
+// the frame's size), without materialising it.
+hipError_t conv3x3_in_frame(const FrameGlue& g, const uint16_t* w_fwd, const float* bias, const Map& y,
+                            const Shape& s, hipStream_t st);
+// conv3x3_out_fwd with the frame's mean as base, writing the frame instead
+// of out: den[e] = (out, mean alpha), or the mean where the tile falls back
+// (n >= 2 and variance > tau); padding pixels of ragged edge tiles get the
+// mean; then the display value of every pixel in final_out by mode
+// (kModeFmtRGBA8 / kModeFmtF32, kModeGamma).  den is required; final_out
+// when mode has a format.
+hipError_t conv3x3_out_frame(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
+                             const FrameGlue& g, float tau, float* den, void* final_out, uint32_t mode,
+                             float inv_gamma, const Shape& s, hipStream_t st);
 
 }  // namespace unet
 }  // namespace dfb

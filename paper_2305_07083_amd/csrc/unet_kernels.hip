@@ -222,15 +222,23 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 __device__ __forceinline__ float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
 
+
 // Epilogue kinds: plain, plus the 2x2 average pool, or instead of storing
-// y the network's 1x1 output conv and residual (inference, 32 channels).
-enum Epi { kEpiPlain = 0, kEpiPool = 1, kEpiOut = 2 };
+// y the network's 1x1 output conv and residual (inference, 32 channels):
+// into out, or (kEpiFrame) straight into a compositor frame.
+enum Epi { kEpiPlain = 0, kEpiPool = 1, kEpiOut = 2, kEpiFrame = 3 };
 struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c < 3
   const float* w;    // [32][3]
   const float* b;    // [3]
   const float* base; // [p][base_ld]
   int base_ld;
   float* out;        // [p][3]
+  // kEpiFrame: base is the frame's running mean (tile-major), and pixel e
+  // of the frame becomes den[e] = (out[p], mean alpha), or the mean itself
+  // where the tile falls back (n >= 2 and its variance above tau)
+  FrameGlue glue;
+  float tau;
+  float* den;        // [T][P][4]
 };
 
 template <int BN, int CP, int TH, bool UP, int EPI>
@@ -239,7 +247,7 @@ __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
 conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
            Shape s) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
-  constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiOut;
+  constexpr bool POOL = EPI == kEpiPool, FRAME = EPI == kEpiFrame, OUT = EPI == kEpiOut || FRAME;
   static_assert(!OUT || BN == 32, "the output conv takes 32 channels, one pixel per thread");
   constexpr int NT = C::NT;  // threads (CS waves per two tile rows)
   constexpr int NCH = CP / kKC, MB = 2, NB = BN / 32 / C::CS;  // tile rows and 32-channel blocks per wave
@@ -251,7 +259,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   uint4* wts = lds4 + C::REGION_CH;  // [WS][9 * BN][4]
   float* lbias = reinterpret_cast<float*>(wts + C::WS * C::W_CH);  // [BN]: read per tile through LDS, so
   // starting a tile waits on no global load issued after the prefetch
-  float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut)
+  float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut, kEpiFrame)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
   // wave = (channel group) * TH/2 + (row pair): rows 2 rw, 2 rw + 1 and the
   // channel blocks cb0 / 32 .. + NB - 1
@@ -401,7 +409,11 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / NT;                             // stores per thread and pass
   constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + NT - 1) / NT : 0;  // pool stores per thread and pass
   uint16_t* stg = reinterpret_cast<uint16_t*>(lds4);
-  float bcur[3] = {0.f, 0.f, 0.f};  // kEpiOut: base of this thread's pixel of the tile being computed
+  // kEpiOut: base of this thread's pixel of the tile being computed;
+  // kEpiFrame: its mean RGBA and tile variance, and its frame index
+  float bcur[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  int ecur = 0;
+  const int n_acc = FRAME ? oc.glue.state->n_acc : 0;
   auto epilogue = [&](const Tile& u, bool dummy) {
     const int n = u.n, oy0 = u.ty * TH, ox0 = u.tx * kTW;
     const bool out_full = oy0 + TH <= s.h && ox0 + kTW <= s.w;
@@ -489,19 +501,39 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 #pragma unroll
           for (int c = 0; c < 3; ++c) o3[c] = (bcur[c] + lout[96 + c]) + a3[c];
         }
-        const __amdgpu_buffer_rsrc_t ob =
-            buf_rsrc(oc.out + ((static_cast<long long>(n) * s.h + oy0) * s.w + ox0) * 3);
-        const u32x3 ov = {__float_as_uint(o3[0]), __float_as_uint(o3[1]), __float_as_uint(o3[2])};
-        __builtin_amdgcn_raw_buffer_store_b96(ov, ob, ok ? (row * s.w + col) * 12 : kOOB + pass * 16, 0, 0);
+        if constexpr (FRAME) {
+          const bool fb = n_acc >= 2 && bcur[4] > oc.tau;
+          const u32x4 dv = {__float_as_uint(fb ? bcur[0] : o3[0]), __float_as_uint(fb ? bcur[1] : o3[1]),
+                            __float_as_uint(fb ? bcur[2] : o3[2]), __float_as_uint(bcur[3])};
+          __builtin_amdgcn_raw_buffer_store_b128(dv, buf_rsrc(oc.den), ok ? ecur * 16 : kOOB + pass * 16, 0, 0);
+        } else {
+          const __amdgpu_buffer_rsrc_t ob =
+              buf_rsrc(oc.out + ((static_cast<long long>(n) * s.h + oy0) * s.w + ox0) * 3);
+          const u32x3 ov = {__float_as_uint(o3[0]), __float_as_uint(o3[1]), __float_as_uint(o3[2])};
+          __builtin_amdgcn_raw_buffer_store_b96(ov, ob, ok ? (row * s.w + col) * 12 : kOOB + pass * 16, 0, 0);
+        }
       }
     }
   };
 
   uint4 hreg[HIT], wreg[WIT];
-  float breg[3];  // kEpiOut: base of this thread's pixel of the tile being prefetched
+  float breg[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // bcur and ecur of the tile being prefetched
+  int ereg = 0;
   auto load_base = [&](const Tile& u, bool none) {
     if (!OUT) return;
     const int oy0 = u.ty * TH, ox0 = u.tx * kTW, row = tid / kTW, col = tid % kTW;
+    if constexpr (FRAME) {
+      const FrameGlue& g = oc.glue;
+      const int r = oy0 + row, c = ox0 + col, ty = r / g.tile_h, tx = c / g.tile_w, t = ty * g.tiles_x + tx;
+      const int ok = !none & (r < s.h) & (c < s.w);
+      ereg = t * g.P + (r - ty * g.tile_h) * g.tile_w + (c - tx * g.tile_w);
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(buf_rsrc(g.accum), ok ? ereg * 16 : kOOB, 0, 0);
+      const uint32_t var = __builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(g.tile_var), ok ? t * 4 : kOOB, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) breg[i] = __uint_as_float(v[i]);
+      breg[4] = __uint_as_float(var);
+      return;
+    }
     const __amdgpu_buffer_rsrc_t br =
         buf_rsrc(oc.base + ((static_cast<long long>(u.n) * s.h + oy0) * s.w + ox0) * oc.base_ld);
     const int ok = !none & (oy0 + row < s.h) & (ox0 + col < s.w);
@@ -541,9 +573,9 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
         if (tid + NT * k < HALO_EL) halo[hlds + (NT / 4) * C::HPITCH * k] = hreg[k];
       if (!RESW) store_w(wreg, 0);
       if (OUT && ck == 0) {
-        bcur[0] = breg[0];
-        bcur[1] = breg[1];
-        bcur[2] = breg[2];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) bcur[i] = breg[i];
+        ecur = ereg;
       }
       __syncthreads();
       // prefetch the next step: the next slice, or slice 0 of the next tile
@@ -608,8 +640,13 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 // input (6 f32 channels per pixel) is read directly and rounded to bf16
 // while it is staged, as the input packing does.
 constexpr int kInTH = 8, kInHW = kTW + 2, kInHH = kInTH + 2, kInHalo = kInHH * kInHW, kInWP = 11;
-template <bool F32IN>
-__global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict__ xin, int xin_ld,
+// SRC: kInMap reads the packed bf16 input x; kInF32 the f32 network input
+// xin [p][xin_ld]; kInFrame builds the input from a compositor frame's
+// running mean and tile variance as it loads the halo (the values the frame
+// glue would write: mean RGBA, log variance or 0 before two frames, 1/n).
+enum InSrc { kInMap = 0, kInF32 = 1, kInFrame = 2 };
+template <int SRC>
+__global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict__ xin, int xin_ld, FrameGlue fg,
                                                  const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y,
                                                  Shape s) {
   constexpr int LDO = 40;  // staging row (one pixel) in bf16
@@ -629,7 +666,20 @@ __global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict_
     const int ok = (e < kInHalo) & (static_cast<unsigned>(r) < static_cast<unsigned>(s.h)) &
                    (static_cast<unsigned>(c) < static_cast<unsigned>(s.w));
     const int pix = r * s.w + c;  // within image n
-    if (F32IN) {
+    if (SRC == kInFrame) {  // one image
+      float4 mu = make_float4(0.f, 0.f, 0.f, 0.f);
+      float lv = 0.f, inv_n = 0.f;
+      if (ok) {
+        const int ty = r / fg.tile_h, tx = c / fg.tile_w, t = ty * fg.tiles_x + tx;
+        mu = reinterpret_cast<const float4*>(fg.accum)[static_cast<size_t>(t) * fg.P + (r - ty * fg.tile_h) * fg.tile_w +
+                                                      (c - tx * fg.tile_w)];
+        const float v = fg.tile_var[t];
+        const int n_acc = fg.state->n_acc;
+        lv = n_acc >= 2 ? logf(v > 1e-12f ? v : 1e-12f) : 0.f;
+        inv_n = 1.f / static_cast<float>(n_acc);
+      }
+      hv[k] = uint4{pack_bf16(mu.x, mu.y), pack_bf16(mu.z, mu.w), pack_bf16(lv, inv_n), 0u};
+    } else if (SRC == kInF32) {
       const __amdgpu_buffer_rsrc_t src = buf_rsrc(xin + static_cast<long long>(n) * s.h * s.w * xin_ld);
       const int off = ok ? pix * xin_ld * 4 : kOOB;
       const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(src, off, 0, 0);
@@ -1230,6 +1280,7 @@ __global__ void frame_to_input_k(FrameGlue g, float* __restrict__ in6) {
   o[5] = 1.f / static_cast<float>(n_acc);
 }
 
+// display quantisation of one channel to 8 bits (optional gamma)
 __device__ __forceinline__ uint32_t q8(float x, bool gamma, float inv_gamma) {
   float y = x > 0.f ? x : 0.f;
   y = y < 1.f ? y : 1.f;
@@ -1237,24 +1288,24 @@ __device__ __forceinline__ uint32_t q8(float x, bool gamma, float inv_gamma) {
   return static_cast<uint32_t>(floorf(fmaf(255.f, y, 0.5f)));
 }
 
-__global__ void frame_from_output_k(FrameGlue g, const float* __restrict__ out3, float tau,
-                                    float* __restrict__ den, void* final_out, uint32_t mode, float inv_gamma) {
+// The frame's display buffer from its denoised pixels; the padding pixels of
+// ragged edge tiles, which the network does not see, take the running mean
+// (in den too).
+__global__ void frame_display_k(FrameGlue g, float* __restrict__ den, void* final_out, uint32_t mode,
+                                float inv_gamma) {
   const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int T = g.tiles_x * ((g.height + g.tile_h - 1) / g.tile_h);
   if (e >= static_cast<long long>(T) * g.P) return;
   const int t = static_cast<int>(e / g.P), q = static_cast<int>(e - static_cast<long long>(t) * g.P);
   const int x = (t % g.tiles_x) * g.tile_w + q % g.tile_w;
   const int y = (t / g.tiles_x) * g.tile_h + q / g.tile_w;
-  float4 v = reinterpret_cast<const float4*>(g.accum)[e];
-  const float var = g.tile_var[t];
-  const bool fallback = g.state->n_acc >= 2 && var > tau;   // measured and too noisy: plain mean
-  if (!fallback && x < g.width && y < g.height) {
-    const long long p = static_cast<long long>(y) * g.width + x;
-    v.x = out3[p * 3];
-    v.y = out3[p * 3 + 1];
-    v.z = out3[p * 3 + 2];
+  float4 v;
+  if (x < g.width && y < g.height) {
+    v = reinterpret_cast<const float4*>(den)[e];
+  } else {
+    v = reinterpret_cast<const float4*>(g.accum)[e];
+    reinterpret_cast<float4*>(den)[e] = v;
   }
-  if (den) reinterpret_cast<float4*>(den)[e] = v;
   if (mode & kModeFmtRGBA8) {
     const bool gm = (mode & kModeGamma) != 0;
     static_cast<uint32_t*>(final_out)[e] = q8(v.x, gm, inv_gamma) | (q8(v.y, gm, inv_gamma) << 8) |
@@ -1273,7 +1324,7 @@ hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const flo
                        const OutConv& oc, const Shape& s, hipStream_t st) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
   const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, EPI>);
-  const size_t lds = C::BYTES + (EPI == kEpiOut ? 99 * 4 : 0);
+  const size_t lds = C::BYTES + (EPI == kEpiOut || EPI == kEpiFrame ? 99 * 4 : 0);
   const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
   if (tiles == 0) return hipSuccess;
   if (tiles > (1LL << 30)) return hipErrorInvalidValue;
@@ -1436,10 +1487,22 @@ hipError_t conv3x3_in_fwd(const Map* x, const float* xin, int xin_ld, const uint
   if (tiles == 0) return hipSuccess;
   if (tiles > (1LL << 30)) return hipErrorInvalidValue;
   const Map none{nullptr, 0, 0, 0};
+  const FrameGlue ng{};
   if (x)
-    conv_in_k<false><<<static_cast<unsigned>(tiles), 256, 0, st>>>(*x, nullptr, 0, w_fwd, bias, y, s);
+    conv_in_k<kInMap><<<static_cast<unsigned>(tiles), 256, 0, st>>>(*x, nullptr, 0, ng, w_fwd, bias, y, s);
   else
-    conv_in_k<true><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, xin, xin_ld, w_fwd, bias, y, s);
+    conv_in_k<kInF32><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, xin, xin_ld, ng, w_fwd, bias, y, s);
+  return hipGetLastError();
+}
+
+hipError_t conv3x3_in_frame(const FrameGlue& g, const uint16_t* w_fwd, const float* bias, const Map& y,
+                            const Shape& s, hipStream_t st) {
+  if (y.c != 32 || y.ld % 8 || y.off % 8 || s.n != 1 || s.h != g.height || s.w != g.width) return hipErrorInvalidValue;
+  if (static_cast<long long>(s.h) * s.w * y.ld >= (1LL << 30)) return hipErrorInvalidValue;
+  const long long tiles = static_cast<long long>((s.h + kInTH - 1) / kInTH) * ((s.w + kTW - 1) / kTW);
+  if (tiles == 0) return hipSuccess;
+  const Map none{nullptr, 0, 0, 0};
+  conv_in_k<kInFrame><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, nullptr, 0, g, w_fwd, bias, y, s);
   return hipGetLastError();
 }
 
@@ -1452,6 +1515,24 @@ hipError_t conv3x3_out_fwd(const Map& x, const uint16_t* w_fwd, const float* bia
   const OutConv oc{ow, ob, base, base_ld, out};
   const Map y{nullptr, 32, 0, 32};
   return launch_conv<32, 32, DFB_TH_32_32, false, kEpiOut>(x, none, w_fwd, bias, y, none, oc, s, st);
+}
+
+hipError_t conv3x3_out_frame(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
+                             const FrameGlue& g, float tau, float* den, void* final_out, uint32_t mode,
+                             float inv_gamma, const Shape& s, hipStream_t st) {
+  if (x.c != 32 || x.ld % 8 || x.off % 8 || !den || s.n != 1 || s.h != g.height || s.w != g.width)
+    return hipErrorInvalidValue;
+  if ((mode & (kModeFmtRGBA8 | kModeFmtF32)) && !final_out) return hipErrorInvalidValue;
+  const long long T = static_cast<long long>(g.tiles_x) * ((g.height + g.tile_h - 1) / g.tile_h);
+  if (T * g.P * 16 >= (1LL << 31) || static_cast<long long>(s.h) * s.w * x.ld >= (1LL << 30))
+    return hipErrorInvalidValue;
+  const Map none{nullptr, 0, 0, 0};
+  const OutConv oc{ow, ob, nullptr, 0, nullptr, g, tau, den};
+  const Map y{nullptr, 32, 0, 32};
+  hipError_t e = launch_conv<32, 32, DFB_TH_32_32, false, kEpiFrame>(x, none, w_fwd, bias, y, none, oc, s, st);
+  if (e != hipSuccess) return e;
+  frame_display_k<<<blocks(T * g.P, 256), 256, 0, st>>>(g, den, final_out, mode, inv_gamma);
+  return hipGetLastError();
 }
 
 hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base, int base_ld, float* out,
@@ -1509,13 +1590,6 @@ hipError_t frame_to_input(const FrameGlue& g, float* in6, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t frame_from_output(const FrameGlue& g, const float* out3, float var_threshold, float* denoised,
-                             void* final_out, uint32_t mode, float inv_gamma, hipStream_t st) {
-  const long long T = static_cast<long long>(g.tiles_x) * ((g.height + g.tile_h - 1) / g.tile_h);
-  frame_from_output_k<<<blocks(T * g.P, 256), 256, 0, st>>>(g, out3, var_threshold, denoised, final_out, mode,
-                                                            inv_gamma);
-  return hipGetLastError();
-}
 
 }  // namespace unet
 }  // namespace dfb

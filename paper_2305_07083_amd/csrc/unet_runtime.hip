@@ -81,10 +81,6 @@ struct dfb_denoiser_ctx {
   size_t scratch_n = 0;
   uint16_t* gate = nullptr;  // gated output gradient of the layer in the backward pass (bf16)
   float* loss_dev = nullptr;
-  // frame inference buffers (dfb_denoise)
-  float* frame_in = nullptr;
-  int64_t frame_px = 0;
-  float* frame_out = nullptr;
   Shape last{0, 0, 0};
   bool planar = false;  // the last forward kept the skip concatenations as separate maps
   bool lean = false;    // the last forward fused the output conv and did not store dec1b
@@ -159,7 +155,11 @@ CatLayout cat_layout(const dfb_denoiser_ctx* n, const Shape& s0, bool planar) {
 // `training` also materialises the up-sampled maps the backward pass reads
 // and keeps the skip concatenations interleaved.  `lean` (inference only)
 // computes the output conv in dec1b's epilogue and does not store dec1b.
-dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training, bool lean = false) {
+// With a frame `fv` (lean, in unused) the first layer reads its input from
+// the frame's accumulation and the last writes the frame's denoised and
+// display pixels (fallback threshold tau) instead of n->out.
+dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training, bool lean = false,
+                   const dfb::FrameView* fv = nullptr, float tau = 0.f) {
   const Shape s1{s0.n, s0.h / 2, s0.w / 2}, s2{s0.n, s0.h / 4, s0.w / 4};
   hipStream_t st = n->stream;
   const float* W = n->w;
@@ -167,7 +167,9 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
   using dfb::unet::conv3x3_fwd;
   const Map pool1 = mp(n->pool1, 32, 0, 32), pool2 = mp(n->pool2, 64, 0, 64);
   const CatLayout c = cat_layout(n, s0, !training);
-  if (lean && !training) {  // the first layer reads the f32 input itself
+  if (lean && !training && fv) {
+    NHIP(n, dfb::unet::conv3x3_in_frame(fv->glue, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
+  } else if (lean && !training) {  // the first layer reads the f32 input itself
     NHIP(n, dfb::unet::conv3x3_in_fwd(nullptr, in, 6, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
   } else {
     NHIP(n, dfb::unet::pack_input(in, 6, n->xin, s0, st));
@@ -192,7 +194,11 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
     NHIP(n, conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
   else
     NHIP(n, conv3x3_fwd(c.up1, n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st, false, nullptr, &c.enc1b));
-  if (lean && !training) {
+  if (lean && !training && fv) {
+    NHIP(n, dfb::unet::conv3x3_out_frame(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), W + n->off_ow, W + n->off_ob,
+                                         fv->glue, tau, fv->denoised, fv->final_out, fv->display_mode, fv->inv_gamma,
+                                         s0, st));
+  } else if (lean && !training) {
     NHIP(n, dfb::unet::conv3x3_out_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), W + n->off_ow, W + n->off_ob,
                                        in, 6, n->out, s0, st));
   } else {
@@ -460,10 +466,6 @@ dfb_status dfb_denoise(dfb_handle h, dfb_denoiser n, float var_threshold) {
   if (W % 4 || H % 4) return nfail(n, DFB_ERR_UNSUPPORTED, "frame width and height must be multiples of 4");
   const int64_t px = static_cast<int64_t>(W) * H;
   if (px > n->P0) return nfail(n, DFB_ERR_INVALID_ARG, "frame larger than the denoiser's max_pixels");
-  if (n->frame_px < px) {
-    if ((s = dalloc(n, &n->frame_in, static_cast<size_t>(px) * 6))) return s;
-    n->frame_px = px;
-  }
   if (n->stream != fv.stream) {
     // order the compositor's stream before ours
     hipEvent_t e;
@@ -472,10 +474,7 @@ dfb_status dfb_denoise(dfb_handle h, dfb_denoiser n, float var_threshold) {
     NHIP(n, hipStreamWaitEvent(n->stream, e, 0));
     NHIP(n, hipEventDestroy(e));
   }
-  NHIP(n, dfb::unet::frame_to_input(fv.glue, n->frame_in, n->stream));
-  if ((s = forward(n, n->frame_in, Shape{1, H, W}, false, true)) != DFB_OK) return s;
-  NHIP(n, dfb::unet::frame_from_output(fv.glue, n->out, var_threshold, fv.denoised, fv.final_out, fv.display_mode,
-                                       fv.inv_gamma, n->stream));
+  if ((s = forward(n, nullptr, Shape{1, H, W}, false, true, &fv, var_threshold)) != DFB_OK) return s;
   if (n->stream != fv.stream) {
     hipEvent_t e;
     NHIP(n, hipEventCreateWithFlags(&e, hipEventDisableTiming));

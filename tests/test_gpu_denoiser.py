@@ -171,6 +171,50 @@ def test_denoise_matches_forward_on_a_large_frame(dfb):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-6)
 
 
+@pytest.mark.parametrize("fmt,gamma", [("rgba8", 2.2), ("f32", 1.0)])
+def test_denoise_on_a_ragged_frame(dfb, fmt, gamma):
+    """dfb_denoise on a frame whose edge tiles reach past the image (200 x 136
+    with 64-pixel tiles), for both display formats: the network reads the
+    frame and writes its pixels in place, so against dfb_denoiser_forward on
+    the frame's input through the oracle's select (per-tile fallback, the
+    mean on padding pixels), and the display buffer against the oracle's
+    tonemap (RGBA8) or the denoised pixels themselves (f32)."""
+    torch = torch_dev()
+    W, H = 200, 136
+    f = workloads.brick_frame(W, H, (4, 4, 4), 64, seed=8, name="200x136 ragged")
+    cfg = dfb.make_config(W, H, 64, work=32, waves=4, gamma=gamma,
+                          fmt=dfb.DFB_FMT_RGBA8 if fmt == "rgba8" else dfb.DFB_FMT_RGBAF32)
+    with dfb.Compositor(cfg, stream_handle()) as c, dfb.Denoiser(W * H, seed=2, stream=stream_handle()) as dn:
+        for k in range(3):
+            x = workloads.noisy_colour(f, 0.2, 5, k)
+            c.set_fragments(torch.from_numpy(x).cuda(), x.shape[0], f.layers, f.expected)
+            c.composite(accumulate=True)
+        g_mu = c.read(dfb.DFB_BUF_ACCUM_F32)
+        g_v = c.read(dfb.DFB_BUF_TILE_VARIANCE)
+        inp = torch.empty((H, W, 6), dtype=torch.float32, device="cuda")
+        dfb.dfb_denoiser_frame_input(c.h, inp)
+        out = torch.empty((1, H, W, 3), dtype=torch.float32, device="cuda")
+        dfb.dfb_denoiser_forward(dn.net, inp, out, 1, H, W)
+        tau = float(np.median(g_v))
+        dfb.dfb_denoise(c.h, dn.net, tau)
+        got = c.read(dfb.DFB_BUF_DENOISED_F32)
+        final = c.read(dfb.DFB_BUF_FINAL)
+    ref = unet.select(g_mu, g_v, out.cpu().numpy()[0], 3, tau, W, H, 64, 64)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-6)
+    fell_back = g_v > tau
+    assert 0 < fell_back.sum() < len(g_v)
+    q = np.arange(64 * 64)
+    tiles_x = -(-W // 64)
+    xs = (np.arange(len(g_v))[:, None] % tiles_x) * 64 + q[None, :] % 64
+    ys = (np.arange(len(g_v))[:, None] // tiles_x) * 64 + q[None, :] // 64
+    pad = (xs >= W) | (ys >= H)
+    assert pad.sum() > 0 and np.array_equal(got[pad], g_mu[pad])
+    if fmt == "rgba8":
+        assert np.max(np.abs(final.astype(int) - oracle.tonemap(ref, gamma).astype(int))) <= 1
+    else:
+        assert np.array_equal(final, got)
+
+
 def test_adam_step_matches_oracle(dfb):
     torch = torch_dev()
     rng = np.random.default_rng(5)
