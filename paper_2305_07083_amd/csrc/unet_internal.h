@@ -58,16 +58,10 @@ hipError_t upsample2_backward(const MapF& dy, const MapF& dx, const Shape& s_in,
 hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_t st);
 
 // The first conv3x3 (8 input channels -> 32, ReLU, bf16) with the nine
-// taps packed into a 72-deep contraction, reading either the packed bf16
-// input x (x.c == 8) or, with x null, the f32 network input xin [p][xin_ld]
-// (its first 6 channels, rounded to bf16 as pack_input does).
-hipError_t conv3x3_in_fwd(const Map* x, const float* xin, int xin_ld, const uint16_t* w_fwd, const float* bias,
-                          const Map& y, const Shape& s, hipStream_t st);
-// The last conv3x3 (32 -> 32, ReLU, bf16) fused with the output conv:
-// out[p][c] = base[p][c] + ob[c] + sum_i y[p][i] ow[i][c] with y the conv's
-// bf16 output, which is not stored (inference).
-hipError_t conv3x3_out_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
-                           const float* base, int base_ld, float* out, const Shape& s, hipStream_t st);
+// taps packed into a 72-deep contraction, reading the packed bf16 input x
+// (x.c == 8).
+hipError_t conv3x3_in_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y, const Shape& s,
+                          hipStream_t st);
 // out[p][c] = base[p][c] + b[c] + sum_i x[p][i] w[i][c]   (c < 3, f32)
 hipError_t out_conv_fwd(const Map& x, const float* w, const float* b, const float* base,
                         int base_ld, float* out, const Shape& s, hipStream_t st);
@@ -93,8 +87,10 @@ hipError_t frame_to_input(const FrameGlue& g, float* in6, hipStream_t st);
 // the frame's size), without materialising it.
 hipError_t conv3x3_in_frame(const FrameGlue& g, const uint16_t* w_fwd, const float* bias, const Map& y,
                             const Shape& s, hipStream_t st);
-// conv3x3_out_fwd with the frame's mean as base, writing the frame instead
-// of out: den[e] = (out, mean alpha), or the mean where the tile falls back
+// The last conv3x3 (32 -> 32, ReLU, bf16) fused with the output conv and
+// written into the frame: with out[p][c] = mean[p][c] + ob[c] + sum_i y[p][i]
+// ow[i][c] (y the conv's bf16 output, not stored), den[e] = (out, mean
+// alpha), or the mean where the tile falls back
 // (n >= 2 and variance > tau); padding pixels of ragged edge tiles get the
 // mean; then the display value of every pixel in final_out by mode
 // (kModeFmtRGBA8 / kModeFmtF32, kModeGamma).  den is required; final_out

@@ -224,18 +224,15 @@ __device__ __forceinline__ float bf16_hi(uint32_t u) { return __uint_as_float(u 
 
 
 // Epilogue kinds: plain, plus the 2x2 average pool, or instead of storing
-// y the network's 1x1 output conv and residual (inference, 32 channels):
-// into out, or (kEpiFrame) straight into a compositor frame.
-enum Epi { kEpiPlain = 0, kEpiPool = 1, kEpiOut = 2, kEpiFrame = 3 };
-struct OutConv {     // out[p][c] = base[p][c] + b[c] + sum_i y[p][i] w[i][c], c < 3
+// y the network's 1x1 output conv and residual written straight into a
+// compositor frame (inference, 32 channels).
+enum Epi { kEpiPlain = 0, kEpiPool = 1, kEpiFrame = 2 };
+struct OutConv {     // out[p][c] = mean[p][c] + b[c] + sum_i y[p][i] w[i][c], c < 3
   const float* w;    // [32][3]
   const float* b;    // [3]
-  const float* base; // [p][base_ld]
-  int base_ld;
-  float* out;        // [p][3]
-  // kEpiFrame: base is the frame's running mean (tile-major), and pixel e
-  // of the frame becomes den[e] = (out[p], mean alpha), or the mean itself
-  // where the tile falls back (n >= 2 and its variance above tau)
+  // the frame's running mean (tile-major) and tile variances: pixel e of the
+  // frame becomes den[e] = (out[p], mean alpha), or the mean itself where
+  // the tile falls back (n >= 2 and its variance above tau)
   FrameGlue glue;
   float tau;
   float* den;        // [T][P][4]
@@ -247,7 +244,7 @@ __attribute__((amdgpu_waves_per_eu(ConvCfg<BN, TH, CP / kKC, UP>::WAVES)))
 conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y, Map pool, OutConv oc,
            Shape s) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
-  constexpr bool POOL = EPI == kEpiPool, FRAME = EPI == kEpiFrame, OUT = EPI == kEpiOut || FRAME;
+  constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiFrame;
   static_assert(!OUT || BN == 32, "the output conv takes 32 channels, one pixel per thread");
   constexpr int NT = C::NT;  // threads (CS waves per two tile rows)
   constexpr int NCH = CP / kKC, MB = 2, NB = BN / 32 / C::CS;  // tile rows and 32-channel blocks per wave
@@ -259,7 +256,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   uint4* wts = lds4 + C::REGION_CH;  // [WS][9 * BN][4]
   float* lbias = reinterpret_cast<float*>(wts + C::WS * C::W_CH);  // [BN]: read per tile through LDS, so
   // starting a tile waits on no global load issued after the prefetch
-  float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiOut, kEpiFrame)
+  float* lout = lbias + BN;  // [32 * 3 + 3] output-conv weights and bias (kEpiFrame)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l32 = lane & 31, lh = lane >> 5;
   // wave = (channel group) * TH/2 + (row pair): rows 2 rw, 2 rw + 1 and the
   // channel blocks cb0 / 32 .. + NB - 1
@@ -409,11 +406,11 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   constexpr int NOUT = OUT ? 0 : RP * kTW * OCH / NT;                             // stores per thread and pass
   constexpr int NPOOL = POOL ? ((RP / 2) * (kTW / 2) * OCH + NT - 1) / NT : 0;  // pool stores per thread and pass
   uint16_t* stg = reinterpret_cast<uint16_t*>(lds4);
-  // kEpiOut: base of this thread's pixel of the tile being computed;
-  // kEpiFrame: its mean RGBA and tile variance, and its frame index
+  // kEpiFrame: the mean RGBA and tile variance of this thread's pixel of the
+  // tile being computed, and its frame index
   float bcur[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   int ecur = 0;
-  const int n_acc = FRAME ? oc.glue.state->n_acc : 0;
+  const int n_acc = OUT ? oc.glue.state->n_acc : 0;
   auto epilogue = [&](const Tile& u, bool dummy) {
     const int n = u.n, oy0 = u.ty * TH, ox0 = u.tx * kTW;
     const bool out_full = oy0 + TH <= s.h && ox0 + kTW <= s.w;
@@ -480,7 +477,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
       }
       if (OUT) {
         // pixel tid of the tile: the 1x1 conv over its 32 staged bf16
-        // channels, in channel order, then (base + b) + sum
+        // channels, in channel order, then (mean + b) + sum
         const int lrow = tid / kTW, col = tid % kTW, row = pass * RP + lrow;
         const int ok = !dummy & (out_full | ((oy0 + row < s.h) & (ox0 + col < s.w)));
         float o3[3] = {0.f, 0.f, 0.f};
@@ -501,17 +498,10 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 #pragma unroll
           for (int c = 0; c < 3; ++c) o3[c] = (bcur[c] + lout[96 + c]) + a3[c];
         }
-        if constexpr (FRAME) {
-          const bool fb = n_acc >= 2 && bcur[4] > oc.tau;
-          const u32x4 dv = {__float_as_uint(fb ? bcur[0] : o3[0]), __float_as_uint(fb ? bcur[1] : o3[1]),
-                            __float_as_uint(fb ? bcur[2] : o3[2]), __float_as_uint(bcur[3])};
-          __builtin_amdgcn_raw_buffer_store_b128(dv, buf_rsrc(oc.den), ok ? ecur * 16 : kOOB + pass * 16, 0, 0);
-        } else {
-          const __amdgpu_buffer_rsrc_t ob =
-              buf_rsrc(oc.out + ((static_cast<long long>(n) * s.h + oy0) * s.w + ox0) * 3);
-          const u32x3 ov = {__float_as_uint(o3[0]), __float_as_uint(o3[1]), __float_as_uint(o3[2])};
-          __builtin_amdgcn_raw_buffer_store_b96(ov, ob, ok ? (row * s.w + col) * 12 : kOOB + pass * 16, 0, 0);
-        }
+        const bool fb = n_acc >= 2 && bcur[4] > oc.tau;
+        const u32x4 dv = {__float_as_uint(fb ? bcur[0] : o3[0]), __float_as_uint(fb ? bcur[1] : o3[1]),
+                          __float_as_uint(fb ? bcur[2] : o3[2]), __float_as_uint(bcur[3])};
+        __builtin_amdgcn_raw_buffer_store_b128(dv, buf_rsrc(oc.den), ok ? ecur * 16 : kOOB + pass * 16, 0, 0);
       }
     }
   };
@@ -522,25 +512,15 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
   auto load_base = [&](const Tile& u, bool none) {
     if (!OUT) return;
     const int oy0 = u.ty * TH, ox0 = u.tx * kTW, row = tid / kTW, col = tid % kTW;
-    if constexpr (FRAME) {
-      const FrameGlue& g = oc.glue;
-      const int r = oy0 + row, c = ox0 + col, ty = r / g.tile_h, tx = c / g.tile_w, t = ty * g.tiles_x + tx;
-      const int ok = !none & (r < s.h) & (c < s.w);
-      ereg = t * g.P + (r - ty * g.tile_h) * g.tile_w + (c - tx * g.tile_w);
-      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(buf_rsrc(g.accum), ok ? ereg * 16 : kOOB, 0, 0);
-      const uint32_t var = __builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(g.tile_var), ok ? t * 4 : kOOB, 0, 0);
+    const FrameGlue& g = oc.glue;
+    const int r = oy0 + row, c = ox0 + col, ty = r / g.tile_h, tx = c / g.tile_w, t = ty * g.tiles_x + tx;
+    const int ok = !none & (r < s.h) & (c < s.w);
+    ereg = t * g.P + (r - ty * g.tile_h) * g.tile_w + (c - tx * g.tile_w);
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(buf_rsrc(g.accum), ok ? ereg * 16 : kOOB, 0, 0);
+    const uint32_t var = __builtin_amdgcn_raw_buffer_load_b32(buf_rsrc(g.tile_var), ok ? t * 4 : kOOB, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) breg[i] = __uint_as_float(v[i]);
-      breg[4] = __uint_as_float(var);
-      return;
-    }
-    const __amdgpu_buffer_rsrc_t br =
-        buf_rsrc(oc.base + ((static_cast<long long>(u.n) * s.h + oy0) * s.w + ox0) * oc.base_ld);
-    const int ok = !none & (oy0 + row < s.h) & (ox0 + col < s.w);
-    const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(br, ok ? (row * s.w + col) * oc.base_ld * 4 : kOOB, 0, 0);
-    breg[0] = __uint_as_float(v[0]);
-    breg[1] = __uint_as_float(v[1]);
-    breg[2] = __uint_as_float(v[2]);
+    for (int i = 0; i < 4; ++i) breg[i] = __uint_as_float(v[i]);
+    breg[4] = __uint_as_float(var);
   };
   if (tid < BN) lbias[tid] = bias[tid];
   if (OUT && tid < 99) lout[tid] = tid < 96 ? oc.w[tid] : oc.b[tid - 96];
@@ -636,17 +616,14 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
 // zero weights) where the general kernel takes 18 with K padded to 32.  One
 // 8 x 32-pixel tile per workgroup; a halo pixel is one 16-byte LDS chunk
 // (an odd pitch: fragment reads are free of bank conflicts), a weight row
-// 11 chunks (10 tap slots and one of padding).  With F32IN the network
-// input (6 f32 channels per pixel) is read directly and rounded to bf16
-// while it is staged, as the input packing does.
+// 11 chunks (10 tap slots and one of padding).
 constexpr int kInTH = 8, kInHW = kTW + 2, kInHH = kInTH + 2, kInHalo = kInHH * kInHW, kInWP = 11;
-// SRC: kInMap reads the packed bf16 input x; kInF32 the f32 network input
-// xin [p][xin_ld]; kInFrame builds the input from a compositor frame's
-// running mean and tile variance as it loads the halo (the values the frame
-// glue would write: mean RGBA, log variance or 0 before two frames, 1/n).
-enum InSrc { kInMap = 0, kInF32 = 1, kInFrame = 2 };
-template <int SRC>
-__global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict__ xin, int xin_ld, FrameGlue fg,
+// FRAME false reads the packed bf16 input x; true builds the input from a
+// compositor frame's running mean and tile variance as it loads the halo
+// (the values the frame glue writes: mean RGBA, log variance or 0 before two
+// frames, 1/n, rounded to bf16 as the input packing does).
+template <bool FRAME>
+__global__ void __launch_bounds__(256) conv_in_k(Map x, FrameGlue fg,
                                                  const uint16_t* __restrict__ w, const float* __restrict__ bias, Map y,
                                                  Shape s) {
   constexpr int LDO = 40;  // staging row (one pixel) in bf16
@@ -666,7 +643,7 @@ __global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict_
     const int ok = (e < kInHalo) & (static_cast<unsigned>(r) < static_cast<unsigned>(s.h)) &
                    (static_cast<unsigned>(c) < static_cast<unsigned>(s.w));
     const int pix = r * s.w + c;  // within image n
-    if (SRC == kInFrame) {  // one image
+    if (FRAME) {  // one image
       float4 mu = make_float4(0.f, 0.f, 0.f, 0.f);
       float lv = 0.f, inv_n = 0.f;
       if (ok) {
@@ -679,15 +656,6 @@ __global__ void __launch_bounds__(256) conv_in_k(Map x, const float* __restrict_
         inv_n = 1.f / static_cast<float>(n_acc);
       }
       hv[k] = uint4{pack_bf16(mu.x, mu.y), pack_bf16(mu.z, mu.w), pack_bf16(lv, inv_n), 0u};
-    } else if (SRC == kInF32) {
-      const __amdgpu_buffer_rsrc_t src = buf_rsrc(xin + static_cast<long long>(n) * s.h * s.w * xin_ld);
-      const int off = ok ? pix * xin_ld * 4 : kOOB;
-      const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(src, off, 0, 0);
-      const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(src, off + 8, 0, 0);
-      const u32x2 c2 = __builtin_amdgcn_raw_buffer_load_b64(src, off + 16, 0, 0);
-      hv[k] = uint4{pack_bf16(__uint_as_float(a[0]), __uint_as_float(a[1])),
-                    pack_bf16(__uint_as_float(b[0]), __uint_as_float(b[1])),
-                    pack_bf16(__uint_as_float(c2[0]), __uint_as_float(c2[1])), 0u};
     } else {
       const __amdgpu_buffer_rsrc_t src = buf_rsrc(x.p + x.off + static_cast<long long>(n) * s.h * s.w * x.ld);
       hv[k] = buf_load16(src, ok ? pix * x.ld * 2 : kOOB);
@@ -1324,7 +1292,7 @@ hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const flo
                        const OutConv& oc, const Shape& s, hipStream_t st) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
   const void* f = reinterpret_cast<const void*>(&conv_fwd_k<BN, CP, TH, UP, EPI>);
-  const size_t lds = C::BYTES + (EPI == kEpiOut || EPI == kEpiFrame ? 99 * 4 : 0);
+  const size_t lds = C::BYTES + (EPI == kEpiFrame ? 99 * 4 : 0);
   const long long tiles = static_cast<long long>(s.n) * ((s.h + TH - 1) / TH) * ((s.w + kTW - 1) / kTW);
   if (tiles == 0) return hipSuccess;
   if (tiles > (1LL << 30)) return hipErrorInvalidValue;
@@ -1354,7 +1322,7 @@ hipError_t launch_conv(const Map& x, const Map& x2, const uint16_t* w, const flo
 template <int BN, int CP, int TH, bool UP>
 hipError_t launch_tile(const Map& x, const Map& x2, const uint16_t* w, const float* bias, const Map& y,
                        const Map& pool, const Shape& s, hipStream_t st) {
-  const OutConv none{nullptr, nullptr, nullptr, 0, nullptr};
+  const OutConv none{nullptr, nullptr, FrameGlue{}, 0.f, nullptr};
   if (pool.p) {
     if constexpr ((TH / 4) % 2 == 0) return launch_conv<BN, CP, TH, UP, kEpiPool>(x, x2, w, bias, y, pool, none, s, st);
     return hipErrorInvalidValue;
@@ -1476,22 +1444,16 @@ hipError_t add_into(const MapF& src, const MapF& dst, const Shape& s, hipStream_
   return hipGetLastError();
 }
 
-hipError_t conv3x3_in_fwd(const Map* x, const float* xin, int xin_ld, const uint16_t* w_fwd, const float* bias,
-                          const Map& y, const Shape& s, hipStream_t st) {
+hipError_t conv3x3_in_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const Map& y, const Shape& s,
+                          hipStream_t st) {
   if (y.c != 32 || y.ld % 8 || y.off % 8) return hipErrorInvalidValue;
-  if (x && (x->c != 8 || x->ld % 8 || x->off % 8)) return hipErrorInvalidValue;
-  if (!x && (!xin || xin_ld < 6 || xin_ld % 2)) return hipErrorInvalidValue;
+  if (x.c != 8 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
   const long long img = static_cast<long long>(s.h) * s.w;
-  if (img * (x ? x->ld : xin_ld) * 4 >= (1LL << 31) || img * y.ld >= (1LL << 30)) return hipErrorInvalidValue;
+  if (img * x.ld * 2 >= (1LL << 31) || img * y.ld >= (1LL << 30)) return hipErrorInvalidValue;
   const long long tiles = static_cast<long long>(s.n) * ((s.h + kInTH - 1) / kInTH) * ((s.w + kTW - 1) / kTW);
   if (tiles == 0) return hipSuccess;
   if (tiles > (1LL << 30)) return hipErrorInvalidValue;
-  const Map none{nullptr, 0, 0, 0};
-  const FrameGlue ng{};
-  if (x)
-    conv_in_k<kInMap><<<static_cast<unsigned>(tiles), 256, 0, st>>>(*x, nullptr, 0, ng, w_fwd, bias, y, s);
-  else
-    conv_in_k<kInF32><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, xin, xin_ld, ng, w_fwd, bias, y, s);
+  conv_in_k<false><<<static_cast<unsigned>(tiles), 256, 0, st>>>(x, FrameGlue{}, w_fwd, bias, y, s);
   return hipGetLastError();
 }
 
@@ -1502,19 +1464,8 @@ hipError_t conv3x3_in_frame(const FrameGlue& g, const uint16_t* w_fwd, const flo
   const long long tiles = static_cast<long long>((s.h + kInTH - 1) / kInTH) * ((s.w + kTW - 1) / kTW);
   if (tiles == 0) return hipSuccess;
   const Map none{nullptr, 0, 0, 0};
-  conv_in_k<kInFrame><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, nullptr, 0, g, w_fwd, bias, y, s);
+  conv_in_k<true><<<static_cast<unsigned>(tiles), 256, 0, st>>>(none, g, w_fwd, bias, y, s);
   return hipGetLastError();
-}
-
-hipError_t conv3x3_out_fwd(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
-                           const float* base, int base_ld, float* out, const Shape& s, hipStream_t st) {
-  if (x.c != 32 || x.ld % 8 || x.off % 8) return hipErrorInvalidValue;
-  if (static_cast<long long>(s.h) * s.w * x.ld >= (1LL << 30) || static_cast<long long>(s.h) * s.w * base_ld >= (1LL << 29))
-    return hipErrorInvalidValue;
-  const Map none{nullptr, 0, 0, 0};
-  const OutConv oc{ow, ob, base, base_ld, out};
-  const Map y{nullptr, 32, 0, 32};
-  return launch_conv<32, 32, DFB_TH_32_32, false, kEpiOut>(x, none, w_fwd, bias, y, none, oc, s, st);
 }
 
 hipError_t conv3x3_out_frame(const Map& x, const uint16_t* w_fwd, const float* bias, const float* ow, const float* ob,
@@ -1527,7 +1478,7 @@ hipError_t conv3x3_out_frame(const Map& x, const uint16_t* w_fwd, const float* b
   if (T * g.P * 16 >= (1LL << 31) || static_cast<long long>(s.h) * s.w * x.ld >= (1LL << 30))
     return hipErrorInvalidValue;
   const Map none{nullptr, 0, 0, 0};
-  const OutConv oc{ow, ob, nullptr, 0, nullptr, g, tau, den};
+  const OutConv oc{ow, ob, g, tau, den};
   const Map y{nullptr, 32, 0, 32};
   hipError_t e = launch_conv<32, 32, DFB_TH_32_32, false, kEpiFrame>(x, none, w_fwd, bias, y, none, oc, s, st);
   if (e != hipSuccess) return e;

@@ -153,13 +153,14 @@ CatLayout cat_layout(const dfb_denoiser_ctx* n, const Shape& s0, bool planar) {
 // forward on in (f32 NHWC 6 ch) -> n->out.  The 2x2 pools come out of the
 // enc1b / enc2b epilogues and the up-sampling is read through by up2 / up1;
 // `training` also materialises the up-sampled maps the backward pass reads
-// and keeps the skip concatenations interleaved.  `lean` (inference only)
-// computes the output conv in dec1b's epilogue and does not store dec1b.
-// With a frame `fv` (lean, in unused) the first layer reads its input from
-// the frame's accumulation and the last writes the frame's denoised and
-// display pixels (fallback threshold tau) instead of n->out.
-dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training, bool lean = false,
+// and keeps the skip concatenations interleaved.  With a frame `fv`
+// (inference; in unused) the first layer reads its input from the frame's
+// accumulation, and the last computes the output conv in its epilogue and
+// writes the frame's denoised and display pixels (fallback threshold tau)
+// instead of storing dec1b and n->out.
+dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool training,
                    const dfb::FrameView* fv = nullptr, float tau = 0.f) {
+  const bool lean = fv && !training;
   const Shape s1{s0.n, s0.h / 2, s0.w / 2}, s2{s0.n, s0.h / 4, s0.w / 4};
   hipStream_t st = n->stream;
   const float* W = n->w;
@@ -167,14 +168,11 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
   using dfb::unet::conv3x3_fwd;
   const Map pool1 = mp(n->pool1, 32, 0, 32), pool2 = mp(n->pool2, 64, 0, 64);
   const CatLayout c = cat_layout(n, s0, !training);
-  if (lean && !training && fv) {
+  if (lean) {
     NHIP(n, dfb::unet::conv3x3_in_frame(fv->glue, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
-  } else if (lean && !training) {  // the first layer reads the f32 input itself
-    NHIP(n, dfb::unet::conv3x3_in_fwd(nullptr, in, 6, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
   } else {
     NHIP(n, dfb::unet::pack_input(in, 6, n->xin, s0, st));
-    const Map xin = mp(n->xin, 8, 0, 8);
-    NHIP(n, dfb::unet::conv3x3_in_fwd(&xin, nullptr, 0, n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
+    NHIP(n, dfb::unet::conv3x3_in_fwd(mp(n->xin, 8, 0, 8), n->wf[ENC1A], B(ENC1A), mp(n->e1a, 32, 0, 32), s0, st));
   }
   NHIP(n, conv3x3_fwd(mp(n->e1a, 32, 0, 32), n->wf[ENC1B], B(ENC1B), c.enc1b, s0, st, false, &pool1));
   NHIP(n, conv3x3_fwd(pool1, n->wf[ENC2A], B(ENC2A), mp(n->e2a, 64, 0, 64), s1, st));
@@ -194,20 +192,17 @@ dfb_status forward(dfb_denoiser_ctx* n, const float* in, const Shape& s0, bool t
     NHIP(n, conv3x3_fwd(mp(n->cat1, 64, 0, 64), n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st));
   else
     NHIP(n, conv3x3_fwd(c.up1, n->wf[DEC1A], B(DEC1A), mp(n->d1a, 32, 0, 32), s0, st, false, nullptr, &c.enc1b));
-  if (lean && !training && fv) {
+  if (lean) {
     NHIP(n, dfb::unet::conv3x3_out_frame(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), W + n->off_ow, W + n->off_ob,
                                          fv->glue, tau, fv->denoised, fv->final_out, fv->display_mode, fv->inv_gamma,
                                          s0, st));
-  } else if (lean && !training) {
-    NHIP(n, dfb::unet::conv3x3_out_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), W + n->off_ow, W + n->off_ob,
-                                       in, 6, n->out, s0, st));
   } else {
     NHIP(n, conv3x3_fwd(mp(n->d1a, 32, 0, 32), n->wf[DEC1B], B(DEC1B), mp(n->d1b, 32, 0, 32), s0, st));
     NHIP(n, dfb::unet::out_conv_fwd(mp(n->d1b, 32, 0, 32), W + n->off_ow, W + n->off_ob, in, 6, n->out, s0, st));
   }
   n->last = s0;
   n->planar = !training;
-  n->lean = lean && !training;
+  n->lean = lean;
   return DFB_OK;
 }
 
@@ -474,7 +469,7 @@ dfb_status dfb_denoise(dfb_handle h, dfb_denoiser n, float var_threshold) {
     NHIP(n, hipStreamWaitEvent(n->stream, e, 0));
     NHIP(n, hipEventDestroy(e));
   }
-  if ((s = forward(n, nullptr, Shape{1, H, W}, false, true, &fv, var_threshold)) != DFB_OK) return s;
+  if ((s = forward(n, nullptr, Shape{1, H, W}, false, &fv, var_threshold)) != DFB_OK) return s;
   if (n->stream != fv.stream) {
     hipEvent_t e;
     NHIP(n, hipEventCreateWithFlags(&e, hipEventDisableTiming));
