@@ -201,9 +201,16 @@ __device__ __forceinline__ uint4 buf_load16(__amdgpu_buffer_rsrc_t r, int byte_o
   const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
   return uint4{v[0], v[1], v[2], v[3]};
 }
+// Cache policy of a store: kNT marks it non-temporal (streamed past the
+// caches).  The first layer and the 32 -> 64 and 64 -> 128 layers store
+// their activations that way (2048^2: enc1a 64 -> 55, dec1a 184 -> 176,
+// dec2a 170 -> 165 us); the 32 -> 32 layers were slower with it (enc1b 125
+// -> 130, dec1b 105 -> 113 us) and the others unchanged.
+constexpr int kNT = 2;
+template <int POLICY = 0>
 __device__ __forceinline__ void buf_store16(__amdgpu_buffer_rsrc_t r, int byte_off, uint4 v) {
   const u32x4 w = {v.x, v.y, v.z, v.w};
-  __builtin_amdgcn_raw_buffer_store_b128(w, r, byte_off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b128(w, r, byte_off, 0, POLICY);
 }
 __device__ __forceinline__ void buf_store8(__amdgpu_buffer_rsrc_t r, int byte_off, uint32_t lo, uint32_t hi) {
   const u32x2 v = {lo, hi};
@@ -245,6 +252,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
            Shape s) {
   using C = ConvCfg<BN, TH, CP / kKC, UP>;
   constexpr bool POOL = EPI == kEpiPool, OUT = EPI == kEpiFrame;
+  constexpr int STORE_POLICY = (BN == 32 && CP == 64) || (BN == 64 && CP == 128) ? kNT : 0;
   static_assert(!OUT || BN == 32, "the output conv takes 32 channels, one pixel per thread");
   constexpr int NT = C::NT;  // threads (CS waves per two tile rows)
   constexpr int NCH = CP / kKC, MB = 2, NB = BN / 32 / C::CS;  // tile rows and 32-channel blocks per wave
@@ -445,7 +453,7 @@ conv_fwd_k(Map x, Map x2, const uint16_t* __restrict__ w, const float* __restric
         const int ok = !dummy & (out_full | ((oy0 + row < s.h) & (ox0 + col < s.w)));
         const uint4 v = dummy ? uint4{0u, 0u, 0u, 0u} : *reinterpret_cast<const uint4*>(stg + (lrow * kTW + col) * LDO + c * 8);
         // (distinct out-of-range offsets: identical ones would let the compiler drop all but the last)
-        buf_store16(yb, ok ? ((row * s.w + col) * y.ld + c * 8) * 2 : kOOB + (pass * NOUT + k) * 16, v);
+        buf_store16<STORE_POLICY>(yb, ok ? ((row * s.w + col) * y.ld + c * 8) * 2 : kOOB + (pass * NOUT + k) * 16, v);
       }
 #pragma unroll
       for (int k = 0; k < NPOOL; ++k) {
@@ -710,7 +718,8 @@ __global__ void __launch_bounds__(256) conv_in_k(Map x, FrameGlue fg,
   for (int k = 0; k < 4; ++k) {
     const int e = tid + 256 * k, px = e / 4, c = e % 4, row = px / kTW, col = px % kTW;
     const int ok = (oy0 + row < s.h) & (ox0 + col < s.w);
-    buf_store16(yb, ok ? ((row * s.w + col) * y.ld + c * 8) * 2 : kOOB, *reinterpret_cast<const uint4*>(stg + px * LDO + c * 8));
+    buf_store16<kNT>(yb, ok ? ((row * s.w + col) * y.ld + c * 8) * 2 : kOOB,
+                     *reinterpret_cast<const uint4*>(stg + px * LDO + c * 8));
   }
 }
 
