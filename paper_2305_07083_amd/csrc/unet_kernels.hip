@@ -67,14 +67,16 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 }
 
 // ------------------------------------------------------------- forward
-// Persistent implicit-GEMM conv3x3 forward.  Workgroup b computes the
-// TH x 32-pixel output tiles b, b + gridDim.x, ... for all BN output
-// channels; a tile is CP/32 steps, one per 32-input-channel slice.  A step
-// stages the slice's (TH+2) x 34 input halo (zero outside the image; read
-// through the nearest-neighbour up-sampling when UP) and the slice's weights
-// of all nine taps in LDS, then runs the nine taps' MFMAs with no barrier
-// between them.  The next step's halo and weights are loaded into registers
-// while this step's MFMAs run, so a workgroup hides its own load latency.
+// Persistent implicit-GEMM conv3x3 forward.  A workgroup computes a
+// contiguous range of the TH x 32-pixel output tiles (each XCD one band of
+// them) for all BN output channels; a tile is CP/32 steps, one per
+// 32-input-channel slice.  A step stages the slice's input halo ((TH+2) x 34
+// pixels, zero outside the image; with UP the (TH/2+2) x 18 source pixels the
+// up-sampled halo reads) and, unless all slices' weights stay resident, the
+// slice's weights of all nine taps in LDS, then runs the nine taps' MFMAs
+// with no barrier between them.  The next step's halo and weights are loaded
+// into registers while this step's MFMAs run, so a workgroup hides its own
+// load latency.
 //
 // The MFMA is v_mfma_f32_32x32x16_bf16 (measured on the device: about 2.0
 // PFLOP/s, against about 1.15 for v_mfma_f32_16x16x32_bf16 with the same
@@ -85,8 +87,10 @@ __device__ __forceinline__ long long shifted(const Pix& q, int dr, int dc, const
 // owns two tile rows and BN / CS output channels (CS = 2 for 128 channels,
 // else 1), so a taller tile spreads a staged weight slice over more waves at
 // the same registers per wave.  The accumulators start from the bias;
-// the epilogue (ReLU, v_cvt_pk_bf16_f32, optionally the 2x2 average pool)
-// goes through a staging tile in LDS so that the stores are coalesced.
+// the epilogue (ReLU, v_cvt_pk_bf16_f32, optionally the 2x2 average pool, or
+// instead of the stores the network's output conv written into a
+// compositor frame) goes through a staging tile in LDS so that the stores
+// are coalesced.
 //
 // LDS rows hold 32 bf16 channels (4 16-byte chunks).  gfx950 serves a
 // ds_read_b128 16 lanes per cycle (per half-wave, the lanes whose bits 2-4
